@@ -1,0 +1,98 @@
+/*
+ * mhd_oracle.h -- interface of the CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, serial, FP64 C implementation
+ * of the ideal-MHD finite-volume update that the GPU library is checked
+ * against.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * The scheme is the main cycle of arXiv 2606.12753 §2.2.3: per-direction
+ * reconstruction of primitive variables, a Riemann solve at every interface,
+ * a flux-conservative update, constrained transport for the magnetic field and
+ * Runge-Kutta time stepping (here the two-stage SSP form).  The component
+ * algorithms are the published ones named in mhd_oracle.c.
+ *
+ * Array layout at this interface (the "boundary layout"): C order [z][y][x],
+ * x fastest.  Cell arrays hold nz*ny*nx doubles.  Face arrays hold both
+ * bounding faces of every cell: Bx nz*ny*(nx+1), By nz*(ny+1)*nx,
+ * Bz (nz+1)*ny*nx.  On periodic axes the last face must equal the first.
+ */
+#ifndef MHD_ORACLE_H
+#define MHD_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_BC_PERIODIC 0
+#define ORC_BC_OUTFLOW 1
+
+typedef struct orc_box orc_box;
+
+/* n[3] cells per axis (n==1: inactive axis), lo/hi domain corners, bc[3] per
+ * axis (both sides alike), gamma, CFL number, pressure floor.  NULL on bad
+ * arguments or out of memory. */
+orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
+                     const int bc[3], double gamma, double cfl, double pfloor);
+void orc_box_free(orc_box *b);
+
+/* Copies the state in/out (boundary layout).  set returns 0, or -1 when a
+ * periodic axis has last face != first face. */
+int orc_set_state(orc_box *b, const double *const cons[5],
+                  const double *const bface[3], double t);
+void orc_get_state(const orc_box *b, double *const cons[5],
+                   double *const bface[3], double *t);
+
+/* Advances nsteps full SSP-RK2 steps with the CFL time step of each step's
+ * starting state (clamped to t_stop - t when t_stop > 0). */
+void orc_step(orc_box *b, int nsteps, double t_stop);
+/* One step with a caller-given dt (used for sampled parity on sub-boxes). */
+void orc_step_fixed_dt(orc_box *b, double dt);
+/* CFL time step of the current state (no t_stop clamp). */
+double orc_dt(orc_box *b);
+/* Stage operator L(U,B) of the current state: cell residual R[5] (cell
+ * layout) and face rates rB[3] (boundary face layout). */
+void orc_rhs(orc_box *b, double *const R[5], double *const rB[3]);
+/* counters[0] = pressure-floor hits, [1] = HLL fallbacks, [2] = bad cells
+ * (rho <= 0 or non-finite), accumulated since creation / last set_state. */
+void orc_counters(const orc_box *b, long long counters[3]);
+/* max over cells of |div B| (face differences / dx). */
+double orc_divb_max(const orc_box *b);
+
+/* ---- point functions (for the pins) ---- */
+/* cons (rho, mx, my, mz, E) + cell-centred B -> prims (rho, vx, vy, vz, p,
+ * bx, by, bz); returns bit0 = floor hit, bit1 = bad. */
+int orc_cons_to_prim(const double u[5], const double bc[3], double gamma,
+                     double pfloor, double w[8]);
+double orc_fast_speed(double rho, double p, double bn, double bt1, double bt2,
+                      double gamma);
+double orc_minmod(double a, double b);
+/* PLM interface values between cells c-1 and c from q(c-2..c+1) */
+void orc_plm_face(double qm2, double qm1, double q0, double qp1, double *ql,
+                  double *qr);
+/* states in the face frame: (rho, vn, vt1, vt2, p, bt1, bt2), normal field bn.
+ * flux out: (mass, mom n, mom t1, mom t2, energy, B t1, B t2). */
+void orc_phys_flux(const double w[7], double bn, double gamma, double f[7],
+                   double u[7]);
+int orc_hlld(const double wl[7], const double wr[7], double bn, double gamma,
+             double f[7]);
+void orc_hll(const double wl[7], const double wr[7], double bn, double gamma,
+             double f[7]);
+/* mass flux of the face as handed to the CT upwinding (zero when it is zero
+ * up to rounding, see mhd_oracle.c) */
+double orc_ct_mass_flux(const double wl[7], const double wr[7], double bn,
+                        double gamma);
+/* Corner EMF of the contact-upwinded constrained-transport average.
+ * fa1/fa0: edge-component EMF on the two a-faces (b index ib, ib-1);
+ * fb1/fb0: on the two b-faces (a index ia, ia-1); ec[2][2] cell values
+ * indexed [b offset][a offset] with offset 0 = lower cell; ma1/ma0 mass flux
+ * on the a-faces (ib, ib-1), mb1/mb0 on the b-faces (ia, ia-1). */
+double orc_ct_corner(double fa1, double fa0, double fb1, double fb0,
+                     const double ec[4], double ma1, double ma0, double mb1,
+                     double mb0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

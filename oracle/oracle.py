@@ -1,0 +1,224 @@
+"""ctypes wrapper of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+The oracle itself is ``mhd_oracle.c``: a plain serial FP64 implementation of
+the ideal-MHD finite-volume update of arXiv 2606.12753 §2.2.3 (reconstruct,
+Riemann solve, conservative update per direction; constrained transport;
+Runge-Kutta stepping).  This module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+_dp = C.POINTER(C.c_double)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.environ.get("MHD_ORACLE_LIB")
+        if not path:
+            path = os.path.join(_build.HERE, "liboracle.so")
+            if not os.path.exists(path) or (
+                os.path.getmtime(path) < os.path.getmtime(_build.SRC)
+            ):
+                _build.build()
+        lib = C.CDLL(path)
+        lib.orc_box_new.restype = C.c_void_p
+        lib.orc_box_new.argtypes = [C.POINTER(C.c_int), _dp, _dp, C.POINTER(C.c_int),
+                                    C.c_double, C.c_double, C.c_double]
+        lib.orc_box_free.argtypes = [C.c_void_p]
+        lib.orc_set_state.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp), C.c_double]
+        lib.orc_set_state.restype = C.c_int
+        lib.orc_get_state.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp), _dp]
+        lib.orc_step.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        lib.orc_step_fixed_dt.argtypes = [C.c_void_p, C.c_double]
+        lib.orc_dt.argtypes = [C.c_void_p]
+        lib.orc_dt.restype = C.c_double
+        lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
+        lib.orc_counters.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
+        lib.orc_divb_max.argtypes = [C.c_void_p]
+        lib.orc_divb_max.restype = C.c_double
+        lib.orc_cons_to_prim.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp]
+        lib.orc_cons_to_prim.restype = C.c_int
+        lib.orc_fast_speed.argtypes = [C.c_double] * 6
+        lib.orc_fast_speed.restype = C.c_double
+        lib.orc_minmod.argtypes = [C.c_double, C.c_double]
+        lib.orc_minmod.restype = C.c_double
+        lib.orc_plm_face.argtypes = [C.c_double] * 4 + [_dp, _dp]
+        lib.orc_phys_flux.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp]
+        lib.orc_hlld.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp]
+        lib.orc_hlld.restype = C.c_int
+        lib.orc_hll.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp]
+        lib.orc_ct_mass_flux.argtypes = [_dp, _dp, C.c_double, C.c_double]
+        lib.orc_ct_mass_flux.restype = C.c_double
+        lib.orc_ct_corner.argtypes = [C.c_double] * 4 + [_dp] + [C.c_double] * 4
+        lib.orc_ct_corner.restype = C.c_double
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _vec(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    assert a.shape == (n,)
+    return a
+
+
+class OracleBox:
+    """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
+
+    def __init__(self, spec, pfloor: float = 1e-10):
+        lib = _lib()
+        self.spec = spec
+        self.n = tuple(int(v) for v in spec.n)
+        n = (C.c_int * 3)(*self.n)
+        lo = (C.c_double * 3)(*spec.lo)
+        hi = (C.c_double * 3)(*spec.hi)
+        bc = (C.c_int * 3)(*spec.bc)
+        self._h = lib.orc_box_new(n, lo, hi, bc, spec.gamma, spec.cfl, pfloor)
+        if not self._h:
+            raise ValueError("oracle: bad box description or out of memory")
+
+    def close(self):
+        if self._h:
+            _lib().orc_box_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shapes(self):
+        nx, ny, nz = self.n
+        cell = (nz, ny, nx)
+        faces = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+        return cell, faces
+
+    def set_state(self, cons, bface, t=0.0):
+        cell, faces = self.shapes()
+        cons = [np.ascontiguousarray(c, dtype=np.float64) for c in cons]
+        bface = [np.ascontiguousarray(b, dtype=np.float64) for b in bface]
+        for c in cons:
+            assert c.shape == cell
+        for b, s in zip(bface, faces):
+            assert b.shape == s
+        cp = (_dp * 5)(*[_ptr(c) for c in cons])
+        bp = (_dp * 3)(*[_ptr(b) for b in bface])
+        rc = _lib().orc_set_state(self._h, cp, bp, float(t))
+        if rc != 0:
+            raise ValueError("oracle: periodic face mismatch")
+
+    def get_state(self):
+        cell, faces = self.shapes()
+        cons = [np.empty(cell) for _ in range(5)]
+        bface = [np.empty(s) for s in faces]
+        t = C.c_double(0.0)
+        cp = (_dp * 5)(*[_ptr(c) for c in cons])
+        bp = (_dp * 3)(*[_ptr(b) for b in bface])
+        _lib().orc_get_state(self._h, cp, bp, C.byref(t))
+        return cons, bface, t.value
+
+    def step(self, nsteps: int, t_stop: float = 0.0):
+        _lib().orc_step(self._h, int(nsteps), float(t_stop))
+
+    def step_fixed_dt(self, dt: float):
+        _lib().orc_step_fixed_dt(self._h, float(dt))
+
+    def dt(self) -> float:
+        return _lib().orc_dt(self._h)
+
+    def rhs(self):
+        cell, faces = self.shapes()
+        R = [np.empty(cell) for _ in range(5)]
+        rB = [np.empty(s) for s in faces]
+        rp = (_dp * 5)(*[_ptr(c) for c in R])
+        bp = (_dp * 3)(*[_ptr(b) for b in rB])
+        _lib().orc_rhs(self._h, rp, bp)
+        return R, rB
+
+    def counters(self):
+        c = (C.c_longlong * 3)()
+        _lib().orc_counters(self._h, c)
+        return {"floor": c[0], "hll": c[1], "bad": c[2]}
+
+    def divb_max(self) -> float:
+        return _lib().orc_divb_max(self._h)
+
+
+# ---- point functions ------------------------------------------------------
+
+def cons_to_prim(u, bc, gamma, pfloor=1e-10):
+    u = _vec(u, 5)
+    bc = _vec(bc, 3)
+    w = np.empty(8)
+    fl = _lib().orc_cons_to_prim(_ptr(u), _ptr(bc), gamma, pfloor, _ptr(w))
+    return w, fl
+
+
+def fast_speed(rho, p, bn, bt1, bt2, gamma):
+    return _lib().orc_fast_speed(rho, p, bn, bt1, bt2, gamma)
+
+
+def minmod(a, b):
+    return _lib().orc_minmod(a, b)
+
+
+def plm_face(qm2, qm1, q0, qp1):
+    ql = C.c_double()
+    qr = C.c_double()
+    _lib().orc_plm_face(qm2, qm1, q0, qp1, C.byref(ql), C.byref(qr))
+    return ql.value, qr.value
+
+
+def phys_flux(w, bn, gamma):
+    w = _vec(w, 7)
+    f = np.empty(7)
+    u = np.empty(7)
+    _lib().orc_phys_flux(_ptr(w), bn, gamma, _ptr(f), _ptr(u))
+    return f, u
+
+
+def hlld(wl, wr, bn, gamma):
+    wl = _vec(wl, 7)
+    wr = _vec(wr, 7)
+    f = np.empty(7)
+    used_hll = _lib().orc_hlld(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
+    return f, bool(used_hll)
+
+
+def hll(wl, wr, bn, gamma):
+    wl = _vec(wl, 7)
+    wr = _vec(wr, 7)
+    f = np.empty(7)
+    _lib().orc_hll(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
+    return f
+
+
+def ct_mass_flux(wl, wr, bn, gamma):
+    wl = _vec(wl, 7)
+    wr = _vec(wr, 7)
+    return _lib().orc_ct_mass_flux(_ptr(wl), _ptr(wr), bn, gamma)
+
+
+def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0):
+    ec = _vec(ec, 4)
+    return _lib().orc_ct_corner(fa1, fa0, fb1, fb0, _ptr(ec), ma1, ma0, mb1, mb0)
+
+
+__all__ = [
+    "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
+    "hll", "ct_mass_flux", "ct_corner",
+]

@@ -1,0 +1,66 @@
+"""The pins must catch plausible mistakes in the oracle.  Each case plants one
+mistake in a copy of the oracle source (a flipped sign, a dropped term, a
+swapped operand), builds it on the CPU and checks that the named pins fail
+against it.  The real oracle is never modified."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, original text, mutated text, pins expected to fail)
+MUTATIONS = [
+    ("ct_corner_sign", "0.25 * (dbm - dbp)", "0.25 * (dbp - dbm)",
+     "test_oracle_point.py::test_ct_plane_parallel_reduction"),
+    ("ct_upwind_swapped", "if (mflux > 0.0) return lower;", "if (mflux > 0.0) return upper;",
+     "test_oracle_point.py::test_ct_upwind_selection"),
+    ("minmod_max", "return a < b ? a : b;", "return a < b ? b : a;",
+     "test_oracle_point.py::test_plm_brute_force_tiny"),
+    ("fast_speed_sign", "s * s - 4.0 * a2 * bn2", "s * s + 4.0 * a2 * bn2",
+     "test_oracle_point.py::test_fast_speed_special_cases"),
+    ("flux_drops_bn2", "f[1] = rho * vn * vn + pt - bn * bn;", "f[1] = rho * vn * vn + pt;",
+     "test_oracle_point.py::test_static_flux test_oracle_point.py::test_hlld_isolated_stationary_contact"),
+    ("flux_energy_term", "f[4] = (en + pt) * vn - bn * vb;", "f[4] = (en + pt) * vn;",
+     "test_oracle_point.py::test_flux_jacobian_eigenvalues"),
+    ("hlld_star_energy_term", "+ pts * sm + bn * (vb - vbs)) / sms;", "+ bn * (vb - vbs)) / sms;",
+     "test_oracle_point.py::test_hlld_isolated_stationary_contact "
+     "test_oracle_point.py::test_hlld_isolated_rotational_discontinuity"),
+    ("hlld_double_star_sign", "(str.bt1 - stl.bt1) * sgn) / ssum;", "(stl.bt1 - str.bt1) * sgn) / ssum;",
+     "test_oracle_point.py::test_hlld_isolated_rotational_discontinuity"),
+    ("face_rate_sign", "b->RB[d][c0] = -(t1 - t2);", "b->RB[d][c0] = (t1 - t2);",
+     "test_oracle_scheme.py::test_cp_alfven_linear_amplitude"),
+    ("bc_wrong_index", "b->Bc[1][c] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i, j + 1, k)]);",
+     "b->Bc[1][c] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i + 1, j, k)]);",
+     "test_oracle_scheme.py::test_cp_alfven_axes_equivalent"),
+    ("rk2_combine", "0.5 * (b->U0[q][c] + (b->U[q][c] + dt * b->R[q][c]))",
+     "0.5 * (b->U0[q][c] + b->U[q][c]) + dt * b->R[q][c]",
+     "test_oracle_scheme.py::test_sod_shock_tube_against_exact"),
+    ("divergence_sign", "r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) / b->dx[d];",
+     "r = r + (b->FH[d][q][up[d]] - b->FH[d][q][c]) / b->dx[d];",
+     "test_oracle_scheme.py::test_sod_shock_tube_against_exact"),
+    ("dt_ignores_velocity", "double l = (fabs(w[1 + d]) + cf) / b->dx[d];",
+     "double l = cf / b->dx[d];",
+     "test_oracle_scheme.py::test_uniform_dt_closed_form"),
+    ("periodic_ghost_off_by_one", "while (i < 0) i += n;", "while (i < 0) i += n - 1;",
+     "test_oracle_scheme.py::test_conservation_divb_mean_field"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,mut,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, orig, mut, pins):
+    src = open(B.SRC).read()
+    assert src.count(orig) >= 1, f"mutation anchor for {name} not found"
+    mutated = src.replace(orig, mut, 1)
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(mutated)
+    lib = B.compile_to(str(msrc), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, MHD_ORACLE_LIB=lib)
+    args = [sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"]
+    args += [os.path.join(ROOT, "tests", p) for p in pins.split()]
+    r = subprocess.run(args, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins {pins} did not catch mutation {name}:\n{r.stdout[-2000:]}"

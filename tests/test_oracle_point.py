@@ -1,0 +1,338 @@
+"""Pins of the oracle's point functions against facts fixed independently of
+its own formulas: textbook special cases, eigen-structure of the flux
+Jacobian, exactness properties of HLLD proven by Miyoshi & Kusano (2005),
+symmetries of the equations, and the plane-parallel reduction of the
+contact-upwinded CT average (Gardiner & Stone 2005)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_12753_amd import workloads as W
+
+G = 5.0 / 3.0
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b)))))
+
+
+def rand_state(rng, umag=1.0):
+    return np.array([
+        rng.uniform(0.2, 3.0),          # rho
+        rng.uniform(-umag, umag),       # vn
+        rng.uniform(-umag, umag),       # vt1
+        rng.uniform(-umag, umag),       # vt2
+        rng.uniform(0.05, 3.0),         # p
+        rng.uniform(-2, 2),             # bt1
+        rng.uniform(-2, 2),             # bt2
+    ])
+
+
+# ---------------------------------------------------------------- minmod/PLM
+
+def test_minmod_cases():
+    assert O.minmod(1.0, 2.0) == 1.0
+    assert O.minmod(2.0, 1.0) == 1.0
+    assert O.minmod(-1.0, -3.0) == -1.0
+    assert O.minmod(-3.0, -1.0) == -1.0
+    assert O.minmod(1.0, -1.0) == 0.0
+    assert O.minmod(0.0, 5.0) == 0.0
+    assert O.minmod(-2.0, 0.0) == 0.0
+
+
+def test_plm_exact_on_linear_data():
+    # a linear profile is reproduced exactly at the interface
+    for a, s in [(0.3, 0.7), (-1.25, 2.5), (4.0, -0.5)]:
+        q = [a + s * i for i in range(4)]          # cells c-2..c+1
+        ql, qr = O.plm_face(*q)
+        exact = a + s * 1.5                        # interface between c-1 and c
+        assert ql == pytest.approx(exact, rel=1e-15, abs=1e-15)
+        assert qr == pytest.approx(exact, rel=1e-15, abs=1e-15)
+
+
+def test_plm_flat_at_extrema_and_bounded():
+    # local maximum at c-1: its slope is zero, so q_L = q(c-1)
+    ql, qr = O.plm_face(0.0, 2.0, 1.0, 0.5)
+    assert ql == 2.0
+    # TVD: interface values stay within the neighbouring cell values
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        q = rng.normal(size=4)
+        ql, qr = O.plm_face(*q)
+        assert min(q[0], q[1], q[2]) - 1e-15 <= ql <= max(q[0], q[1], q[2]) + 1e-15
+        assert min(q[1], q[2], q[3]) - 1e-15 <= qr <= max(q[1], q[2], q[3]) + 1e-15
+
+
+def test_plm_brute_force_tiny():
+    # brute force over a small integer lattice against the limiter definition
+    # (the smaller-magnitude one-sided difference when both agree in sign)
+    vals = [-2.0, -1.0, 0.0, 1.0, 3.0]
+    for a in vals:
+        for b in vals:
+            for c in vals:
+                for d in vals:
+                    ql, qr = O.plm_face(a, b, c, d)
+                    s1 = [x for x in (b - a, c - b)]
+                    s2 = [x for x in (c - b, d - c)]
+                    def lim(u, v):
+                        if u * v <= 0:
+                            return 0.0
+                        return u if abs(u) < abs(v) else v
+                    assert ql == b + 0.5 * lim(*s1)
+                    assert qr == c - 0.5 * lim(*s2)
+
+
+# ---------------------------------------------------------------- cons/prim
+
+def test_cons_prim_roundtrip():
+    rng = np.random.default_rng(5)
+    spec = W.BoxSpec((4, 3, 2))
+    for _ in range(200):
+        rho, p = rng.uniform(0.1, 5), rng.uniform(0.01, 5)
+        v = rng.uniform(-3, 3, size=3)
+        b = rng.uniform(-2, 2, size=3)
+        bface = [np.full(s, b[d]) for d, s in enumerate(W.face_shapes(spec))]
+        st = W.conserved(spec, rho, v[0], v[1], v[2], p, bface)
+        u = [c[0, 0, 0] for c in st.cons]
+        w, fl = O.cons_to_prim(u, b, G)
+        assert fl == 0
+        assert rel(w, [rho, *v, p, *b]) < 1e-12
+
+
+def test_pressure_floor_and_bad_flags():
+    w, fl = O.cons_to_prim([1.0, 0.0, 0.0, 0.0, 0.1], [1.0, 0.0, 0.0], G, 1e-10)
+    assert fl & 1 and w[4] == 1e-10            # E below magnetic energy: floored
+    w, fl = O.cons_to_prim([-1.0, 0.0, 0.0, 0.0, 1.0], [0.0, 0.0, 0.0], G)
+    assert fl & 2                               # negative density flagged
+    w, fl = O.cons_to_prim([np.nan, 0.0, 0.0, 0.0, 1.0], [0.0, 0.0, 0.0], G)
+    assert fl & 2
+
+
+# ---------------------------------------------------------------- wave speeds
+
+def test_fast_speed_special_cases():
+    rho, p = 1.7, 0.9
+    a = math.sqrt(G * p / rho)
+    # no field: sound speed
+    assert O.fast_speed(rho, p, 0.0, 0.0, 0.0, G) == pytest.approx(a, rel=1e-15)
+    # field along the normal: max(sound, Alfven)
+    for bn in (0.3, 2.5):
+        ca = abs(bn) / math.sqrt(rho)
+        assert O.fast_speed(rho, p, bn, 0.0, 0.0, G) == pytest.approx(max(a, ca), rel=1e-14)
+    # field perpendicular: sqrt(a^2 + b^2/rho)
+    b1, b2 = 0.8, -0.6
+    assert O.fast_speed(rho, p, 0.0, b1, b2, G) == pytest.approx(
+        math.sqrt(a * a + (b1 * b1 + b2 * b2) / rho), rel=1e-14)
+
+
+def test_flux_jacobian_eigenvalues():
+    """The eigenvalues of dF/dU (7-wave system, face frame) are u, u +- c_a,
+    u +- c_s, u +- c_f: pins the physical flux and the fast speed at once."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        w = rand_state(rng)
+        bn = rng.uniform(-1.5, 1.5)
+        h = 1e-6
+        # U(w) and F(w); J = dF/dw (dU/dw)^-1 by central differences
+        dF = np.zeros((7, 7))
+        dU = np.zeros((7, 7))
+        for k in range(7):
+            e = np.zeros(7)
+            e[k] = h * max(1.0, abs(w[k]))
+            fp, up = O.phys_flux(w + e, bn, G)
+            fm, um = O.phys_flux(w - e, bn, G)
+            dF[:, k] = (fp - fm) / (2 * e[k])
+            dU[:, k] = (up - um) / (2 * e[k])
+        J = dF @ np.linalg.inv(dU)
+        ev = np.sort(np.linalg.eigvals(J).real)
+        rho, u, p = w[0], w[1], w[4]
+        bt2 = w[5] ** 2 + w[6] ** 2
+        a2 = G * p / rho
+        ca = abs(bn) / math.sqrt(rho)
+        b2 = (bn * bn + bt2) / rho
+        cf = O.fast_speed(rho, p, bn, w[5], w[6], G)
+        cs2 = 0.5 * (a2 + b2 - math.sqrt(max(0.0, (a2 + b2) ** 2 - 4 * a2 * bn * bn / rho)))
+        cs = math.sqrt(max(cs2, 0.0))
+        exact = np.sort([u - cf, u - ca, u - cs, u, u + cs, u + ca, u + cf])
+        assert np.allclose(ev, exact, atol=1e-5 * (abs(u) + cf)), (ev, exact)
+
+
+def test_static_flux():
+    w = np.array([1.3, 0.0, 0.0, 0.0, 0.7, 0.4, -0.9])
+    bn = 0.6
+    f, _ = O.phys_flux(w, bn, G)
+    pt = 0.7 + 0.5 * (0.36 + 0.16 + 0.81)
+    assert rel(f, [0.0, pt - 0.36, -0.6 * 0.4, -0.6 * -0.9, 0.0, 0.0, 0.0]) < 1e-15
+
+
+# ---------------------------------------------------------------- HLLD
+
+def test_hlld_consistency_random():
+    rng = np.random.default_rng(21)
+    for _ in range(500):
+        w = rand_state(rng, umag=3.0)
+        bn = rng.uniform(-2, 2)
+        f, used = O.hlld(w, w, bn, G)
+        fe, _ = O.phys_flux(w, bn, G)
+        assert not used
+        scale = np.max(np.abs(fe)) + 1.0
+        assert np.max(np.abs(f - fe)) <= 5e-15 * scale * 10
+
+
+def test_hlld_supersonic_upwind():
+    rng = np.random.default_rng(22)
+    for _ in range(50):
+        wl = rand_state(rng)
+        wr = rand_state(rng)
+        wl[1] += 20.0
+        wr[1] += 20.0
+        f, _ = O.hlld(wl, wr, 0.3, G)
+        fl, _ = O.phys_flux(wl, 0.3, G)
+        assert np.array_equal(f, fl)
+        wl[1] -= 40.0
+        wr[1] -= 40.0
+        f, _ = O.hlld(wl, wr, 0.3, G)
+        fr, _ = O.phys_flux(wr, 0.3, G)
+        assert np.array_equal(f, fr)
+
+
+def test_hlld_isolated_stationary_contact():
+    """A contact (density jump only, at rest) is resolved exactly: zero mass
+    and energy flux, the momentum flux is the total pressure minus Bn^2."""
+    for bn in (0.0, 0.75, -1.2):
+        for bt in ((0.0, 0.0), (0.5, -0.3)):
+            wl = np.array([1.0, 0.0, 0.0, 0.0, 0.8, bt[0], bt[1]])
+            wr = np.array([0.125, 0.0, 0.0, 0.0, 0.8, bt[0], bt[1]])
+            f, used = O.hlld(wl, wr, bn, G)
+            assert not used
+            pt = 0.8 + 0.5 * (bn * bn + bt[0] ** 2 + bt[1] ** 2)
+            exact = [0.0, pt - bn * bn, -bn * bt[0], -bn * bt[1], 0.0, 0.0, 0.0]
+            assert np.max(np.abs(f - exact)) < 1e-14
+
+
+@pytest.mark.parametrize("family", [-1, +1])
+@pytest.mark.parametrize("frame", [0.0, 0.37, -0.8])
+def test_hlld_isolated_rotational_discontinuity(family, frame):
+    """Two states joined by a rotational (Alfven) discontinuity alone: the
+    HLLD flux equals the exact Godunov flux (Miyoshi & Kusano 2005)."""
+    rho, p, bn = 1.4, 0.6, 0.9
+    ca = bn / math.sqrt(rho)
+    th = 1.1
+    btl = np.array([0.7, -0.2])
+    btr = np.array([math.cos(th) * btl[0] - math.sin(th) * btl[1],
+                    math.sin(th) * btl[0] + math.cos(th) * btl[1]])
+    # discontinuity speed relative to the fluid: family*ca; lab speed S
+    # jump condition: [v_t] = -family * [B_t] / sqrt(rho) * sign(bn)
+    vtl = np.array([0.1, 0.25])
+    vtr = vtl - family * (btr - btl) / math.sqrt(rho)
+    u = -family * ca + frame   # S = u + family*ca = frame
+    wl = np.array([rho, u, vtl[0], vtl[1], p, btl[0], btl[1]])
+    wr = np.array([rho, u, vtr[0], vtr[1], p, btr[0], btr[1]])
+    f, used = O.hlld(wl, wr, bn, G)
+    assert not used
+    S = frame
+    fl, ul = O.phys_flux(wl, bn, G)
+    fr, ur = O.phys_flux(wr, bn, G)
+    # Rankine-Hugoniot across the discontinuity holds for the constructed states
+    assert np.max(np.abs((fr - fl) - S * (ur - ul))) < 1e-13
+    exact = fl if S > 0 else (fr if S < 0 else fl)
+    assert np.max(np.abs(f - exact)) < 1e-13, (f, exact)
+
+
+def test_hlld_mirror_symmetry():
+    rng = np.random.default_rng(31)
+    sgn = np.array([-1, 1, -1, -1, -1, -1, -1], dtype=float)
+    m = np.array([1, -1, 1, 1, 1, 1, 1], dtype=float)
+    for _ in range(300):
+        wl, wr = rand_state(rng, 2.0), rand_state(rng, 2.0)
+        bn = rng.uniform(-2, 2)
+        f, _ = O.hlld(wl, wr, bn, G)
+        g, _ = O.hlld(wr * m, wl * m, -bn, G)
+        assert np.max(np.abs(g - sgn * f)) <= 1e-13 * (1 + np.max(np.abs(f)))
+
+
+def test_hlld_transverse_rotation():
+    """Rotating the transverse plane by 90 degrees rotates the flux."""
+    rng = np.random.default_rng(32)
+    for _ in range(200):
+        wl, wr = rand_state(rng, 2.0), rand_state(rng, 2.0)
+        bn = rng.uniform(-2, 2)
+
+        def rot(w):
+            return np.array([w[0], w[1], -w[3], w[2], w[4], -w[6], w[5]])
+
+        f, _ = O.hlld(wl, wr, bn, G)
+        g, _ = O.hlld(rot(wl), rot(wr), bn, G)
+        assert np.max(np.abs(g - rot(f))) <= 1e-13 * (1 + np.max(np.abs(f)))
+
+
+def test_hlld_bn_to_zero_continuity():
+    rng = np.random.default_rng(33)
+    for _ in range(100):
+        wl, wr = rand_state(rng), rand_state(rng)
+        f0, _ = O.hlld(wl, wr, 0.0, G)
+        f1, _ = O.hlld(wl, wr, 1e-7, G)
+        assert np.max(np.abs(f1 - f0)) < 1e-5 * (1 + np.max(np.abs(f0)))
+
+
+def test_hll_fallback_on_strong_rarefaction():
+    # two streams flying apart: the HLLD star pressure is not positive
+    wl = np.array([1.0, -30.0, 0.0, 0.0, 1e-4, 0.1, 0.0])
+    wr = np.array([1.0, 30.0, 0.0, 0.0, 1e-4, 0.1, 0.0])
+    f, used = O.hlld(wl, wr, 0.05, G)
+    assert used
+    assert np.all(np.isfinite(f))
+    g = O.hll(wl, wr, 0.05, G)
+    assert np.array_equal(f, g)
+    # symmetric: zero mass flux through the centre
+    assert abs(f[0]) < 1e-12
+
+
+def test_hll_consistency():
+    rng = np.random.default_rng(34)
+    for _ in range(100):
+        w = rand_state(rng)
+        bn = rng.uniform(-2, 2)
+        f = O.hll(w, w, bn, G)
+        fe, _ = O.phys_flux(w, bn, G)
+        assert np.max(np.abs(f - fe)) <= 1e-13 * (1 + np.max(np.abs(fe)))
+
+
+# ---------------------------------------------------------------- CT corner
+
+def test_ct_plane_parallel_reduction():
+    """Grid-aligned plane-parallel flow: the corner EMF equals the face EMF
+    of the direction of variation, whatever the transverse mass flux."""
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        F = rng.normal()
+        ec_lo, ec_hi = rng.normal(size=2)       # cells ia-1, ia
+        m = rng.normal(size=2)
+        mt = rng.choice([-1.0, 0.0, 1.0])
+        # variation along a: a-faces carry F, b-faces carry the cell values
+        ec = np.array([ec_lo, ec_hi, ec_lo, ec_hi])
+        e = O.ct_corner(F, F, ec_hi, ec_lo, ec, m[0], m[0], mt, mt)
+        assert e == pytest.approx(F, abs=1e-14 * (1 + abs(F) + abs(ec_lo) + abs(ec_hi)))
+        # variation along b: b-faces carry G, a-faces the cell values (ib, ib-1)
+        ec = np.array([ec_lo, ec_lo, ec_hi, ec_hi])
+        e = O.ct_corner(ec_hi, ec_lo, F, F, ec, mt, mt, m[1], m[1])
+        assert e == pytest.approx(F, abs=1e-14 * (1 + abs(F) + abs(ec_lo) + abs(ec_hi)))
+
+
+def test_ct_upwind_selection():
+    """With all transverse derivatives on one side zero and the other side
+    non-zero, the sign of the mass flux picks which side contributes."""
+    ec = np.array([0.0, 0.0, 0.0, 1.0])      # only cell (ia, ib) non-zero
+    faces = (0.0, 0.0, 0.0, 0.0)
+    # flux > 0 through both faces: upwind = lower cells, which are all zero
+    assert O.ct_corner(*faces, ec, 1.0, 1.0, 1.0, 1.0) == 0.0
+    # flux < 0 through both: upper cells, (ia, ib) enters d_b+ and d_a+
+    e = O.ct_corner(*faces, ec, -1.0, -1.0, -1.0, -1.0)
+    assert e == pytest.approx(-0.5)
+    # zero flux: averages -> half weight
+    e = O.ct_corner(*faces, ec, 0.0, 0.0, 0.0, 0.0)
+    assert e == pytest.approx(-0.25)
