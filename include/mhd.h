@@ -1,0 +1,155 @@
+/*
+ * mhd.h -- C ABI of the MI355X ideal-MHD finite-volume library.
+ *
+ * The library advances the ideal-MHD conservation laws with the main cycle
+ * that arXiv 2606.12753 §2.2.3 describes: per direction, reconstruction of
+ * primitive variables, a Riemann solve at every interface and a
+ * flux-conservative update; constrained transport (CT) for the magnetic
+ * field; Runge-Kutta stepping.  Concretely: PLM-minmod reconstruction, HLLD
+ * fluxes with HLL fallback, the flux-divergence update, contact-upwinded CT
+ * corner EMFs with the face-field update, the CFL time step from a
+ * max-reduction of the fast magnetosonic rate and the two-stage SSP
+ * Runge-Kutta combine, on 3D structured boxes (2D and 1D as boxes with
+ * inactive axes of one cell).
+ *
+ * All entry points return MHD_OK (0) or a negative status and never throw,
+ * abort or exit across the ABI.  A context is used by one host thread at a
+ * time.  Every compute step runs in the library's HIP kernels on the current
+ * HIP device of mhd_create; there is no CPU fallback.
+ *
+ * Array layout at this boundary (host or device memory, caller-owned):
+ * C order [z][y][x], x fastest, FP64.
+ *   cons[5]  = rho, m_x, m_y, m_z, E (total energy incl. |B|^2/2 of the
+ *              face-averaged field); nz*ny*nx doubles each.
+ *   bface[3] = face-centred B_x, B_y, B_z including both bounding faces:
+ *              B_x nz*ny*(nx+1), B_y nz*(ny+1)*nx, B_z (nz+1)*ny*nx.  On a
+ *              periodic axis the last face must equal the first.
+ * Caller arrays are never retained past the call that receives them.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MHD_OK 0
+#define MHD_E_INVAL (-1)   /* bad argument; nothing was changed */
+#define MHD_E_NOMEM (-2)   /* device allocation failed or workspace too small */
+#define MHD_E_DEVICE (-3)  /* HIP runtime error or no usable device */
+#define MHD_E_NONPHYS (-4) /* a cell had rho <= 0 or a non-finite state */
+#define MHD_E_STATE (-5)   /* call out of order (e.g. step before set_state) */
+
+/* boundary conditions, per axis (both sides of an axis must agree) */
+#define MHD_BC_PERIODIC 0
+#define MHD_BC_OUTFLOW 1 /* zero-gradient: ghosts copy the boundary cell */
+
+/* arithmetic of the reconstruction / Riemann / EMF work */
+#define MHD_FP64 0  /* everything FP64 */
+#define MHD_MIXED 1 /* FP32 reconstruction, fluxes, EMFs, residual; FP64
+                       state, pressure recovery, RK accumulation, dt */
+
+/* where caller arrays live */
+#define MHD_HOST 0
+#define MHD_DEVICE 1
+
+/* config flags */
+#define MHD_F_GRAPH 1u      /* replay each step from a captured HIP graph */
+#define MHD_F_PERSISTENT 2u /* persistent-grid launches over the tile table */
+#define MHD_F_TIMING 4u     /* time every kernel launch with HIP events on the
+                               context stream (serialises steps; no graph) */
+
+/* kernel kinds reported by mhd_kernel_times */
+#define MHD_K_LAMBDA 0   /* CFL rate max-reduction, per tile */
+#define MHD_K_DT 1       /* per-box time step from the tile maxima */
+#define MHD_K_SWEEP_X 2  /* x faces: PLM + Riemann solver */
+#define MHD_K_SWEEP_Y 3  /* y faces + x/y flux divergence */
+#define MHD_K_SWEEP_Z 4  /* z faces + divergence + RK stage combine */
+#define MHD_K_CT_EDGE 5  /* constrained-transport corner EMFs */
+#define MHD_K_CT_FACE 6  /* face-field update + RK stage combine */
+#define MHD_NKERNELS 7
+
+typedef struct {
+  int32_t n[3];            /* cells per axis; n == 1 makes the axis inactive */
+  double lo[3], hi[3];     /* domain corners; dx = (hi - lo) / n */
+  int32_t bc_lo[3], bc_hi[3];
+  double gamma;            /* ratio of specific heats (> 1) */
+  double cfl;              /* CFL number (> 0) */
+} mhd_box;
+
+typedef struct {
+  int32_t nboxes;          /* >= 1 independent boxes, advanced together */
+  const mhd_box *boxes;    /* nboxes descriptors (copied by mhd_create) */
+  int32_t precision;       /* MHD_FP64 or MHD_MIXED */
+  double p_floor;          /* pressure floor of the primitive recovery; <= 0:
+                              1e-10.  Total energy is never modified. */
+  void *stream;            /* hipStream_t to run on; NULL: the library
+                              creates its own */
+  void *workspace;         /* caller-owned device memory for all device
+                              buffers (e.g. a torch tensor), kept alive until
+                              mhd_destroy; NULL: the library allocates */
+  uint64_t workspace_bytes;
+  uint32_t flags;          /* MHD_F_* */
+} mhd_config;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* Device bytes the configuration needs (for a caller-provided workspace).
+ * Validates cfg like mhd_create; touches no device. */
+int mhd_workspace_bytes(const mhd_config *cfg, uint64_t *bytes);
+
+/* Validates cfg (before any device call), then creates a context on the
+ * current HIP device.  *out is set only on MHD_OK. */
+int mhd_create(const mhd_config *cfg, mhd_ctx **out);
+
+/* Copies the state of one box in (boundary layout; where = MHD_HOST or
+ * MHD_DEVICE) and sets its time.  Returns after the copy has completed.
+ * MHD_E_INVAL if a periodic axis has last face != first face. */
+int mhd_set_state(mhd_ctx *ctx, int32_t box, const double *const cons[5],
+                  const double *const bface[3], double t, int32_t where);
+
+/* Enqueues nsteps full SSP-RK2 steps of every box on the context stream.
+ * Each box steps with its own CFL time step computed on the device from its
+ * state at the start of the step, clamped to t_stop - t when t_stop > 0
+ * (steps at t >= t_stop are no-ops).  Returns without waiting; device errors
+ * surface at the next mhd_dt / mhd_get_state. */
+int mhd_step(mhd_ctx *ctx, int32_t nsteps, double t_stop);
+
+/* Waits for the stream, then returns the CFL time step the next step of the
+ * box would take (no t_stop clamp) and the box time.  MHD_E_NONPHYS if a
+ * non-physical cell was met since the last set_state (values still
+ * returned). */
+int mhd_dt(mhd_ctx *ctx, int32_t box, double *dt_next, double *t);
+
+/* Waits for the stream, then copies the state of one box out (boundary
+ * layout; where = MHD_HOST or MHD_DEVICE).  MHD_E_NONPHYS as for mhd_dt
+ * (the state is still copied). */
+int mhd_get_state(mhd_ctx *ctx, int32_t box, double *const cons[5],
+                  double *const bface[3], double *t, int32_t where);
+
+/* Waits for the stream, then returns the box's event counters since its last
+ * set_state: [0] pressure-floor hits (cells x stages), [1] HLL fallbacks
+ * (faces x stages), [2] non-physical cells (cells x stages). */
+int mhd_counters(mhd_ctx *ctx, int32_t box, int64_t counters[3]);
+
+/* With MHD_F_TIMING: total device milliseconds and launch counts of each
+ * kernel kind (MHD_K_*) since creation or the last reset (reset != 0 clears
+ * after reading).  Waits for the stream.  MHD_E_STATE without the flag. */
+int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
+                     int64_t launches[MHD_NKERNELS], int32_t reset);
+
+/* Frees the context and every buffer the library allocated (a caller
+ * workspace is left alone).  NULL is a no-op. */
+void mhd_destroy(mhd_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); for ctx == NULL, the
+ * last failure of mhd_create / mhd_workspace_bytes in this thread. */
+const char *mhd_last_error(const mhd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,776 @@
+// mhd_lib.hip -- host runtime and C ABI of the MI355X ideal-MHD library.
+//
+// One context owns the device buffers of an ensemble of boxes (one box is an
+// ensemble of one), a tile table per kernel kind and the launch sequence of
+// one SSP-RK2 step (arXiv 2606.12753 §2.2.3: reconstruct, Riemann solve,
+// conservative update per direction, constrained transport, Runge-Kutta):
+//
+//   k_lambda + k_dt            CFL rate max-reduction -> dt, t (per box)
+//   stage 1 and stage 2:
+//     k_sweep_x                x faces (LDS row segments)
+//     k_sweep_march<y>         y faces (register-window march), residual
+//     k_sweep_march<z>         z faces, residual, RK stage combine
+//     k_ct_edge                contact-upwinded corner EMFs
+//     k_ct_face                face-field update + RK stage combine
+//
+// The sequence can be captured once into a HIP graph and replayed per step;
+// dt and t never leave the device between steps.
+#include "../../include/mhd.h"
+#include "mhd_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using mhd::Box;
+using mhd::kTPB;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Geom {
+  int n[3], nf[3], per[3], act[3];
+  size_t N, F[3], E[3];
+};
+
+Geom geom_of(const mhd_box& b) {
+  Geom g;
+  for (int d = 0; d < 3; d++) {
+    g.n[d] = b.n[d];
+    g.per[d] = b.bc_lo[d] == MHD_BC_PERIODIC;
+    g.nf[d] = g.per[d] ? b.n[d] : b.n[d] + 1;
+    g.act[d] = b.n[d] > 1;
+  }
+  g.N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  for (int d = 0; d < 3; d++) {
+    size_t f = 1, e = 1;
+    for (int a = 0; a < 3; a++) {
+      f *= (size_t)(a == d ? g.nf[a] : g.n[a]);
+      e *= (size_t)(a == d ? g.n[a] : g.nf[a]);
+    }
+    g.F[d] = f;
+    g.E[d] = e;
+  }
+  return g;
+}
+
+int validate_box(const mhd_box& b, std::string& err) {
+  for (int d = 0; d < 3; d++) {
+    if (b.n[d] < 1 || b.n[d] > (1 << 20)) {
+      err = "box: n[" + std::to_string(d) + "] out of range";
+      return MHD_E_INVAL;
+    }
+    if (!(b.hi[d] > b.lo[d]) || !std::isfinite(b.hi[d] - b.lo[d])) {
+      err = "box: hi must exceed lo on every axis";
+      return MHD_E_INVAL;
+    }
+    if (b.bc_lo[d] != b.bc_hi[d] ||
+        (b.bc_lo[d] != MHD_BC_PERIODIC && b.bc_lo[d] != MHD_BC_OUTFLOW)) {
+      err = "box: boundary conditions must be periodic or outflow and alike on both sides";
+      return MHD_E_INVAL;
+    }
+  }
+  if (!(b.gamma > 1.0) || !std::isfinite(b.gamma)) {
+    err = "box: gamma must be > 1";
+    return MHD_E_INVAL;
+  }
+  if (!(b.cfl > 0.0) || !std::isfinite(b.cfl)) {
+    err = "box: cfl must be > 0";
+    return MHD_E_INVAL;
+  }
+  const Geom g = geom_of(b);
+  if (g.N > (size_t)1 << 31) {
+    err = "box: more than 2^31 cells";
+    return MHD_E_INVAL;
+  }
+  return MHD_OK;
+}
+
+int validate_config(const mhd_config* cfg, std::string& err) {
+  if (!cfg) {
+    err = "config is NULL";
+    return MHD_E_INVAL;
+  }
+  if (cfg->nboxes < 1 || cfg->nboxes > (1 << 20) || !cfg->boxes) {
+    err = "config: need nboxes >= 1 and a boxes array";
+    return MHD_E_INVAL;
+  }
+  if (cfg->precision != MHD_FP64 && cfg->precision != MHD_MIXED) {
+    err = "config: precision must be MHD_FP64 or MHD_MIXED";
+    return MHD_E_INVAL;
+  }
+  if (cfg->flags & ~(uint32_t)(MHD_F_GRAPH | MHD_F_PERSISTENT | MHD_F_TIMING)) {
+    err = "config: unknown flag bits";
+    return MHD_E_INVAL;
+  }
+  if (!std::isfinite(cfg->p_floor)) {
+    err = "config: p_floor must be finite";
+    return MHD_E_INVAL;
+  }
+  for (int b = 0; b < cfg->nboxes; b++) {
+    int rc = validate_box(cfg->boxes[b], err);
+    if (rc) {
+      err = "box " + std::to_string(b) + ": " + err;
+      return rc;
+    }
+  }
+  return MHD_OK;
+}
+
+// tiling of one box (the y/z march segment lengths are tunable)
+struct Tiling {
+  int xw, xr, xseg, ysl, yseg, zsl, zseg;
+  int ntile[6];
+};
+
+Tiling tiling_of(const Geom& g, int ysl, int zsl) {
+  Tiling t;
+  if (g.nf[0] <= kTPB) {
+    t.xw = g.nf[0];
+    t.xr = std::min(kTPB / g.nf[0], mhd::kLdsCells / (g.nf[0] + 3));
+    if (t.xr < 1) t.xr = 1;
+    t.xseg = 1;
+  } else {
+    t.xw = kTPB;
+    t.xr = 1;
+    t.xseg = (g.nf[0] + kTPB - 1) / kTPB;
+  }
+  t.ysl = g.act[1] ? std::max(1, std::min(ysl, g.n[1])) : 1;
+  t.yseg = (g.n[1] + t.ysl - 1) / t.ysl;
+  t.zsl = g.act[2] ? std::max(1, std::min(zsl, g.n[2])) : 1;
+  t.zseg = (g.n[2] + t.zsl - 1) / t.zsl;
+  const long long nrows = (long long)g.n[1] * g.n[2];
+  t.ntile[mhd::kXS] = (int)(t.xseg == 1 ? (nrows + t.xr - 1) / t.xr : nrows * t.xseg);
+  t.ntile[mhd::kYS] = (int)(((long long)g.n[0] * g.n[2] + kTPB - 1) / kTPB * t.yseg);
+  t.ntile[mhd::kZS] = (int)(((long long)g.n[0] * g.n[1] + kTPB - 1) / kTPB * t.zseg);
+  const long long P = (long long)g.nf[0] * g.nf[1] * g.nf[2];
+  t.ntile[mhd::kCTE] = (int)((P + kTPB - 1) / kTPB);
+  t.ntile[mhd::kCTF] = t.ntile[mhd::kCTE];
+  t.ntile[mhd::kLAM] = (int)((g.N + kTPB - 1) / kTPB);
+  return t;
+}
+
+constexpr int kDefaultSeg = 32;
+
+// byte layout of the workspace
+struct Plan {
+  size_t total;
+  size_t boxes_off, base_off, flag_off;
+  std::vector<size_t> box_off;  // start of each box's region
+  std::vector<size_t> box_bytes;
+};
+
+size_t box_bytes(const Geom& g, const Tiling& t, size_t rs) {
+  size_t s = 0;
+  s += 2 * mhd::kNQ * align_up(g.N * 8);
+  for (int d = 0; d < 3; d++) s += 2 * align_up(g.F[d] * 8);
+  s += 3 * align_up(g.N * rs);                      // Ec
+  s += mhd::kNQ * align_up(g.F[0] * rs);            // FX
+  for (int d = 0; d < 3; d++) s += 3 * align_up(g.F[d] * rs);  // EF x2 + MF
+  s += mhd::kNQ * align_up(g.N * rs);               // R
+  for (int c = 0; c < 3; c++) s += align_up(g.E[c] * rs);  // ED
+  s += align_up((size_t)t.ntile[mhd::kLAM] * 8);    // lam
+  s += align_up(4 * 8);                             // scal
+  s += align_up(3 * 8);                             // cnt
+  return s;
+}
+
+Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
+  Plan p;
+  const size_t rs = cfg->precision == MHD_FP64 ? 8 : 4;
+  size_t off = 0;
+  p.boxes_off = off;
+  off += align_up(sizeof(Box) * (size_t)cfg->nboxes);
+  p.base_off = off;
+  off += align_up(sizeof(int) * 6 * ((size_t)cfg->nboxes + 1));
+  p.flag_off = off;
+  off += align_up(sizeof(int));
+  for (int b = 0; b < cfg->nboxes; b++) {
+    Geom g = geom_of(cfg->boxes[b]);
+    Tiling t = tiling_of(g, ysl, zsl);
+    size_t bb = box_bytes(g, t, rs);
+    p.box_off.push_back(off);
+    p.box_bytes.push_back(bb);
+    off += bb;
+  }
+  p.total = off;
+  return p;
+}
+
+}  // namespace
+
+struct mhd_ctx {
+  std::vector<mhd_box> boxes;
+  int precision = MHD_FP64;
+  double pfloor = 1e-10;
+  uint32_t flags = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  std::vector<Box> hbox;
+  std::vector<Geom> geom;
+  std::vector<int> base;  // 6 * (nboxes + 1)
+  int total[6] = {0, 0, 0, 0, 0, 0};
+  int grid[6] = {0, 0, 0, 0, 0, 0};
+  Box* dbox = nullptr;
+  int* dbase = nullptr;
+  int* dflag = nullptr;
+  std::vector<char> state_set;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  // MHD_F_TIMING: one event pair per launch of a step, reused every step
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  double kms[MHD_NKERNELS] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t kcount[MHD_NKERNELS] = {0, 0, 0, 0, 0, 0, 0};
+  std::string err;
+};
+
+namespace {
+
+int fail(mhd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                      \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return fail((ctx), MHD_E_DEVICE,                                         \
+                  std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+template <typename real>
+int enqueue_step_t(mhd_ctx* c) {
+  mhd::Launch L;
+  L.boxes = c->dbox;
+  L.base = c->dbase;
+  L.nboxes = (int)c->boxes.size();
+  auto grid = [&](int kind) {
+    int g = c->total[kind];
+    if (c->grid[kind] > 0 && c->grid[kind] < g) g = c->grid[kind];
+    return g < 1 ? 1 : g;
+  };
+  const bool timing = (c->flags & MHD_F_TIMING) != 0;
+  int slot = 0;
+  // event pair around each launch in timing mode
+  auto mark = [&](int kind, bool before) {
+    if (!timing) return;
+    if (before) {
+      c->ev_kind[slot] = kind;
+      (void)hipEventRecord(c->ev[2 * slot], c->stream);
+    } else {
+      (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+      slot++;
+    }
+  };
+  L.stage = 0;
+  L.ntiles = c->total[mhd::kLAM];
+  mark(MHD_K_LAMBDA, true);
+  hipLaunchKernelGGL(mhd::k_lambda, dim3(grid(mhd::kLAM)), dim3(kTPB), 0, c->stream, L);
+  mark(MHD_K_LAMBDA, false);
+  mark(MHD_K_DT, true);
+  hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 0);
+  mark(MHD_K_DT, false);
+  for (int s = 0; s < 2; s++) {
+    L.stage = s;
+    L.ntiles = c->total[mhd::kXS];
+    mark(MHD_K_SWEEP_X, true);
+    hipLaunchKernelGGL(mhd::k_sweep_x<real>, dim3(grid(mhd::kXS)), dim3(kTPB), 0, c->stream, L);
+    mark(MHD_K_SWEEP_X, false);
+    L.ntiles = c->total[mhd::kYS];
+    mark(MHD_K_SWEEP_Y, true);
+    hipLaunchKernelGGL((mhd::k_sweep_march<real, 1>), dim3(grid(mhd::kYS)), dim3(kTPB), 0,
+                       c->stream, L);
+    mark(MHD_K_SWEEP_Y, false);
+    L.ntiles = c->total[mhd::kZS];
+    mark(MHD_K_SWEEP_Z, true);
+    hipLaunchKernelGGL((mhd::k_sweep_march<real, 2>), dim3(grid(mhd::kZS)), dim3(kTPB), 0,
+                       c->stream, L);
+    mark(MHD_K_SWEEP_Z, false);
+    L.ntiles = c->total[mhd::kCTE];
+    mark(MHD_K_CT_EDGE, true);
+    hipLaunchKernelGGL(mhd::k_ct_edge<real>, dim3(grid(mhd::kCTE)), dim3(kTPB), 0, c->stream, L);
+    mark(MHD_K_CT_EDGE, false);
+    L.ntiles = c->total[mhd::kCTF];
+    mark(MHD_K_CT_FACE, true);
+    hipLaunchKernelGGL(mhd::k_ct_face<real>, dim3(grid(mhd::kCTF)), dim3(kTPB), 0, c->stream, L);
+    mark(MHD_K_CT_FACE, false);
+  }
+  HIPCHK(c, hipGetLastError());
+  if (timing) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < slot; k++) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+      c->kms[c->ev_kind[k]] += ms;
+      c->kcount[c->ev_kind[k]] += 1;
+    }
+  }
+  return MHD_OK;
+}
+
+constexpr int kLaunchesPerStep = 12;
+
+int enqueue_step(mhd_ctx* c) {
+  return c->precision == MHD_FP64 ? enqueue_step_t<double>(c) : enqueue_step_t<float>(c);
+}
+
+__global__ void k_set_scalar(const Box* boxes, int nboxes, int slot, double v) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nboxes) boxes[b].scal[slot] = v;
+}
+
+__global__ void k_reset_box(const Box* boxes, int box, double t) {
+  const Box& b = boxes[box];
+  if (threadIdx.x == 0) {
+    b.scal[0] = 0.0;
+    b.scal[1] = t;
+    b.scal[2] = 0.0;
+    b.scal[3] = 0.0;
+    b.cnt[0] = 0;
+    b.cnt[1] = 0;
+    b.cnt[2] = 0;
+  }
+}
+
+int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
+  const int nb = cfg->nboxes;
+  const Plan plan = make_plan(cfg, kDefaultSeg, kDefaultSeg);
+  if (cfg->workspace) {
+    if (cfg->workspace_bytes < plan.total)
+      return fail(c, MHD_E_NOMEM, "workspace smaller than mhd_workspace_bytes()");
+    if ((uintptr_t)cfg->workspace % kAlign)
+      return fail(c, MHD_E_INVAL, "workspace must be 256-byte aligned");
+    c->ws = static_cast<char*>(cfg->workspace);
+    c->ws_bytes = cfg->workspace_bytes;
+    c->own_ws = false;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, plan.total) != hipSuccess)
+      return fail(c, MHD_E_NOMEM, "hipMalloc of " + std::to_string(plan.total) + " bytes failed");
+    c->ws = static_cast<char*>(p);
+    c->ws_bytes = plan.total;
+    c->own_ws = true;
+  }
+  const size_t rs = cfg->precision == MHD_FP64 ? 8 : 4;
+  c->dbox = reinterpret_cast<Box*>(c->ws + plan.boxes_off);
+  c->dbase = reinterpret_cast<int*>(c->ws + plan.base_off);
+  c->dflag = reinterpret_cast<int*>(c->ws + plan.flag_off);
+  c->hbox.resize(nb);
+  c->geom.resize(nb);
+  c->base.assign(6 * (nb + 1), 0);
+  for (int k = 0; k < 6; k++) c->total[k] = 0;
+  for (int bi = 0; bi < nb; bi++) {
+    const mhd_box& mb = cfg->boxes[bi];
+    Geom g = geom_of(mb);
+    Tiling t = tiling_of(g, kDefaultSeg, kDefaultSeg);
+    c->geom[bi] = g;
+    Box& b = c->hbox[bi];
+    std::memset(&b, 0, sizeof(Box));
+    for (int d = 0; d < 3; d++) {
+      b.n[d] = g.n[d];
+      b.nf[d] = g.nf[d];
+      b.per[d] = g.per[d];
+      b.act[d] = g.act[d];
+      b.dx[d] = (mb.hi[d] - mb.lo[d]) / (double)mb.n[d];
+    }
+    b.gamma = mb.gamma;
+    b.cfl = mb.cfl;
+    b.pfloor = cfg->p_floor > 0.0 ? cfg->p_floor : 1e-10;
+    char* p = c->ws + plan.box_off[bi];
+    auto take = [&](size_t bytes) {
+      char* q = p;
+      p += align_up(bytes);
+      return q;
+    };
+    for (int s = 0; s < 2; s++)
+      for (int q = 0; q < mhd::kNQ; q++) b.U[s][q] = reinterpret_cast<double*>(take(g.N * 8));
+    for (int s = 0; s < 2; s++)
+      for (int d = 0; d < 3; d++) b.B[s][d] = reinterpret_cast<double*>(take(g.F[d] * 8));
+    for (int d = 0; d < 3; d++) b.Ec[d] = take(g.N * rs);
+    for (int q = 0; q < mhd::kNQ; q++) b.FX[q] = take(g.F[0] * rs);
+    for (int d = 0; d < 3; d++) {
+      b.EF[d][0] = take(g.F[d] * rs);
+      b.EF[d][1] = take(g.F[d] * rs);
+      b.MF[d] = take(g.F[d] * rs);
+    }
+    for (int q = 0; q < mhd::kNQ; q++) b.R[q] = take(g.N * rs);
+    for (int cc = 0; cc < 3; cc++) b.ED[cc] = take(g.E[cc] * rs);
+    b.lam = reinterpret_cast<double*>(take((size_t)t.ntile[mhd::kLAM] * 8));
+    b.scal = reinterpret_cast<double*>(take(4 * 8));
+    b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
+    b.xw = t.xw;
+    b.xr = t.xr;
+    b.xseg = t.xseg;
+    b.ysl = t.ysl;
+    b.yseg = t.yseg;
+    b.zsl = t.zsl;
+    b.zseg = t.zseg;
+    for (int k = 0; k < 6; k++) {
+      b.ntile[k] = t.ntile[k];
+      c->base[k * (nb + 1) + bi] = c->total[k];
+      c->total[k] += t.ntile[k];
+    }
+    if ((size_t)(p - c->ws) > plan.box_off[bi] + plan.box_bytes[bi])
+      return fail(c, MHD_E_NOMEM, "internal: workspace plan overflow");
+  }
+  for (int k = 0; k < 6; k++) {
+    c->base[k * (nb + 1) + nb] = c->total[k];
+    if (c->total[k] < 0) return fail(c, MHD_E_INVAL, "tile count overflow");
+  }
+  if (c->flags & MHD_F_TIMING) {
+    c->ev.assign(2 * kLaunchesPerStep, nullptr);
+    c->ev_kind.assign(kLaunchesPerStep, 0);
+    for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  if (c->flags & MHD_F_PERSISTENT) {
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+    // eight resident workgroups per compute unit
+    for (int k = 0; k < 6; k++) c->grid[k] = prop.multiProcessorCount * 8;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->dbox, c->hbox.data(), sizeof(Box) * nb, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dbase, c->base.data(), sizeof(int) * c->base.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  for (int bi = 0; bi < nb; bi++)
+    hipLaunchKernelGGL(k_reset_box, dim3(1), dim3(64), 0, c->stream, c->dbox, bi, 0.0);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->state_set.assign(nb, 0);
+  return MHD_OK;
+}
+
+int check_box_index(mhd_ctx* c, int32_t box) {
+  if (!c) return MHD_E_INVAL;
+  if (box < 0 || box >= (int32_t)c->boxes.size())
+    return fail(c, MHD_E_INVAL, "box index out of range");
+  return MHD_OK;
+}
+
+// copy between the boundary layout (n+1 faces) and the internal layout (n
+// faces on periodic axes)
+int copy_faces(mhd_ctx* c, const Geom& g, int d, double* dst, const double* src, bool to_internal,
+               hipMemcpyKind kind) {
+  const size_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  if (!g.per[d]) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, g.F[d] * 8, kind, c->stream));
+    return MHD_OK;
+  }
+  size_t width, rows, ext_pitch, int_pitch;
+  if (d == 0) {
+    width = nx * 8;
+    rows = ny * nz;
+    ext_pitch = (nx + 1) * 8;
+    int_pitch = nx * 8;
+  } else if (d == 1) {
+    width = ny * nx * 8;
+    rows = nz;
+    ext_pitch = (ny + 1) * nx * 8;
+    int_pitch = ny * nx * 8;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(dst, src, nz * ny * nx * 8, kind, c->stream));
+    if (!to_internal) {
+      // last plane = first plane
+      HIPCHK(c, hipMemcpyAsync(dst + nz * ny * nx, src, ny * nx * 8, kind, c->stream));
+    }
+    return MHD_OK;
+  }
+  if (to_internal) {
+    HIPCHK(c, hipMemcpy2DAsync(dst, int_pitch, src, ext_pitch, width, rows, kind, c->stream));
+  } else {
+    HIPCHK(c, hipMemcpy2DAsync(dst, ext_pitch, src, int_pitch, width, rows, kind, c->stream));
+    // duplicate face 0 into face n
+    const size_t first_w = d == 0 ? 8 : nx * 8;
+    HIPCHK(c, hipMemcpy2DAsync(reinterpret_cast<char*>(dst) + width, ext_pitch, src, int_pitch,
+                               first_w, rows, kind, c->stream));
+  }
+  return MHD_OK;
+}
+
+bool host_periodic_ok(const Geom& g, int d, const double* a) {
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int ex = nx + (d == 0), ey = ny + (d == 1);
+  const int e0 = d == 0 ? 1 : nx, e1 = d == 1 ? 1 : ny, e2 = d == 2 ? 1 : nz;
+  for (int k = 0; k < e2; k++)
+    for (int j = 0; j < e1; j++)
+      for (int i = 0; i < e0; i++) {
+        int i2 = i, j2 = j, k2 = k;
+        if (d == 0) i2 = nx; else if (d == 1) j2 = ny; else k2 = nz;
+        if (a[((size_t)k * ey + j) * ex + i] != a[((size_t)k2 * ey + j2) * ex + i2]) return false;
+      }
+  return true;
+}
+
+int read_flags(mhd_ctx* c, int32_t box, unsigned long long cnt[3]) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(cnt, c->hbox[box].cnt, 3 * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost));
+  return MHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhd_workspace_bytes(const mhd_config* cfg, uint64_t* bytes) {
+  std::string err;
+  int rc = validate_config(cfg, err);
+  if (rc) {
+    g_create_error = err;
+    return rc;
+  }
+  if (!bytes) {
+    g_create_error = "bytes is NULL";
+    return MHD_E_INVAL;
+  }
+  *bytes = make_plan(cfg, kDefaultSeg, kDefaultSeg).total;
+  return MHD_OK;
+}
+
+int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
+  std::string err;
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MHD_E_INVAL;
+  }
+  int rc = validate_config(cfg, err);
+  if (rc) {
+    g_create_error = err;
+    return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_create_error = "no HIP device";
+    return MHD_E_DEVICE;
+  }
+  mhd_ctx* c = new (std::nothrow) mhd_ctx();
+  if (!c) {
+    g_create_error = "out of host memory";
+    return MHD_E_NOMEM;
+  }
+  c->boxes.assign(cfg->boxes, cfg->boxes + cfg->nboxes);
+  c->precision = cfg->precision;
+  c->pfloor = cfg->p_floor > 0.0 ? cfg->p_floor : 1e-10;
+  c->flags = cfg->flags;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    g_create_error = "hipGetDevice failed";
+    return MHD_E_DEVICE;
+  }
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      g_create_error = "hipStreamCreate failed";
+      return MHD_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  rc = build_ctx(c, cfg);
+  if (rc) {
+    g_create_error = c->err;
+    mhd_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MHD_OK;
+}
+
+int mhd_set_state(mhd_ctx* c, int32_t box, const double* const cons[5],
+                  const double* const bface[3], double t, int32_t where) {
+  int rc = check_box_index(c, box);
+  if (rc) return rc;
+  if (!cons || !bface) return fail(c, MHD_E_INVAL, "cons/bface is NULL");
+  for (int q = 0; q < 5; q++)
+    if (!cons[q]) return fail(c, MHD_E_INVAL, "cons array is NULL");
+  for (int d = 0; d < 3; d++)
+    if (!bface[d]) return fail(c, MHD_E_INVAL, "bface array is NULL");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(c, MHD_E_INVAL, "bad where");
+  if (!std::isfinite(t)) return fail(c, MHD_E_INVAL, "t must be finite");
+  const Geom& g = c->geom[box];
+  const hipMemcpyKind kind = where == MHD_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  if (where == MHD_HOST) {
+    for (int d = 0; d < 3; d++)
+      if (g.per[d] && !host_periodic_ok(g, d, bface[d]))
+        return fail(c, MHD_E_INVAL, "periodic axis " + std::to_string(d) +
+                                        ": last face differs from the first");
+  } else {
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->dflag, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    for (int d = 0; d < 3; d++) {
+      if (!g.per[d]) continue;
+      hipLaunchKernelGGL(mhd::k_check_periodic, dim3(256), dim3(kTPB), 0, c->stream, bface[d], d,
+                         g.n[0], g.n[1], g.n[2], c->dflag);
+    }
+    HIPCHK(c, hipGetLastError());
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, MHD_E_INVAL, "periodic axis: last face differs from the first");
+  }
+  const Box& b = c->hbox[box];
+  for (int q = 0; q < 5; q++)
+    HIPCHK(c, hipMemcpyAsync(b.U[0][q], cons[q], g.N * 8, kind, c->stream));
+  for (int d = 0; d < 3; d++) {
+    rc = copy_faces(c, g, d, b.B[0][d], bface[d], true, kind);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_reset_box, dim3(1), dim3(64), 0, c->stream, c->dbox, box, t);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->state_set[box] = 1;
+  return MHD_OK;
+}
+
+int mhd_step(mhd_ctx* c, int32_t nsteps, double t_stop) {
+  if (!c) return MHD_E_INVAL;
+  if (nsteps < 0) return fail(c, MHD_E_INVAL, "nsteps < 0");
+  if (!std::isfinite(t_stop)) return fail(c, MHD_E_INVAL, "t_stop must be finite");
+  for (size_t b = 0; b < c->boxes.size(); b++)
+    if (!c->state_set[b]) return fail(c, MHD_E_STATE, "mhd_step before mhd_set_state of every box");
+  if (nsteps == 0) return MHD_OK;
+  const int nb = (int)c->boxes.size();
+  hipLaunchKernelGGL(k_set_scalar, dim3((nb + 255) / 256), dim3(256), 0, c->stream, c->dbox, nb, 2,
+                     t_stop > 0.0 ? t_stop : 0.0);
+  HIPCHK(c, hipGetLastError());
+  if ((c->flags & MHD_F_GRAPH) && !(c->flags & MHD_F_TIMING)) {
+    if (!c->gexec) {
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue_step(c);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (rc) return rc;
+      if (e != hipSuccess) return fail(c, MHD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      c->graph = g;
+      HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    }
+    for (int s = 0; s < nsteps; s++) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    for (int s = 0; s < nsteps; s++) {
+      int rc = enqueue_step(c);
+      if (rc) return rc;
+    }
+  }
+  return MHD_OK;
+}
+
+int mhd_dt(mhd_ctx* c, int32_t box, double* dt_next, double* t) {
+  int rc = check_box_index(c, box);
+  if (rc) return rc;
+  if (!c->state_set[box]) return fail(c, MHD_E_STATE, "mhd_dt before mhd_set_state");
+  mhd::Launch L;
+  L.boxes = c->dbox;
+  L.base = c->dbase;
+  L.nboxes = (int)c->boxes.size();
+  L.stage = 0;
+  L.ntiles = c->total[mhd::kLAM];
+  hipLaunchKernelGGL(mhd::k_lambda, dim3(std::max(1, L.ntiles)), dim3(kTPB), 0, c->stream, L);
+  hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 1);
+  HIPCHK(c, hipGetLastError());
+  double scal[4];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(scal, c->hbox[box].scal, sizeof(scal), hipMemcpyDeviceToHost));
+  if (dt_next) *dt_next = scal[3];
+  if (t) *t = scal[1];
+  unsigned long long cnt[3];
+  rc = read_flags(c, box, cnt);
+  if (rc) return rc;
+  if (cnt[2]) return fail(c, MHD_E_NONPHYS, "non-physical cells were met");
+  return MHD_OK;
+}
+
+int mhd_get_state(mhd_ctx* c, int32_t box, double* const cons[5], double* const bface[3],
+                  double* t, int32_t where) {
+  int rc = check_box_index(c, box);
+  if (rc) return rc;
+  if (!c->state_set[box]) return fail(c, MHD_E_STATE, "mhd_get_state before mhd_set_state");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(c, MHD_E_INVAL, "bad where");
+  if (!cons || !bface) return fail(c, MHD_E_INVAL, "cons/bface is NULL");
+  for (int q = 0; q < 5; q++)
+    if (!cons[q]) return fail(c, MHD_E_INVAL, "cons array is NULL");
+  for (int d = 0; d < 3; d++)
+    if (!bface[d]) return fail(c, MHD_E_INVAL, "bface array is NULL");
+  const Geom& g = c->geom[box];
+  const Box& b = c->hbox[box];
+  const hipMemcpyKind kind = where == MHD_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  for (int q = 0; q < 5; q++)
+    HIPCHK(c, hipMemcpyAsync(cons[q], b.U[0][q], g.N * 8, kind, c->stream));
+  for (int d = 0; d < 3; d++) {
+    rc = copy_faces(c, g, d, bface[d], b.B[0][d], false, kind);
+    if (rc) return rc;
+  }
+  double scal[4];
+  HIPCHK(c, hipMemcpyAsync(scal, b.scal, sizeof(scal), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (t) *t = scal[1];
+  unsigned long long cnt[3];
+  rc = read_flags(c, box, cnt);
+  if (rc) return rc;
+  if (cnt[2]) return fail(c, MHD_E_NONPHYS, "non-physical cells were met");
+  return MHD_OK;
+}
+
+int mhd_counters(mhd_ctx* c, int32_t box, int64_t counters[3]) {
+  int rc = check_box_index(c, box);
+  if (rc) return rc;
+  if (!counters) return fail(c, MHD_E_INVAL, "counters is NULL");
+  unsigned long long cnt[3];
+  rc = read_flags(c, box, cnt);
+  if (rc) return rc;
+  for (int k = 0; k < 3; k++) counters[k] = (int64_t)cnt[k];
+  return MHD_OK;
+}
+
+int mhd_kernel_times(mhd_ctx* c, double ms[MHD_NKERNELS], int64_t launches[MHD_NKERNELS],
+                     int32_t reset) {
+  if (!c) return MHD_E_INVAL;
+  if (!(c->flags & MHD_F_TIMING)) return fail(c, MHD_E_STATE, "context created without MHD_F_TIMING");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < MHD_NKERNELS; k++) {
+    if (ms) ms[k] = c->kms[k];
+    if (launches) launches[k] = c->kcount[k];
+    if (reset) {
+      c->kms[k] = 0.0;
+      c->kcount[k] = 0;
+    }
+  }
+  return MHD_OK;
+}
+
+void mhd_destroy(mhd_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* mhd_last_error(const mhd_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

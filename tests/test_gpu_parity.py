@@ -1,0 +1,330 @@
+"""GPU parity: the HIP library, called through the C ABI, against the CPU
+oracle on the same seeded inputs.
+
+FP64 bar: relative L1 <= 1e-12 per variable (rho, m, E and the three face
+fields) after the fixed step count, with identical time, time step and event
+counters.  The library evaluates every FP64 formula in the oracle's order
+without FMA contraction, so the comparison is expected to be exact; the
+tolerance is the stated bar.  Mixed bar: relative L1 <= 1e-4 on rho, p and
+|B| (computed in FP64 from both final states) and normalised
+max|div B| <= 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_12753_amd import mhd
+from paper_2606_12753_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOLMIX = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mhd.load()
+
+
+def rel_l1(a, b):
+    den = float(np.sum(np.abs(b)))
+    num = float(np.sum(np.abs(a - b)))
+    return num / den if den > 0 else num / max(1, b.size)
+
+
+def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None):
+    idx = range(len(wl.boxes)) if boxes is None else boxes
+    specs = [wl.boxes[i] for i in idx]
+    out = []
+    with mhd.Sim(specs, precision=precision, flags=flags) as sim:
+        for k, i in enumerate(idx):
+            st = wl.states[i]
+            sim.set_state(k, st.cons, st.bface, st.t)
+        sim.step(nsteps, t_stop)
+        for k in range(len(specs)):
+            cons, bface, t = sim.get_state(k)
+            out.append((cons, bface, t, sim.counters(k)))
+    return out
+
+
+def oracle_run(spec, st, nsteps, t_stop=0.0):
+    b = O.OracleBox(spec)
+    b.set_state(st.cons, st.bface, st.t)
+    b.step(nsteps, t_stop)
+    cons, bface, t = b.get_state()
+    return cons, bface, t, b.counters()
+
+
+def assert_fp64_parity(g, o, label=""):
+    gc, gb, gt, gcnt = g
+    oc, ob, ot, ocnt = o
+    assert gt == ot, (label, gt, ot)
+    names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
+    worst = 0.0
+    for name, a, b in zip(names, gc + gb, oc + ob):
+        e = rel_l1(a, b)
+        worst = max(worst, e)
+        assert e <= TOL64, (label, name, e)
+    assert gcnt == ocnt, (label, gcnt, ocnt)
+    return worst
+
+
+def pressure_bmag(spec, cons, bface):
+    bx = 0.5 * (bface[0][:, :, :-1] + bface[0][:, :, 1:])
+    by = 0.5 * (bface[1][:, :-1, :] + bface[1][:, 1:, :])
+    bz = 0.5 * (bface[2][:-1, :, :] + bface[2][1:, :, :])
+    rho, mx, my, mz, en = cons
+    b2 = bx * bx + by * by + bz * bz
+    p = (spec.gamma - 1.0) * (en - 0.5 * (mx * mx + my * my + mz * mz) / rho - 0.5 * b2)
+    return p, np.sqrt(b2)
+
+
+def divb_norm(spec, bface):
+    dx = spec.dx
+    div = ((bface[0][:, :, 1:] - bface[0][:, :, :-1]) / dx[0]
+           + (bface[1][:, 1:, :] - bface[1][:, :-1, :]) / dx[1]
+           + (bface[2][1:, :, :] - bface[2][:-1, :, :]) / dx[2])
+    bmax = max(float(np.max(np.abs(b))) for b in bface)
+    return float(np.max(np.abs(div))) * min(dx) / max(bmax, 1e-300), float(np.max(np.abs(div)))
+
+
+# ---------------------------------------------------------------- FP64
+
+def test_orszag_tang_2d_fp64_50_steps():
+    wl = W.orszag_tang_2d(n=128, steps=50)
+    g = gpu_run(wl, 50)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 50)
+    worst = assert_fp64_parity(g, o, "OT2D")
+    print(f"OT2D 128^2 x 50: worst rel L1 = {worst:.3e}")
+
+
+@pytest.mark.parametrize("n,bc", [
+    ((37, 23, 19), (0, 0, 0)),      # ragged tiles everywhere
+    ((33, 20, 17), (0, 1, 0)),      # outflow in y
+    ((24, 18, 40), (1, 0, 1)),      # outflow in x and z, two z segments
+    ((300, 6, 5), (0, 0, 0)),       # x rows longer than one workgroup
+    ((40, 70, 3), (0, 0, 0)),       # ragged y segments
+])
+def test_random_state_fp64(n, bc):
+    wl = W.random_smooth(n=n, seed=sum(n), bc=bc)
+    g = gpu_run(wl, 4)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4)
+    assert_fp64_parity(g, o, f"random {n} {bc}")
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_inactive_axes_fp64(axis):
+    wl = W.cp_alfven(64, axis=axis)
+    g = gpu_run(wl, 20)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 20)
+    assert_fp64_parity(g, o, f"cp axis {axis}")
+
+
+def test_hll_fallback_and_floor_counters_match():
+    # a violent state: strong converging/diverging flows at low pressure
+    spec = W.BoxSpec((24, 16, 8), cfl=0.3)
+    z, y, x = W._grid(spec)
+    rng = np.random.default_rng(99)
+    vx = 8.0 * np.sign(np.sin(2 * np.pi * x)) + 0 * y + 0 * z
+    vy = rng.uniform(-3, 3, size=(8, 16, 24))
+    p = 1e-3 + 0 * x * y * z
+    bface = [np.full(s, 0.05) for s in W.face_shapes(spec)]
+    st = W.conserved(spec, 1.0 + 0 * x * y * z, vx, vy, 0.0, p, bface)
+    wl = W.Workload("violent", [spec], [st], 3)
+    g = gpu_run(wl, 3)[0]
+    o = oracle_run(spec, st, 3)
+    assert o[3]["hll"] > 0
+    assert_fp64_parity(g, o, "violent")
+
+
+def test_graph_persistent_and_plain_launches_identical():
+    wl = W.random_smooth(n=(29, 21, 13), seed=3)
+    ref = gpu_run(wl, 3, flags=0)[0]
+    for flags in (mhd.MHD_F_GRAPH, mhd.MHD_F_PERSISTENT, mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT):
+        g = gpu_run(wl, 3, flags=flags)[0]
+        assert g[2] == ref[2]
+        for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
+            assert np.array_equal(a, b), flags
+
+
+def test_ensemble_of_uneven_boxes():
+    boxes, states = [], []
+    for n, seed, bc in [((16, 16, 16), 1, (0, 0, 0)), ((24, 12, 20), 2, (0, 1, 0)),
+                        ((32, 32, 8), 3, (0, 0, 0)), ((48, 20, 1), 4, (0, 0, 0))]:
+        w = W.random_smooth(n=n, seed=seed, bc=bc)
+        boxes += w.boxes
+        states += w.states
+    wl = W.Workload("mix", boxes, states, 3)
+    for flags in (0, mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT):
+        res = gpu_run(wl, 3, flags=flags)
+        for i, g in enumerate(res):
+            o = oracle_run(boxes[i], states[i], 3)
+            assert_fp64_parity(g, o, f"ensemble box {i}")
+
+
+def test_dt_query_and_t_stop():
+    wl = W.random_smooth(n=(20, 16, 12), seed=8)
+    spec, st = wl.boxes[0], wl.states[0]
+    ob = O.OracleBox(spec)
+    ob.set_state(st.cons, st.bface)
+    with mhd.Sim([spec]) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt, t = sim.dt(0)
+        assert dt == ob.dt() and t == 0.0
+        sim.step(10, t_stop=2.5 * dt)
+        _, _, t = sim.get_state(0)
+    ob.step(10, 2.5 * dt)
+    assert t == ob.get_state()[2]
+
+
+def test_set_get_roundtrip_host_and_device():
+    import torch
+    wl = W.random_smooth(n=(10, 9, 8), seed=11, bc=(0, 1, 0))
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec]) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.25)
+        cons, bface, t = sim.get_state(0)
+        assert t == 0.25
+        for a, b in zip(cons + bface, st.cons + st.bface):
+            assert np.array_equal(a, b)
+        dc = [torch.from_numpy(a).cuda() for a in st.cons]
+        db = [torch.from_numpy(a).cuda() for a in st.bface]
+        sim.set_state(0, dc, db, 0.5)
+        oc = [torch.empty_like(a) for a in dc]
+        obf = [torch.empty_like(a) for a in db]
+        _, _, t = sim.get_state(0, out=(oc, obf))
+        torch.cuda.synchronize()
+        assert t == 0.5
+        for a, b in zip(oc + obf, dc + db):
+            assert torch.equal(a, b)
+
+
+def test_periodic_face_mismatch_rejected():
+    import torch
+    wl = W.random_smooth(n=(8, 8, 8), seed=12)
+    spec, st = wl.boxes[0], wl.states[0]
+    bad = [b.copy() for b in st.bface]
+    bad[1][:, -1, :] += 1e-3
+    with mhd.Sim([spec]) as sim:
+        with pytest.raises(mhd.MhdError) as ei:
+            sim.set_state(0, st.cons, bad)
+        assert ei.value.code == mhd.MHD_E_INVAL
+        with pytest.raises(mhd.MhdError) as ei:
+            sim.set_state(0, [torch.from_numpy(a).cuda() for a in st.cons],
+                          [torch.from_numpy(a).cuda() for a in bad])
+        assert ei.value.code == mhd.MHD_E_INVAL
+        with pytest.raises(mhd.MhdError) as ei:
+            sim.step(1)
+        assert ei.value.code == mhd.MHD_E_STATE
+
+
+def test_nonphysical_state_reported():
+    wl = W.random_smooth(n=(8, 8, 8), seed=13)
+    spec, st = wl.boxes[0], wl.states[0]
+    cons = [c.copy() for c in st.cons]
+    cons[0][3, 3, 3] = -1.0
+    with mhd.Sim([spec]) as sim:
+        sim.set_state(0, cons, st.bface)
+        sim.step(1)
+        with pytest.warns(UserWarning):
+            sim.get_state(0)
+        assert sim.nonphysical
+        assert sim.counters(0)["bad"] > 0
+
+
+# ---------------------------------------------------------------- mixed
+
+@pytest.mark.parametrize("flags", [0, mhd.MHD_F_GRAPH])
+def test_orszag_tang_2d_mixed(flags):
+    wl = W.orszag_tang_2d(n=128, steps=50)
+    spec = wl.boxes[0]
+    g = gpu_run(wl, 50, precision=mhd.MHD_MIXED, flags=flags)[0]
+    o = oracle_run(spec, wl.states[0], 50)
+    gp, gb = pressure_bmag(spec, g[0], g[1])
+    op, obm = pressure_bmag(spec, o[0], o[1])
+    errs = {"rho": rel_l1(g[0][0], o[0][0]), "p": rel_l1(gp, op), "|B|": rel_l1(gb, obm)}
+    print("OT2D mixed rel L1:", errs)
+    for k, e in errs.items():
+        assert e <= TOLMIX, (k, e)
+    assert divb_norm(spec, g[1])[0] <= 1e-12
+
+
+def test_random_3d_mixed():
+    wl = W.random_smooth(n=(32, 24, 20), seed=21)
+    spec = wl.boxes[0]
+    g = gpu_run(wl, 10, precision=mhd.MHD_MIXED)[0]
+    o = oracle_run(spec, wl.states[0], 10)
+    gp, gb = pressure_bmag(spec, g[0], g[1])
+    op, obm = pressure_bmag(spec, o[0], o[1])
+    for name, a, b in (("rho", g[0][0], o[0][0]), ("p", gp, op), ("|B|", gb, obm)):
+        assert rel_l1(a, b) <= TOLMIX, name
+    assert divb_norm(spec, g[1])[0] <= 1e-12
+    # conserved totals are accumulated in FP64 in both paths
+    for q in range(5):
+        s0 = math.fsum(wl.states[0].cons[q].ravel())
+        s1 = math.fsum(g[0][q].ravel())
+        assert abs(s1 - s0) <= 1e-12 * math.fsum(np.abs(wl.states[0].cons[q]).ravel())
+
+
+# ---------------------------------------------------------------- full size
+
+def _sub_box(spec, st, centre, r):
+    """(2r+1)^3 neighbourhood of a cell, periodic wrap, as an oracle box with
+    outflow walls; only the centre is exact after one step."""
+    n = 2 * r + 1
+    idx = [np.arange(centre[d] - r, centre[d] + r + 1) % spec.n[d] for d in range(3)]
+    fidx = [np.arange(centre[d] - r, centre[d] + r + 2) % spec.n[d] for d in range(3)]
+    cons = [np.ascontiguousarray(c[np.ix_(idx[2], idx[1], idx[0])]) for c in st.cons]
+    bface = [
+        np.ascontiguousarray(st.bface[0][np.ix_(idx[2], idx[1], fidx[0])]),
+        np.ascontiguousarray(st.bface[1][np.ix_(idx[2], fidx[1], idx[0])]),
+        np.ascontiguousarray(st.bface[2][np.ix_(fidx[2], idx[1], idx[0])]),
+    ]
+    dx = spec.dx
+    sub = W.BoxSpec((n, n, n), lo=(0.0, 0.0, 0.0), hi=tuple(n * dx[d] for d in range(3)),
+                    bc=(W.OUTFLOW,) * 3, gamma=spec.gamma, cfl=spec.cfl)
+    return sub, cons, bface
+
+
+def test_blast_256_full_size_sampled():
+    """The benchmark workload at full size in the benchmark's launch
+    configuration (graph replay): one step on the GPU; the oracle recomputes
+    the time step over the whole grid and the step of sampled cells on
+    periodic neighbourhoods of radius 8 (the update of a cell depends on
+    cells within 6)."""
+    wl = W.blast_3d(n=256)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt_gpu, _ = sim.dt(0)
+        sim.step(1)
+        cons, bface, t = sim.get_state(0)
+    ob = O.OracleBox(spec)
+    ob.set_state(st.cons, st.bface)
+    assert dt_gpu == ob.dt()
+    assert t == dt_gpu
+    del ob
+    rng = np.random.default_rng(5)
+    centres = [tuple(int(v) for v in rng.integers(0, 256, size=3)) for _ in range(4)]
+    centres += [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25)]
+    r = 8
+    for c in centres:
+        sub, sc, sb = _sub_box(spec, st, c, r)
+        ob = O.OracleBox(sub)
+        ob.set_state(sc, sb)
+        ob.step_fixed_dt(dt_gpu)
+        oc, obf, _ = ob.get_state()
+        i, j, k = c
+        for q in range(5):
+            a, b = cons[q][k, j, i], oc[q][r, r, r]
+            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, q, a, b)
+        for d, (a, b) in enumerate([(bface[0][k, j, i], obf[0][r, r, r]),
+                                    (bface[1][k, j, i], obf[1][r, r, r]),
+                                    (bface[2][k, j, i], obf[2][r, r, r])]):
+            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, "B", d, a, b)
