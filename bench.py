@@ -42,8 +42,8 @@ BYTES_FP64 = {
 BYTES_MIXED = {
     "lambda": (64, 64),
     "sweep_x": (108, 108),
-    "sweep_y": (116, 116),
-    "sweep_z": (136, 176),
+    "sweep_y": (128, 128),
+    "sweep_z": (156, 196),
     "ct_edge": (60, 60),
     "ct_face": (60, 84),
 }

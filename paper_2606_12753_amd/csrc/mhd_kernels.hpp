@@ -31,8 +31,9 @@
 // be smaller than the tile count (persistent grid-stride loop).
 //
 // The arithmetic type `real` is double (FP64 path) or float (mixed path:
-// FP32 reconstruction, Riemann solver, EMFs and residual; the state, the
-// primitive recovery, the RK accumulation and the time step stay FP64).  In
+// FP32 reconstruction, Riemann solver, face fluxes and EMFs; the state, the
+// primitive recovery, the flux differences and residual, the RK
+// accumulation, the face-field curl and the time step stay FP64).  In
 // FP64 every operation is written in the order of the method's defining
 // formulas and the library is built without FMA contraction, so that the
 // result does not depend on tiling or launch shape.
@@ -62,7 +63,9 @@ struct Box {
   void* FX[kNQ];      // hydro flux on x faces
   void* EF[3][2];     // EMF (E_t1, E_t2) on the faces normal to each axis
   void* MF[3];        // mass flux for the CT upwinding, per face direction
-  void* R[kNQ];       // cell residual
+  double* R[kNQ];     // cell residual (FP64 in both paths: the flux
+                      // differences telescope exactly, so the update
+                      // conserves to FP64 rounding)
   void* ED[3];        // corner EMF along each axis
   double* lam;        // per-tile max CFL rate
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
@@ -677,23 +680,22 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
       const size_t c = cidx(b, ci, cj, ck);
       const double dxD = b.dx[D];
       if (D == 1) {
-        real r[kNQ];
         const size_t f0 = fidx(b, 0, ci, cj, ck);
         const size_t f1 = fidx(b, 0, face_up(ci, b.n[0], b.per[0]), cj, ck);
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
-          r[q] = (real)0;
+          double r = 0.0;
           if (b.act[0])
-            r[q] = r[q] - dv(ld<real>(b.FX[q], f1) - ld<real>(b.FX[q], f0), (real)b.dx[0]);
-          r[q] = r[q] - dv(fl[q] - fprev[q], (real)dxD);
-          st<real>(b.R[q], c, r[q]);
+            r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) / b.dx[0];
+          r = r - ((double)fl[q] - (double)fprev[q]) / dxD;
+          b.R[q][c] = r;
         }
       } else {
         const double dt = b.scal[0];
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
-          real r = ld<real>(b.R[q], c);
-          r = r - dv(fl[q] - fprev[q], (real)dxD);
+          double r = b.R[q][c];
+          r = r - ((double)fl[q] - (double)fprev[q]) / dxD;
           if (s == 0) {
             b.U[1][q][c] = b.U[0][q][c] + dt * (double)r;
           } else {
@@ -738,15 +740,16 @@ __device__ __forceinline__ void inactive_column(const Box& b, int s, int i, int 
     const size_t f1 = fidx(b, 0, face_up(ci, b.n[0], b.per[0]), cj, ck);
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
-      real r = (real)0;
-      if (b.act[0]) r = r - dv(ld<real>(b.FX[q], f1) - ld<real>(b.FX[q], f0), (real)b.dx[0]);
-      st<real>(b.R[q], c, r);
+      double r = 0.0;
+      if (b.act[0])
+        r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) / b.dx[0];
+      b.R[q][c] = r;
     }
   } else {
     const double dt = b.scal[0];
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
-      real r = ld<real>(b.R[q], c);
+      double r = b.R[q][c];
       if (s == 0)
         b.U[1][q][c] = b.U[0][q][c] + dt * (double)r;
       else
