@@ -61,6 +61,10 @@ extern "C" {
 #define MHD_F_PERSISTENT 2u /* persistent-grid launches over the tile table */
 #define MHD_F_TIMING 4u     /* time every kernel launch with HIP events on the
                                context stream (serialises steps; no graph) */
+#define MHD_F_AUTOTUNE 8u   /* before the first step, time the launch variants
+                               on the context's own boxes and keep the fastest
+                               (the state is saved and restored around the
+                               trials; needs workspace for one state copy) */
 
 /* kernel kinds reported by mhd_kernel_times */
 #define MHD_K_LAMBDA 0   /* CFL rate max-reduction, per tile */
@@ -140,6 +144,12 @@ int mhd_counters(mhd_ctx *ctx, int32_t box, int64_t counters[3]);
  * after reading).  Waits for the stream.  MHD_E_STATE without the flag. */
 int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
                      int64_t launches[MHD_NKERNELS], int32_t reset);
+
+/* The launch variant in use: [0] min waves per SIMD of the x sweep's
+ * register budget (1 = unconstrained, 3, 4), [1] the same for the y/z
+ * marches, [2] march segment length (cells), [3] persistent grid (0/1).
+ * The variants differ only in scheduling: FP64 results are identical. */
+int mhd_tuning(mhd_ctx *ctx, int32_t variant[4]);
 
 /* Frees the context and every buffer the library allocated (a caller
  * workspace is left alone).  NULL is a no-op. */

@@ -37,6 +37,13 @@
  *   cell's cell-centred state and the tangential faces; the CFL rate of a cell
  *   is the max over active axes of (|v_d| + c_f,d)/dx_d.
  *
+ * Floating-point evaluation: a quotient that shares its denominator with
+ * others is formed as one reciprocal and products (1/rho for the velocities
+ * and the fast speed, 1/(gamma-1), 1/dx, and the common denominators of the
+ * HLLD contact speed, star states and double-star averages), in the same
+ * order as the GPU library, so that FP64 results can be compared bit for
+ * bit.
+ *
  * Parity pins live in tests/ (consistency, exact contact and rotational
  * discontinuities, conservation, div B, uniform state, symmetry, second-order
  * convergence on the circularly polarised Alfven wave).
@@ -58,7 +65,7 @@ struct orc_box {
   int n[3];
   int bc[3];
   int active[3];
-  double dx[3];
+  double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
   size_t np;           /* elements per padded array */
@@ -100,9 +107,10 @@ double orc_minmod(double a, double b) {
 int orc_cons_to_prim(const double u[5], const double bc[3], double gamma,
                      double pfloor, double w[8]) {
   double rho = u[0];
-  double vx = u[1] / rho;
-  double vy = u[2] / rho;
-  double vz = u[3] / rho;
+  double ir = 1.0 / rho;
+  double vx = u[1] * ir;
+  double vy = u[2] * ir;
+  double vz = u[3] * ir;
   double ek = 0.5 * rho * (vx * vx + vy * vy + vz * vz);
   double em = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
   double p = (gamma - 1.0) * (u[4] - ek - em);
@@ -139,9 +147,10 @@ void orc_plm_face(double qm2, double qm1, double q0, double qp1, double *ql,
 /* fast magnetosonic speed along the normal of (bn, bt1, bt2) */
 double orc_fast_speed(double rho, double p, double bn, double bt1, double bt2,
                       double gamma) {
-  double a2 = gamma * p / rho;
-  double b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / rho;
-  double bn2 = bn * bn / rho;
+  double ir = 1.0 / rho;
+  double a2 = gamma * p * ir;
+  double b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * ir;
+  double bn2 = bn * bn * ir;
   double s = a2 + b2;
   double disc = s * s - 4.0 * a2 * bn2;
   if (disc < 0.0) disc = 0.0;
@@ -156,7 +165,7 @@ void orc_phys_flux(const double w[7], double bn, double gamma, double f[7],
   double bsq = bn * bn + b1 * b1 + b2 * b2;
   double pt = p + 0.5 * bsq;
   double vb = vn * bn + vt1 * b1 + vt2 * b2;
-  double en = p / (gamma - 1.0) + 0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) +
+  double en = p * (1.0 / (gamma - 1.0)) + 0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) +
               0.5 * bsq;
   u[0] = rho;
   u[1] = rho * vn;
@@ -190,8 +199,9 @@ static void hll_with(const double uL[7], const double fL[7], const double uR[7],
     for (c = 0; c < 7; c++) f[c] = fR[c];
     return;
   }
+  double isd = 1.0 / (sr - sl);
   for (c = 0; c < 7; c++)
-    f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) / (sr - sl);
+    f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;
 }
 
 static void wave_speeds(const double wl[7], const double wr[7], double bn,
@@ -227,7 +237,8 @@ static void star_side(const double w[7], const double u[7], double pt,
                       double sa, double sm, double pts, double bn, star_t *s) {
   double sd = sa - w[1];
   double sms = sa - sm;
-  double rs = w[0] * sd / sms;
+  double isms = 1.0 / sms;
+  double rs = w[0] * sd * isms;
   double dd = w[0] * sd * sms - bn * bn;
   double vt1s, vt2s, bt1s, bt2s;
   if (fabs(dd) <= EPS_DEG * pts) {
@@ -237,8 +248,9 @@ static void star_side(const double w[7], const double u[7], double pt,
     bt1s = w[5];
     bt2s = w[6];
   } else {
-    double cv = bn * (sm - w[1]) / dd;
-    double cb = (w[0] * sd * sd - bn * bn) / dd;
+    double idd = 1.0 / dd;
+    double cv = bn * (sm - w[1]) * idd;
+    double cb = (w[0] * sd * sd - bn * bn) * idd;
     vt1s = w[2] - w[5] * cv;
     vt2s = w[3] - w[6] * cv;
     bt1s = w[5] * cb;
@@ -246,7 +258,7 @@ static void star_side(const double w[7], const double u[7], double pt,
   }
   double vb = w[1] * bn + w[2] * w[5] + w[3] * w[6];
   double vbs = sm * bn + vt1s * bt1s + vt2s * bt2s;
-  double ens = (sd * u[4] - pt * w[1] + pts * sm + bn * (vb - vbs)) / sms;
+  double ens = (sd * u[4] - pt * w[1] + pts * sm + bn * (vb - vbs)) * isms;
   s->rho = rs;
   s->vt1 = vt1s;
   s->vt2 = vt2s;
@@ -326,12 +338,12 @@ static int riemann_flux(const double wl[7], const double wr[7], double bn,
   double ptr = total_pressure(wr, bn);
   double sdl = sl - wl[1];
   double sdr = sr - wr[1];
-  double den = sdr * wr[0] - sdl * wl[0];
+  double iden = 1.0 / (sdr * wr[0] - sdl * wl[0]);
   /* contact speed and star total pressure */
-  double sm = (sdr * wr[0] * wr[1] - sdl * wl[0] * wl[1] - ptr + ptl) / den;
+  double sm = (sdr * wr[0] * wr[1] - sdl * wl[0] * wl[1] - ptr + ptl) * iden;
   double pts = (sdr * wr[0] * ptl - sdl * wl[0] * ptr +
-                wl[0] * wr[0] * sdr * sdl * (wr[1] - wl[1])) /
-               den;
+                wl[0] * wr[0] * sdr * sdl * (wr[1] - wl[1])) *
+               iden;
   int ok = (sl < sm) && (sm < sr) && (pts > 0.0);
   double fo[7];
   if (ok) {
@@ -353,11 +365,11 @@ static int riemann_flux(const double wl[7], const double wr[7], double bn,
         double ssl = sm - fabs(bn) / sql;
         double ssr = sm + fabs(bn) / sqr;
         double sgn = bn > 0.0 ? 1.0 : -1.0;
-        double ssum = sql + sqr;
-        double vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) / ssum;
-        double vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) / ssum;
-        double bt1ss = (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) / ssum;
-        double bt2ss = (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) / ssum;
+        double iss = 1.0 / (sql + sqr);
+        double vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) * iss;
+        double vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) * iss;
+        double bt1ss = (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) * iss;
+        double bt2ss = (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) * iss;
         double vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
         if (sm > 0.0) {
           double fs[7], uss[7];
@@ -480,6 +492,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->bc[d] = bc[d];
     b->active[d] = n[d] > 1;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
+    b->idx[d] = 1.0 / b->dx[d];
   }
   b->gamma = gamma;
   b->cfl = cfl;
@@ -798,7 +811,7 @@ static void stage_operator(orc_box *b) {
           double r = 0.0;
           for (d = 0; d < 3; d++) {
             if (!b->active[d]) continue;
-            r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) / b->dx[d];
+            r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];
           }
           b->R[q][c] = r;
         }
@@ -819,8 +832,8 @@ static void stage_operator(orc_box *b) {
           pf[f] += 1;
           size_t c0 = IXp(b, pos);
           double t1 = 0.0, t2 = 0.0;
-          if (b->active[e]) t1 = (b->ED[f][IXp(b, pe)] - b->ED[f][c0]) / b->dx[e];
-          if (b->active[f]) t2 = (b->ED[e][IXp(b, pf)] - b->ED[e][c0]) / b->dx[f];
+          if (b->active[e]) t1 = (b->ED[f][IXp(b, pe)] - b->ED[f][c0]) * b->idx[e];
+          if (b->active[f]) t2 = (b->ED[e][IXp(b, pf)] - b->ED[e][c0]) * b->idx[f];
           b->RB[d][c0] = -(t1 - t2);
         }
   }
@@ -843,7 +856,7 @@ double orc_dt(orc_box *b) {
           if (!b->active[d]) continue;
           int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
           double cf = orc_fast_speed(w[0], w[4], w[5 + d], w[5 + t1], w[5 + t2], b->gamma);
-          double l = (fabs(w[1 + d]) + cf) / b->dx[d];
+          double l = (fabs(w[1 + d]) + cf) * b->idx[d];
           if (l > lmax) lmax = l;
         }
       }

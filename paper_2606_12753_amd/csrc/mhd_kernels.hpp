@@ -20,10 +20,11 @@
 //     primitive recovery per cell) and computes one x face per lane;
 //   * the y and z sweeps march each lane along its column: a register window
 //     of four cells slides along the strided axis, so the strided access
-//     never reaches HBM as strided; each new cell is one coalesced row load.
+//     never reaches HBM as strided; each new cell is one coalesced row load,
+//     issued one face ahead of its use.
 // Periodic axes wrap cell indices and store n faces per axis (face n is face
 // 0); outflow axes clamp cell indices (ghost = copy of the boundary cell) and
-// store n+1 faces.
+// store n+1 faces.  All offsets are 32-bit (a box holds at most 2^30 cells).
 //
 // Every kernel takes a tile table: tiles of all boxes of an ensemble are
 // numbered consecutively and a workgroup finds its box by a binary search of
@@ -55,8 +56,8 @@ struct Box {
   int nf[3];     // faces along each axis normal: n (periodic) or n+1 (outflow)
   int per[3];    // periodic axis
   int act[3];    // active axis (n > 1)
-  double dx[3];
-  double gamma, cfl, pfloor;
+  double dx[3], idx[3];  // cell size and its reciprocal
+  double gamma, igm1, cfl, pfloor;  // igm1 = 1/(gamma-1)
   double* U[2][kNQ];  // conserved state: [0] start of step, [1] stage state
   double* B[2][3];    // face field, same two copies
   void* Ec[3];        // cell EMF  E = -v x B
@@ -67,7 +68,7 @@ struct Box {
                       // differences telescope exactly, so the update
                       // conserves to FP64 rounding)
   void* ED[3];        // corner EMF along each axis
-  double* lam;        // per-tile max CFL rate
+  double* lam;        // per-tile max CFL rate (length: max(x tiles, cell tiles))
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
   int xw, xr, xseg;   // x sweep: faces per segment, rows per tile, segments/row
@@ -85,6 +86,7 @@ struct Launch {
   int nboxes;
   int ntiles;       // tiles of this kind over all boxes
   int stage;        // 0: read state 0 (stage 1); 1: read state 1 (stage 2)
+  int lam;          // x sweep: also reduce the CFL rate of the owned cells
 };
 
 // ---------------------------------------------------------------- helpers
@@ -98,13 +100,9 @@ __device__ __forceinline__ int find_box(const int* base, int nb, int t) {
   return lo;
 }
 
-// cell index along an axis for a (possibly ghost) position
+// cell index along an axis for a position at most n outside the box
 __device__ __forceinline__ int map_cell(int i, int n, int per) {
-  if (per) {
-    while (i < 0) i += n;
-    while (i >= n) i -= n;
-    return i;
-  }
+  if (per) return i < 0 ? i + n : (i >= n ? i - n : i);
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
@@ -114,38 +112,43 @@ __device__ __forceinline__ int face_up(int i, int n, int per) {
   return (per && f == n) ? 0 : f;
 }
 
-__device__ __forceinline__ size_t cidx(const Box& b, int i, int j, int k) {
-  return ((size_t)k * b.n[1] + j) * b.n[0] + i;
+__device__ __forceinline__ int cidx(const Box& b, int i, int j, int k) {
+  return (k * b.n[1] + j) * b.n[0] + i;
 }
 
 // element of the face array normal to axis d
-__device__ __forceinline__ size_t fidx(const Box& b, int d, int i, int j, int k) {
+__device__ __forceinline__ int fidx(const Box& b, int d, int i, int j, int k) {
   int ex = d == 0 ? b.nf[0] : b.n[0];
   int ey = d == 1 ? b.nf[1] : b.n[1];
-  return ((size_t)k * ey + j) * ex + i;
+  return (k * ey + j) * ex + i;
 }
 
 // element of the corner-EMF array along axis c: face extents on the two
 // other axes, cell extent along c
-__device__ __forceinline__ size_t eidx(const Box& b, int c, int i, int j, int k) {
+__device__ __forceinline__ int eidx(const Box& b, int c, int i, int j, int k) {
   int ex = c == 0 ? b.n[0] : b.nf[0];
   int ey = c == 1 ? b.n[1] : b.nf[1];
-  return ((size_t)k * ey + j) * ex + i;
+  return (k * ey + j) * ex + i;
 }
 
+// element access through the global address space (the pointers in Box are
+// generic; naming the address space gives global_load / global_store rather
+// than flat accesses)
 template <typename T>
-__device__ __forceinline__ T ld(const void* p, size_t i) {
-  return static_cast<const T*>(p)[i];
+__device__ __forceinline__ T ld(const void* p, int i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
 }
 template <typename T>
-__device__ __forceinline__ void st(void* p, size_t i, T v) {
-  static_cast<T*>(p)[i] = v;
+__device__ __forceinline__ void st(void* p, int i, T v) {
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
 }
 
-// division and square root: IEEE in FP64; hardware reciprocal / square root
-// (about 1 ulp) in the FP32 work of the mixed path
-__device__ __forceinline__ double dv(double a, double b) { return a / b; }
-__device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// reciprocal and square root: IEEE in FP64; hardware reciprocal / square
+// root (about 1 ulp) in the FP32 work of the mixed path.  A quotient that
+// shares its denominator with others is formed as one reciprocal and
+// products (the oracle evaluates the same expressions in the same order).
+__device__ __forceinline__ double rcp(double b) { return 1.0 / b; }
+__device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double ab(double a) { return __builtin_fabs(a); }
@@ -177,9 +180,10 @@ struct PrimD {
 __device__ __forceinline__ int cons_to_prim(double u0, double u1, double u2, double u3,
                                             double u4, double bx, double by, double bz,
                                             double gamma, double pfloor, PrimD& w) {
-  double vx = u1 / u0;
-  double vy = u2 / u0;
-  double vz = u3 / u0;
+  double ir = 1.0 / u0;
+  double vx = u1 * ir;
+  double vy = u2 * ir;
+  double vz = u3 * ir;
   double ek = 0.5 * u0 * (vx * vx + vy * vy + vz * vz);
   double em = 0.5 * (bx * bx + by * by + bz * bz);
   double p = (gamma - 1.0) * (u4 - ek - em);
@@ -195,17 +199,53 @@ __device__ __forceinline__ int cons_to_prim(double u0, double u1, double u2, dou
   return fl;
 }
 
+// Raw data of one cell: conserved variables and its six faces.
+struct Raw {
+  double u[kNQ];
+  double bf[6];  // bx lo/hi, by lo/hi, bz lo/hi
+};
+
+// Offsets of mapped cell (i, j, k) and its six faces.
+struct Addr {
+  int c, bx0, bx1, by0, by1, bz0, bz1;
+};
+
+__device__ __forceinline__ Addr addr_of(const Box& b, int i, int j, int k) {
+  Addr a;
+  const int nx = b.n[0], ny = b.n[1];
+  a.c = (k * ny + j) * nx + i;
+  a.bx0 = (k * ny + j) * b.nf[0] + i;
+  a.bx1 = (b.per[0] && i + 1 == nx) ? a.bx0 - i : a.bx0 + 1;
+  a.by0 = (k * b.nf[1] + j) * nx + i;
+  a.by1 = (b.per[1] && j + 1 == ny) ? a.by0 - j * nx : a.by0 + nx;
+  a.bz0 = a.c;
+  a.bz1 = (b.per[2] && k + 1 == b.n[2]) ? a.c - k * nx * ny : a.c + nx * ny;
+  return a;
+}
+
+__device__ __forceinline__ Raw load_raw(const Box& b, int s, const Addr& a) {
+  Raw r;
+#pragma unroll
+  for (int q = 0; q < kNQ; q++) r.u[q] = ld<double>(b.U[s][q], a.c);
+  r.bf[0] = ld<double>(b.B[s][0], a.bx0);
+  r.bf[1] = ld<double>(b.B[s][0], a.bx1);
+  r.bf[2] = ld<double>(b.B[s][1], a.by0);
+  r.bf[3] = ld<double>(b.B[s][1], a.by1);
+  r.bf[4] = ld<double>(b.B[s][2], a.bz0);
+  r.bf[5] = ld<double>(b.B[s][2], a.bz1);
+  return r;
+}
+
+__device__ __forceinline__ int raw_to_prim(const Box& b, const Raw& r, PrimD& w) {
+  double bx = 0.5 * (r.bf[0] + r.bf[1]);
+  double by = 0.5 * (r.bf[2] + r.bf[3]);
+  double bz = 0.5 * (r.bf[4] + r.bf[5]);
+  return cons_to_prim(r.u[0], r.u[1], r.u[2], r.u[3], r.u[4], bx, by, bz, b.gamma, b.pfloor, w);
+}
+
 // primitives of mapped cell (i, j, k) of state s, with the face-averaged field
 __device__ __forceinline__ int load_prim(const Box& b, int s, int i, int j, int k, PrimD& w) {
-  const size_t c = cidx(b, i, j, k);
-  const double* Bx = b.B[s][0];
-  const double* By = b.B[s][1];
-  const double* Bz = b.B[s][2];
-  double bx = 0.5 * (Bx[fidx(b, 0, i, j, k)] + Bx[fidx(b, 0, face_up(i, b.n[0], b.per[0]), j, k)]);
-  double by = 0.5 * (By[fidx(b, 1, i, j, k)] + By[fidx(b, 1, i, face_up(j, b.n[1], b.per[1]), k)]);
-  double bz = 0.5 * (Bz[fidx(b, 2, i, j, k)] + Bz[fidx(b, 2, i, j, face_up(k, b.n[2], b.per[2]))]);
-  return cons_to_prim(b.U[s][0][c], b.U[s][1][c], b.U[s][2][c], b.U[s][3][c], b.U[s][4][c],
-                      bx, by, bz, b.gamma, b.pfloor, w);
+  return raw_to_prim(b, load_raw(b, s, addr_of(b, i, j, k)), w);
 }
 
 // face-frame state (rho, v_n, v_t1, v_t2, p, B_t1, B_t2), (n,t1,t2) cyclic
@@ -252,26 +292,35 @@ __device__ __forceinline__ void plm(real qm2, real qm1, real q0, real qp1, real&
 template <typename real>
 __device__ __forceinline__ real fast_speed(real rho, real p, real bn, real bt1, real bt2,
                                            real gamma) {
-  real a2 = dv(gamma * p, rho);
-  real b2 = dv(bn * bn + bt1 * bt1 + bt2 * bt2, rho);
-  real bn2 = dv(bn * bn, rho);
+  real ir = rcp(rho);
+  real a2 = gamma * p * ir;
+  real b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * ir;
+  real bn2 = bn * bn * ir;
   real s = a2 + b2;
   real disc = s * s - (real)4 * a2 * bn2;
   if (disc < (real)0) disc = (real)0;
   return sq((real)0.5 * (s + sq(disc)));
 }
 
+// total energy of a face-frame state (igm1 = 1/(gamma-1))
+template <typename real>
+__device__ __forceinline__ real energy(const St7<real>& w, real bn, real igm1) {
+  real bsq = bn * bn + w.v[5] * w.v[5] + w.v[6] * w.v[6];
+  return w.v[4] * igm1 +
+         (real)0.5 * w.v[0] * (w.v[1] * w.v[1] + w.v[2] * w.v[2] + w.v[3] * w.v[3]) +
+         (real)0.5 * bsq;
+}
+
 // physical flux F and conserved vector U of a face-frame state
 template <typename real>
-__device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real gamma, real* f,
+__device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real igm1, real* f,
                                           real* u) {
   const real rho = w.v[0], vn = w.v[1], vt1 = w.v[2], vt2 = w.v[3], p = w.v[4];
   const real b1 = w.v[5], b2 = w.v[6];
   real bsq = bn * bn + b1 * b1 + b2 * b2;
   real pt = p + (real)0.5 * bsq;
   real vb = vn * bn + vt1 * b1 + vt2 * b2;
-  real en = dv(p, gamma - (real)1) + (real)0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) +
-            (real)0.5 * bsq;
+  real en = p * igm1 + (real)0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) + (real)0.5 * bsq;
   u[0] = rho;
   u[1] = rho * vn;
   u[2] = rho * vt1;
@@ -291,16 +340,17 @@ __device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real gamm
 template <typename real>
 struct Star {
   real rho, vt1, vt2, bt1, bt2, en, vb;
-  real u[7];
 };
 
-// HLLD single-star state of one side
+// HLLD single-star state of one side: w face-frame state, en its total
+// energy, pt its total pressure, sa the outer wave speed of the side
 template <typename real>
-__device__ __forceinline__ void star_side(const St7<real>& w, const real* u, real pt, real sa,
-                                          real sm, real pts, real bn, Star<real>& s) {
+__device__ __forceinline__ Star<real> star_side(const St7<real>& w, real en, real pt, real sa,
+                                                real sm, real pts, real bn) {
   real sd = sa - w.v[1];
   real sms = sa - sm;
-  real rs = dv(w.v[0] * sd, sms);
+  real isms = rcp(sms);
+  real rs = w.v[0] * sd * isms;
   real dd = w.v[0] * sd * sms - bn * bn;
   real vt1s, vt2s, bt1s, bt2s;
   if (ab(dd) <= Eps<real>::deg * pts) {
@@ -309,8 +359,9 @@ __device__ __forceinline__ void star_side(const St7<real>& w, const real* u, rea
     bt1s = w.v[5];
     bt2s = w.v[6];
   } else {
-    real cv = dv(bn * (sm - w.v[1]), dd);
-    real cb = dv(w.v[0] * sd * sd - bn * bn, dd);
+    real idd = rcp(dd);
+    real cv = bn * (sm - w.v[1]) * idd;
+    real cb = (w.v[0] * sd * sd - bn * bn) * idd;
     vt1s = w.v[2] - w.v[5] * cv;
     vt2s = w.v[3] - w.v[6] * cv;
     bt1s = w.v[5] * cb;
@@ -318,21 +369,15 @@ __device__ __forceinline__ void star_side(const St7<real>& w, const real* u, rea
   }
   real vb = w.v[1] * bn + w.v[2] * w.v[5] + w.v[3] * w.v[6];
   real vbs = sm * bn + vt1s * bt1s + vt2s * bt2s;
-  real ens = dv(sd * u[4] - pt * w.v[1] + pts * sm + bn * (vb - vbs), sms);
+  Star<real> s;
+  s.en = (sd * en - pt * w.v[1] + pts * sm + bn * (vb - vbs)) * isms;
   s.rho = rs;
   s.vt1 = vt1s;
   s.vt2 = vt2s;
   s.bt1 = bt1s;
   s.bt2 = bt2s;
-  s.en = ens;
   s.vb = vbs;
-  s.u[0] = rs;
-  s.u[1] = rs * sm;
-  s.u[2] = rs * vt1s;
-  s.u[3] = rs * vt2s;
-  s.u[4] = ens;
-  s.u[5] = bt1s;
-  s.u[6] = bt2s;
+  return s;
 }
 
 template <typename real>
@@ -342,16 +387,44 @@ __device__ __forceinline__ real star_pressure(const Star<real>& s, real sm, real
           (real)0.5 * (bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2));
 }
 
+template <typename real>
+__device__ __forceinline__ real sel(bool c, real a, real b) {
+  return c ? a : b;
+}
+
+// HLL flux with outer speeds sl < 0 < sr (or the upwind flux at the edges)
+template <typename real>
+__device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& wr, real bn,
+                                         real igm1, real sl, real sr, real* f) {
+  real uL[7], fL[7], uR[7], fR[7];
+  phys_flux(wl, bn, igm1, fL, uL);
+  phys_flux(wr, bn, igm1, fR, uR);
+  if (sl >= (real)0) {
+#pragma unroll
+    for (int c = 0; c < 7; c++) f[c] = fL[c];
+  } else if (sr <= (real)0) {
+#pragma unroll
+    for (int c = 0; c < 7; c++) f[c] = fR[c];
+  } else {
+    const real isd = rcp(sr - sl);
+#pragma unroll
+    for (int c = 0; c < 7; c++) f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;
+  }
+}
+
 // Riemann flux at one face: HLLD, HLL when the HLLD star states are not
 // physical.  f[7] = (mass, mom n, mom t1, mom t2, energy, B_t1, B_t2); *fm is
 // the mass flux handed to the CT upwinding (zero when zero up to rounding).
 // Returns 1 when HLL was used.
+//
+// The flux of the Riemann fan at x/t = 0 lies on the side of the contact
+// given by sign(S_M): the solver computes both single-star states (both
+// enter the double-star average and the positivity check), then selects the
+// side once and assembles F*, and F** when the rotational wave of that side
+// is left of (right of) x/t = 0, with selects instead of divergent branches.
 template <typename real>
 __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr, real bn,
-                                       real gamma, real* f, real* fm) {
-  real uL[7], fL[7], uR[7], fR[7];
-  phys_flux(wl, bn, gamma, fL, uL);
-  phys_flux(wr, bn, gamma, fR, uR);
+                                       real gamma, real igm1, real* f, real* fm) {
   real cfl = fast_speed(wl.v[0], wl.v[4], bn, wl.v[5], wl.v[6], gamma);
   real cfr = fast_speed(wr.v[0], wr.v[4], bn, wr.v[5], wr.v[6], gamma);
   real cmax = cfl > cfr ? cfl : cfr;
@@ -360,112 +433,105 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
   real sl = umin - cmax;
   real sr = umax + cmax;
   int used = 0;
-  if (sl > (real)0) {
+  if (sl > (real)0 || sr < (real)0) {
+    // supersonic: physical flux of the upwind state
+    St7<real> w;
+    const bool left = sl > (real)0;
 #pragma unroll
-    for (int c = 0; c < 7; c++) f[c] = fL[c];
-  } else if (sr < (real)0) {
-#pragma unroll
-    for (int c = 0; c < 7; c++) f[c] = fR[c];
+    for (int v = 0; v < 7; v++) w.v[v] = sel(left, wl.v[v], wr.v[v]);
+    real u[7];
+    phys_flux(w, bn, igm1, f, u);
   } else {
     real ptl = wl.v[4] + (real)0.5 * (bn * bn + wl.v[5] * wl.v[5] + wl.v[6] * wl.v[6]);
     real ptr = wr.v[4] + (real)0.5 * (bn * bn + wr.v[5] * wr.v[5] + wr.v[6] * wr.v[6]);
     real sdl = sl - wl.v[1];
     real sdr = sr - wr.v[1];
-    real den = sdr * wr.v[0] - sdl * wl.v[0];
-    real sm = dv(sdr * wr.v[0] * wr.v[1] - sdl * wl.v[0] * wl.v[1] - ptr + ptl, den);
-    real pts = dv(sdr * wr.v[0] * ptl - sdl * wl.v[0] * ptr +
-                      wl.v[0] * wr.v[0] * sdr * sdl * (wr.v[1] - wl.v[1]),
-                  den);
+    real iden = rcp(sdr * wr.v[0] - sdl * wl.v[0]);
+    real sm = (sdr * wr.v[0] * wr.v[1] - sdl * wl.v[0] * wl.v[1] - ptr + ptl) * iden;
+    real pts = (sdr * wr.v[0] * ptl - sdl * wl.v[0] * ptr +
+                wl.v[0] * wr.v[0] * sdr * sdl * (wr.v[1] - wl.v[1])) *
+               iden;
     bool ok = (sl < sm) && (sm < sr) && (pts > (real)0);
-    real fo[7];
     if (ok) {
-      Star<real> stl, str;
-      star_side(wl, uL, ptl, sl, sm, pts, bn, stl);
-      star_side(wr, uR, ptr, sr, sm, pts, bn, str);
+      const real enl = energy(wl, bn, igm1);
+      const real enr = energy(wr, bn, igm1);
+      const Star<real> stl = star_side(wl, enl, ptl, sl, sm, pts, bn);
+      const Star<real> str = star_side(wr, enr, ptr, sr, sm, pts, bn);
       if (!(star_pressure(stl, sm, bn, gamma) > (real)0) ||
           !(star_pressure(str, sm, bn, gamma) > (real)0))
         ok = false;
       if (ok) {
+        // side of the contact holding x/t = 0
+        const bool left = sm > (real)0;
+        St7<real> w;
+#pragma unroll
+        for (int v = 0; v < 7; v++) w.v[v] = sel(left, wl.v[v], wr.v[v]);
+        Star<real> sa;
+        sa.rho = sel(left, stl.rho, str.rho);
+        sa.vt1 = sel(left, stl.vt1, str.vt1);
+        sa.vt2 = sel(left, stl.vt2, str.vt2);
+        sa.bt1 = sel(left, stl.bt1, str.bt1);
+        sa.bt2 = sel(left, stl.bt2, str.bt2);
+        sa.en = sel(left, stl.en, str.en);
+        sa.vb = sel(left, stl.vb, str.vb);
+        const real s_out = sel(left, sl, sr);
+        real fa[7], ua[7];
+        phys_flux(w, bn, igm1, fa, ua);
+        real us[7];
+        us[0] = sa.rho;
+        us[1] = sa.rho * sm;
+        us[2] = sa.rho * sa.vt1;
+        us[3] = sa.rho * sa.vt2;
+        us[4] = sa.en;
+        us[5] = sa.bt1;
+        us[6] = sa.bt2;
+        real fs[7];
+#pragma unroll
+        for (int c = 0; c < 7; c++) fs[c] = fa[c] + s_out * (us[c] - ua[c]);
         if ((real)0.5 * bn * bn <= Eps<real>::bsmall * pts) {
-          if (sm > (real)0) {
+          // B_n ~ 0: the rotational waves merge with the contact
 #pragma unroll
-            for (int c = 0; c < 7; c++) fo[c] = fL[c] + sl * (stl.u[c] - uL[c]);
-          } else {
-#pragma unroll
-            for (int c = 0; c < 7; c++) fo[c] = fR[c] + sr * (str.u[c] - uR[c]);
-          }
+          for (int c = 0; c < 7; c++) f[c] = fs[c];
         } else {
           real sql = sq(stl.rho), sqr = sq(str.rho);
-          real ssl = sm - dv(ab(bn), sql);
-          real ssr = sm + dv(ab(bn), sqr);
+          real ssl = sm - ab(bn) * rcp(sql);
+          real ssr = sm + ab(bn) * rcp(sqr);
           real sgn = bn > (real)0 ? (real)1 : (real)-1;
-          real ssum = sql + sqr;
-          real vt1ss = dv(sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn, ssum);
-          real vt2ss = dv(sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn, ssum);
-          real bt1ss = dv(sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn, ssum);
-          real bt2ss = dv(sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn, ssum);
+          real iss = rcp(sql + sqr);
+          real vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) * iss;
+          real vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) * iss;
+          real bt1ss = (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) * iss;
+          real bt2ss = (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) * iss;
           real vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
-          if (sm > (real)0) {
-            real fs[7];
+          // rotational wave of the selected side, and whether x/t = 0 lies
+          // between it and the contact
+          const real s_rot = sel(left, ssl, ssr);
+          const bool inner = left ? !(ssl > (real)0) : !(ssr < (real)0);
+          // E** = E* -+ sqrt(rho*) (v*.B* - v**.B**) sign(B_n)
+          real t = sel(left, sql, sqr) * (sa.vb - vbss) * sgn;
+          t = sel(left, -t, t);
+          real uss[7];
+          uss[0] = sa.rho;
+          uss[1] = sa.rho * sm;
+          uss[2] = sa.rho * vt1ss;
+          uss[3] = sa.rho * vt2ss;
+          uss[4] = sa.en + t;
+          uss[5] = bt1ss;
+          uss[6] = bt2ss;
 #pragma unroll
-            for (int c = 0; c < 7; c++) fs[c] = fL[c] + sl * (stl.u[c] - uL[c]);
-            if (ssl > (real)0) {
-#pragma unroll
-              for (int c = 0; c < 7; c++) fo[c] = fs[c];
-            } else {
-              real uss[7];
-              uss[0] = stl.rho;
-              uss[1] = stl.rho * sm;
-              uss[2] = stl.rho * vt1ss;
-              uss[3] = stl.rho * vt2ss;
-              uss[4] = stl.en - sql * (stl.vb - vbss) * sgn;
-              uss[5] = bt1ss;
-              uss[6] = bt2ss;
-#pragma unroll
-              for (int c = 0; c < 7; c++) fo[c] = fs[c] + ssl * (uss[c] - stl.u[c]);
-            }
-          } else {
-            real fs[7];
-#pragma unroll
-            for (int c = 0; c < 7; c++) fs[c] = fR[c] + sr * (str.u[c] - uR[c]);
-            if (ssr < (real)0) {
-#pragma unroll
-              for (int c = 0; c < 7; c++) fo[c] = fs[c];
-            } else {
-              real uss[7];
-              uss[0] = str.rho;
-              uss[1] = str.rho * sm;
-              uss[2] = str.rho * vt1ss;
-              uss[3] = str.rho * vt2ss;
-              uss[4] = str.en + sqr * (str.vb - vbss) * sgn;
-              uss[5] = bt1ss;
-              uss[6] = bt2ss;
-#pragma unroll
-              for (int c = 0; c < 7; c++) fo[c] = fs[c] + ssr * (uss[c] - str.u[c]);
-            }
+          for (int c = 0; c < 7; c++) {
+            const real fss = fs[c] + s_rot * (uss[c] - us[c]);
+            f[c] = inner ? fss : fs[c];
           }
         }
 #pragma unroll
         for (int c = 0; c < 7; c++)
-          if (!finite(fo[c])) ok = false;
+          if (!finite(f[c])) ok = false;
       }
     }
-    if (ok) {
-#pragma unroll
-      for (int c = 0; c < 7; c++) f[c] = fo[c];
-    } else {
+    if (!ok) {
       used = 1;
-      if (sl >= (real)0) {
-#pragma unroll
-        for (int c = 0; c < 7; c++) f[c] = fL[c];
-      } else if (sr <= (real)0) {
-#pragma unroll
-        for (int c = 0; c < 7; c++) f[c] = fR[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 7; c++)
-          f[c] = dv(sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c]), sr - sl);
-      }
+      hll_flux(wl, wr, bn, igm1, sl, sr, f);
     }
   }
   real thr = Eps<real>::mflux * (wl.v[0] + wr.v[0]) * (ab(sl) + ab(sr));
@@ -487,6 +553,21 @@ __device__ __forceinline__ void count(unsigned long long* c, int fl) {
   if (fl & 2) atomicAdd(&c[2], 1ull);
 }
 
+// CFL rate of a cell: max over active axes of (|v_d| + c_f,d) / dx_d
+__device__ __forceinline__ double cfl_rate(const Box& b, const PrimD& w) {
+  const double v[3] = {w.vx, w.vy, w.vz};
+  const double bc[3] = {w.bx, w.by, w.bz};
+  double l = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    if (!b.act[d]) continue;
+    const double cf = fast_speed(w.r, w.p, bc[d], bc[(d + 1) % 3], bc[(d + 2) % 3], b.gamma);
+    const double x = (__builtin_fabs(v[d]) + cf) * b.idx[d];
+    if (x > l) l = x;
+  }
+  return l;
+}
+
 // upwind choice of the CT average: flux > 0 -> lower side, < 0 -> upper,
 // 0 -> mean
 template <typename real>
@@ -496,13 +577,40 @@ __device__ __forceinline__ real upwind(real m, real lower, real upper) {
   return (real)0.5 * (lower + upper);
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// block-wide max: wavefront butterfly, then across the four wavefronts
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double part[kTPB / 64];
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double m = part[0];
+#pragma unroll
+  for (int w = 1; w < kTPB / 64; w++) m = part[w] > m ? part[w] : m;
+  __syncthreads();
+  return m;
+}
+
 // ---------------------------------------------------------------- kernels
 
 // x sweep: row segments staged in LDS; one x face per lane.  Writes the
 // hydro flux, the face EMFs (E_y, E_z), the CT mass flux and the cell EMF of
-// every owned cell.
-template <typename real>
-__global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
+// every owned cell; with L.lam also the tile's max CFL rate (stage 1, the
+// state at the start of the step).
+// WPE: minimum resident wavefronts per SIMD the register allocation must
+// allow (1 = unconstrained); one of the tunable launch variants.
+template <typename real, int WPE>
+__global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_x(
+    Launch L) {
   __shared__ real sw[7][kLdsCells];
   const int s = L.stage;
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
@@ -524,6 +632,7 @@ __global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
       i0 = seg * b.xw;
       W = min(b.xw, b.nf[0] - i0);
     }
+    double lmax = 0.0;
     if (b.act[0]) {
       const int WL = W + 3;
       const int ncell = R * WL;
@@ -545,11 +654,15 @@ __global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
         sw[5][sidx] = (real)w.by;
         sw[6][sidx] = (real)w.bz;
         if (o >= 2 && o < W + 2 && i >= 0 && i < nx) {
-          const size_t c = cidx(b, i, j, k);
+          const int c = cidx(b, i, j, k);
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
           st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
           st<real>(b.Ec[2], c, (real)(w.vy * w.bx - w.vx * w.by));
           if (fl) count(b.cnt, fl);
+          if (L.lam) {
+            const double l = cfl_rate(b, w);
+            if (l > lmax) lmax = l;
+          }
         }
       }
       __syncthreads();
@@ -567,10 +680,10 @@ __global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
           for (int v = 0; v < 7; v++) q[m].v[v] = sw[v][o + m];
         St7<real> wl, wr;
         plm_face(q[0], q[1], q[2], q[3], wl, wr);
-        const size_t fi = fidx(b, 0, f, j, k);
-        const real bn = (real)b.B[s][0][fi];
+        const int fi = fidx(b, 0, f, j, k);
+        const real bn = (real)ld<double>(b.B[s][0], fi);
         real F[7], fm;
-        const int used = riemann(wl, wr, bn, (real)b.gamma, F, &fm);
+        const int used = riemann(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
         st<real>(b.FX[0], fi, F[0]);
         st<real>(b.FX[1], fi, F[1]);
         st<real>(b.FX[2], fi, F[2]);
@@ -581,7 +694,6 @@ __global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
         st<real>(b.MF[0], fi, fm);
         if (used) atomicAdd(&b.cnt[1], 1ull);
       }
-      __syncthreads();
     } else {
       // inactive x: the face carries the cell's physical flux (no divergence)
       for (int t = threadIdx.x; t < R * W; t += kTPB) {
@@ -595,72 +707,112 @@ __global__ __launch_bounds__(kTPB) void k_sweep_x(Launch L) {
         const int fl = load_prim(b, s, im, j, k, w);
         const double ecy = w.vx * w.bz - w.vz * w.bx;
         const double ecz = w.vy * w.bx - w.vx * w.by;
-        const size_t fi = fidx(b, 0, f, j, k);
+        const int fi = fidx(b, 0, f, j, k);
         st<real>(b.EF[0][0], fi, (real)ecy);
         st<real>(b.EF[0][1], fi, (real)ecz);
-        st<real>(b.MF[0], fi, (real)b.U[s][1][cidx(b, im, j, k)]);
+        st<real>(b.MF[0], fi, (real)ld<double>(b.U[s][1], cidx(b, im, j, k)));
         if (f == 0) {
-          const size_t c = cidx(b, 0, j, k);
+          const int c = cidx(b, 0, j, k);
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
           st<real>(b.Ec[1], c, (real)ecy);
           st<real>(b.Ec[2], c, (real)ecz);
           if (fl) count(b.cnt, fl);
+          if (L.lam) {
+            const double l = cfl_rate(b, w);
+            if (l > lmax) lmax = l;
+          }
         }
       }
+    }
+    if (L.lam) {
+      const double m = block_max(lmax);
+      if (threadIdx.x == 0) b.lam[lt] = m;
+    } else {
+      __syncthreads();  // the next tile reuses the LDS
     }
   }
 }
 
 // Marching sweep along axis D (1 = y, 2 = z).  Each lane owns one column of
-// cells along D (lanes run along x) and slides a four-cell register window
-// down its segment; one Riemann solve per face.  Y: adds the x and y flux
-// divergence and writes the residual.  Z: adds the z divergence to the
-// residual and applies the SSP-RK2 stage combine.
+// cells along D (lanes run along x) and slides a register window (two cells,
+// the limited slope of the older one and the incoming cell) down its
+// segment; one Riemann solve per face; the raw data of the cell two faces
+// ahead is loaded before the current face is solved.  Y: adds the x
+// and y flux divergence and writes the residual.  Z: adds the z divergence
+// to the residual and applies the SSP-RK2 stage combine.
 template <typename real, int D>
 __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr, int j0, int j1) {
   // (i, tr): x index and the index along the remaining axis (z for D=1, y
-  // for D=2); positions along D from j0 to j1 (cells [j0, j1))
+  // for D=2); cells [j0, j1) along D, faces j0..j1
   const int n = b.n[D];
   const int per = b.per[D];
-  auto pos = [&](int a, int& ii, int& jj, int& kk) {
-    ii = i;
-    if (D == 1) { jj = a; kk = tr; } else { jj = tr; kk = a; }
+  auto addr_at = [&](int a) {
+    const int am = map_cell(a, n, per);
+    return D == 1 ? addr_of(b, i, am, tr) : addr_of(b, i, tr, am);
   };
-  St7<real> q0, q1, q2, q3;
+  // window: cells f-1 and f and the limited slope of cell f-1
+  St7<real> q1, q2, q3, dm1;
   {
-    int ii, jj, kk;
     PrimD w;
-    pos(map_cell(j0 - 2, n, per), ii, jj, kk);
-    load_prim(b, s, ii, jj, kk, w);
-    q0 = rotate<real>(w, D);
-    pos(map_cell(j0 - 1, n, per), ii, jj, kk);
-    load_prim(b, s, ii, jj, kk, w);
+    raw_to_prim(b, load_raw(b, s, addr_at(j0 - 2)), w);
+    const St7<real> q0 = rotate<real>(w, D);
+    raw_to_prim(b, load_raw(b, s, addr_at(j0 - 1)), w);
     q1 = rotate<real>(w, D);
-    pos(map_cell(j0, n, per), ii, jj, kk);
-    load_prim(b, s, ii, jj, kk, w);
+    raw_to_prim(b, load_raw(b, s, addr_at(j0)), w);
     q2 = rotate<real>(w, D);
+#pragma unroll
+    for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
   }
+  Raw next = load_raw(b, s, addr_at(j0 + 1));
   real fprev[kNQ];
-  const int lastface = j1;  // faces j0..j1
   const bool extra = (j1 == n) && (b.nf[D] == n + 1);
-  for (int f = j0; f <= lastface; ++f) {
-    int ii, jj, kk;
-    pos(map_cell(f + 1, n, per), ii, jj, kk);
+  // face offsets along D: face f of this column
+  const int fstride = D == 1 ? b.n[0] : b.n[0] * b.n[1];
+  const int fbase = D == 1 ? (tr * b.nf[1]) * b.n[0] + i : tr * b.n[0] + i;
+  const int cstride = fstride;
+  const int cbase = D == 1 ? (tr * b.n[1]) * b.n[0] + i : tr * b.n[0] + i;
+  const double dt = D == 2 ? b.scal[0] : 0.0;
+  for (int f = j0; f <= j1; ++f) {
     PrimD w;
-    load_prim(b, s, ii, jj, kk, w);
+    raw_to_prim(b, next, w);
     q3 = rotate<real>(w, D);
-    St7<real> wl, wr;
-    plm_face(q0, q1, q2, q3, wl, wr);
-    int fi_, fj_, fk_;
-    pos(f, fi_, fj_, fk_);
-    // face index f along D is in [0, n]; periodic face n is face 0
-    if (per && f == n) {
-      if (D == 1) fj_ = 0; else fk_ = 0;
+    if (f < j1) next = load_raw(b, s, addr_at(f + 2));
+    // inputs of the cell update, issued before the solve
+    const int cprev = cbase + (f - 1) * cstride;
+    double racc[kNQ];
+    double u0v[kNQ], u1v[kNQ];
+    if (f > j0) {
+      if (D == 1) {
+        const int f0 = (tr * b.n[1] + (f - 1)) * b.nf[0] + i;
+        const int f1 = (b.per[0] && i + 1 == b.n[0]) ? f0 - i : f0 + 1;
+#pragma unroll
+        for (int q = 0; q < kNQ; q++) {
+          double r = 0.0;
+          if (b.act[0])
+            r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) * b.idx[0];
+          racc[q] = r;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kNQ; q++) {
+          racc[q] = ld<double>(b.R[q], cprev);
+          u0v[q] = ld<double>(b.U[0][q], cprev);
+          if (s == 1) u1v[q] = ld<double>(b.U[1][q], cprev);
+        }
+      }
     }
-    const size_t fi = fidx(b, D, fi_, fj_, fk_);
-    const real bn = (real)b.B[s][D][fi];
+    St7<real> wl, wr, d0;
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      d0.v[v] = minmod(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
+      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
+      wr.v[v] = q2.v[v] - (real)0.5 * d0.v[v];
+    }
+    // face index f along D is in [0, n]; periodic face n is face 0
+    const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
+    const real bn = (real)ld<double>(b.B[s][D], fi);
     real F[7], fm;
-    const int used = riemann(wl, wr, bn, (real)b.gamma, F, &fm);
+    const int used = riemann(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
     // lab-frame hydro flux: (rho, mx, my, mz, E)
     real fl[kNQ];
     fl[0] = F[0];
@@ -675,40 +827,24 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
     }
     if (f > j0) {
       // cell f-1 is complete
-      int ci, cj, ck;
-      pos(f - 1, ci, cj, ck);
-      const size_t c = cidx(b, ci, cj, ck);
-      const double dxD = b.dx[D];
-      if (D == 1) {
-        const size_t f0 = fidx(b, 0, ci, cj, ck);
-        const size_t f1 = fidx(b, 0, face_up(ci, b.n[0], b.per[0]), cj, ck);
+      const double idxD = b.idx[D];
 #pragma unroll
-        for (int q = 0; q < kNQ; q++) {
-          double r = 0.0;
-          if (b.act[0])
-            r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) / b.dx[0];
-          r = r - ((double)fl[q] - (double)fprev[q]) / dxD;
-          b.R[q][c] = r;
-        }
-      } else {
-        const double dt = b.scal[0];
-#pragma unroll
-        for (int q = 0; q < kNQ; q++) {
-          double r = b.R[q][c];
-          r = r - ((double)fl[q] - (double)fprev[q]) / dxD;
-          if (s == 0) {
-            b.U[1][q][c] = b.U[0][q][c] + dt * (double)r;
-          } else {
-            b.U[0][q][c] = 0.5 * (b.U[0][q][c] + (b.U[1][q][c] + dt * (double)r));
-          }
+      for (int q = 0; q < kNQ; q++) {
+        const double r = racc[q] - ((double)fl[q] - (double)fprev[q]) * idxD;
+        if (D == 1) {
+          st<double>(b.R[q], cprev, r);
+        } else if (s == 0) {
+          st<double>(b.U[1][q], cprev, u0v[q] + dt * r);
+        } else {
+          st<double>(b.U[0][q], cprev, 0.5 * (u0v[q] + (u1v[q] + dt * r)));
         }
       }
     }
 #pragma unroll
     for (int q = 0; q < kNQ; q++) fprev[q] = fl[q];
-    q0 = q1;
     q1 = q2;
     q2 = q3;
+    dm1 = d0;
   }
 }
 
@@ -724,42 +860,44 @@ __device__ __forceinline__ void inactive_column(const Box& b, int s, int i, int 
   for (int f = 0; f < b.nf[D]; ++f) {
     int ii, jj, kk;
     pos(map_cell(f, b.n[D], b.per[D]), ii, jj, kk);
-    const size_t c = cidx(b, ii, jj, kk);
+    const int c = cidx(b, ii, jj, kk);
     int fi_, fj_, fk_;
     pos(f, fi_, fj_, fk_);
-    const size_t fi = fidx(b, D, fi_, fj_, fk_);
+    const int fi = fidx(b, D, fi_, fj_, fk_);
     st<real>(b.EF[D][0], fi, ld<real>(b.Ec[t1], c));
     st<real>(b.EF[D][1], fi, ld<real>(b.Ec[t2], c));
-    st<real>(b.MF[D], fi, (real)b.U[s][1 + D][c]);
+    st<real>(b.MF[D], fi, (real)ld<double>(b.U[s][1 + D], c));
   }
   int ci, cj, ck;
   pos(0, ci, cj, ck);
-  const size_t c = cidx(b, ci, cj, ck);
+  const int c = cidx(b, ci, cj, ck);
   if (D == 1) {
-    const size_t f0 = fidx(b, 0, ci, cj, ck);
-    const size_t f1 = fidx(b, 0, face_up(ci, b.n[0], b.per[0]), cj, ck);
+    const int f0 = fidx(b, 0, ci, cj, ck);
+    const int f1 = fidx(b, 0, face_up(ci, b.n[0], b.per[0]), cj, ck);
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
       double r = 0.0;
       if (b.act[0])
-        r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) / b.dx[0];
-      b.R[q][c] = r;
+        r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) * b.idx[0];
+      st<double>(b.R[q], c, r);
     }
   } else {
     const double dt = b.scal[0];
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
-      double r = b.R[q][c];
+      double r = ld<double>(b.R[q], c);
       if (s == 0)
-        b.U[1][q][c] = b.U[0][q][c] + dt * (double)r;
+        st<double>(b.U[1][q], c, ld<double>(b.U[0][q], c) + dt * r);
       else
-        b.U[0][q][c] = 0.5 * (b.U[0][q][c] + (b.U[1][q][c] + dt * (double)r));
+        st<double>(b.U[0][q], c,
+                   0.5 * (ld<double>(b.U[0][q], c) + (ld<double>(b.U[1][q], c) + dt * r)));
     }
   }
 }
 
-template <typename real, int D>
-__global__ __launch_bounds__(kTPB) void k_sweep_march(Launch L) {
+template <typename real, int D, int WPE>
+__global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
+    Launch L) {
   const int kind = D == 1 ? kYS : kZS;
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
     const int bi = find_box(L.base + kind * (L.nboxes + 1), L.nboxes, tile);
@@ -785,6 +923,14 @@ __global__ __launch_bounds__(kTPB) void k_sweep_march(Launch L) {
   }
 }
 
+// decompose a flat position over extents (e0, e1, e2)
+__device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
+  const int q = p / e0;
+  pos[0] = p - q * e0;
+  pos[2] = q / e1;
+  pos[1] = q - pos[2] * e1;
+}
+
 // Corner EMFs: for every corner position one lane computes the EMF along
 // each axis c whose range contains it (contact-upwinded average).
 template <typename real>
@@ -793,42 +939,42 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
     const int bi = find_box(L.base + kCTE * (L.nboxes + 1), L.nboxes, tile);
     const Box& b = L.boxes[bi];
     const int lt = tile - L.base[kCTE * (L.nboxes + 1) + bi];
-    const long long p = (long long)lt * kTPB + threadIdx.x;
-    const long long P = (long long)b.nf[0] * b.nf[1] * b.nf[2];
+    const int p = lt * kTPB + (int)threadIdx.x;
+    const int P = b.nf[0] * b.nf[1] * b.nf[2];
     if (p >= P) continue;
     int pos[3];
-    pos[0] = (int)(p % b.nf[0]);
-    pos[1] = (int)((p / b.nf[0]) % b.nf[1]);
-    pos[2] = (int)(p / ((long long)b.nf[0] * b.nf[1]));
+    unflatten(p, b.nf[0], b.nf[1], pos);
+    // mapped cell indices of the positions and of the positions - 1
+    int m1[3], m0[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      m1[d] = map_cell(pos[d], b.n[d], b.per[d]);
+      m0[d] = map_cell(pos[d] - 1, b.n[d], b.per[d]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       const int a = (c + 1) % 3, bb = (c + 2) % 3;
       if (pos[c] >= b.n[c]) continue;
-      const int ia = pos[a], ib = pos[bb];
-      const int ma1 = map_cell(ia, b.n[a], b.per[a]);
-      const int ma0 = map_cell(ia - 1, b.n[a], b.per[a]);
-      const int mb1 = map_cell(ib, b.n[bb], b.per[bb]);
-      const int mb0 = map_cell(ib - 1, b.n[bb], b.per[bb]);
       int q[3];
       // a-faces (ia; ib) and (ia; ib-1)
       q[c] = pos[c];
-      q[a] = ia;
-      q[bb] = mb1;
-      const size_t fa1i = fidx(b, a, q[0], q[1], q[2]);
-      q[bb] = mb0;
-      const size_t fa0i = fidx(b, a, q[0], q[1], q[2]);
+      q[a] = pos[a];
+      q[bb] = m1[bb];
+      const int fa1i = fidx(b, a, q[0], q[1], q[2]);
+      q[bb] = m0[bb];
+      const int fa0i = fidx(b, a, q[0], q[1], q[2]);
       // b-faces (ib; ia) and (ib; ia-1)
-      q[bb] = ib;
-      q[a] = ma1;
-      const size_t fb1i = fidx(b, bb, q[0], q[1], q[2]);
-      q[a] = ma0;
-      const size_t fb0i = fidx(b, bb, q[0], q[1], q[2]);
+      q[bb] = pos[bb];
+      q[a] = m1[a];
+      const int fb1i = fidx(b, bb, q[0], q[1], q[2]);
+      q[a] = m0[a];
+      const int fb0i = fidx(b, bb, q[0], q[1], q[2]);
       // cells (ia-1, ib-1), (ia, ib-1), (ia-1, ib), (ia, ib)
       real ec[4];
-      q[a] = ma0; q[bb] = mb0; ec[0] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = ma1; q[bb] = mb0; ec[1] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = ma0; q[bb] = mb1; ec[2] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = ma1; q[bb] = mb1; ec[3] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+      q[a] = m0[a]; q[bb] = m0[bb]; ec[0] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+      q[a] = m1[a]; q[bb] = m0[bb]; ec[1] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+      q[a] = m0[a]; q[bb] = m1[bb]; ec[2] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+      q[a] = m1[a]; q[bb] = m1[bb]; ec[3] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
       const real fa1 = ld<real>(b.EF[a][1], fa1i);
       const real fa0 = ld<real>(b.EF[a][1], fa0i);
       const real fb1 = ld<real>(b.EF[bb][0], fb1i);
@@ -857,66 +1003,40 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
     const int bi = find_box(L.base + kCTF * (L.nboxes + 1), L.nboxes, tile);
     const Box& b = L.boxes[bi];
     const int lt = tile - L.base[kCTF * (L.nboxes + 1) + bi];
-    const long long p = (long long)lt * kTPB + threadIdx.x;
-    const long long P = (long long)b.nf[0] * b.nf[1] * b.nf[2];
+    const int p = lt * kTPB + (int)threadIdx.x;
+    const int P = b.nf[0] * b.nf[1] * b.nf[2];
     if (p >= P) continue;
     int pos[3];
-    pos[0] = (int)(p % b.nf[0]);
-    pos[1] = (int)((p / b.nf[0]) % b.nf[1]);
-    pos[2] = (int)(p / ((long long)b.nf[0] * b.nf[1]));
+    unflatten(p, b.nf[0], b.nf[1], pos);
     const double dt = b.scal[0];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
       const int e = (d + 1) % 3, f = (d + 2) % 3;
       if (pos[e] >= b.n[e] || pos[f] >= b.n[f]) continue;
       double t1 = 0.0, t2 = 0.0;
-      const size_t e0f = eidx(b, f, pos[0], pos[1], pos[2]);
-      const size_t e0e = eidx(b, e, pos[0], pos[1], pos[2]);
       if (b.act[e]) {
         int q[3] = {pos[0], pos[1], pos[2]};
         q[e] = face_up(pos[e], b.n[e], b.per[e]);
         const double hi = (double)ld<real>(b.ED[f], eidx(b, f, q[0], q[1], q[2]));
-        const double lo = (double)ld<real>(b.ED[f], e0f);
-        t1 = (hi - lo) / b.dx[e];
+        const double lo = (double)ld<real>(b.ED[f], eidx(b, f, pos[0], pos[1], pos[2]));
+        t1 = (hi - lo) * b.idx[e];
       }
       if (b.act[f]) {
         int q[3] = {pos[0], pos[1], pos[2]};
         q[f] = face_up(pos[f], b.n[f], b.per[f]);
         const double hi = (double)ld<real>(b.ED[e], eidx(b, e, q[0], q[1], q[2]));
-        const double lo = (double)ld<real>(b.ED[e], e0e);
-        t2 = (hi - lo) / b.dx[f];
+        const double lo = (double)ld<real>(b.ED[e], eidx(b, e, pos[0], pos[1], pos[2]));
+        t2 = (hi - lo) * b.idx[f];
       }
       const double rate = -(t1 - t2);
-      const size_t fi = fidx(b, d, pos[0], pos[1], pos[2]);
+      const int fi = fidx(b, d, pos[0], pos[1], pos[2]);
       if (L.stage == 0)
-        b.B[1][d][fi] = b.B[0][d][fi] + dt * rate;
+        st<double>(b.B[1][d], fi, ld<double>(b.B[0][d], fi) + dt * rate);
       else
-        b.B[0][d][fi] = 0.5 * (b.B[0][d][fi] + (b.B[1][d][fi] + dt * rate));
+        st<double>(b.B[0][d], fi,
+                   0.5 * (ld<double>(b.B[0][d], fi) + (ld<double>(b.B[1][d], fi) + dt * rate)));
     }
   }
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
-  }
-  return v;
-}
-
-// block-wide max: wavefront butterfly, then across the four wavefronts
-__device__ __forceinline__ double block_max(double v) {
-  __shared__ double part[kTPB / 64];
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) part[wid] = v;
-  __syncthreads();
-  double m = part[0];
-#pragma unroll
-  for (int w = 1; w < kTPB / 64; w++) m = part[w] > m ? part[w] : m;
-  __syncthreads();
-  return m;
 }
 
 // CFL rate of every cell of state s, reduced to one max per tile
@@ -925,24 +1045,15 @@ __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
     const int bi = find_box(L.base + kLAM * (L.nboxes + 1), L.nboxes, tile);
     const Box& b = L.boxes[bi];
     const int lt = tile - L.base[kLAM * (L.nboxes + 1) + bi];
-    const long long p = (long long)lt * kTPB + threadIdx.x;
-    const long long N = (long long)b.n[0] * b.n[1] * b.n[2];
+    const int p = lt * kTPB + (int)threadIdx.x;
+    const int N = b.n[0] * b.n[1] * b.n[2];
     double lmax = 0.0;
     if (p < N) {
-      const int i = (int)(p % b.n[0]);
-      const int j = (int)((p / b.n[0]) % b.n[1]);
-      const int k = (int)(p / ((long long)b.n[0] * b.n[1]));
+      int pos[3];
+      unflatten(p, b.n[0], b.n[1], pos);
       PrimD w;
-      load_prim(b, L.stage, i, j, k, w);
-      const double v[3] = {w.vx, w.vy, w.vz};
-      const double bc[3] = {w.bx, w.by, w.bz};
-#pragma unroll
-      for (int d = 0; d < 3; d++) {
-        if (!b.act[d]) continue;
-        const double cf = fast_speed(w.r, w.p, bc[d], bc[(d + 1) % 3], bc[(d + 2) % 3], b.gamma);
-        const double l = (__builtin_fabs(v[d]) + cf) / b.dx[d];
-        if (l > lmax) lmax = l;
-      }
+      load_prim(b, L.stage, pos[0], pos[1], pos[2], w);
+      lmax = cfl_rate(b, w);
     }
     const double m = block_max(lmax);
     if (threadIdx.x == 0) b.lam[lt] = m;
@@ -951,11 +1062,11 @@ __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
 
 // One workgroup per box: max of the tile partials -> time step.  mode 0:
 // step (clamp to t_stop, advance t); mode 1: query (dt of the current state
-// into scal[3]).
-__global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode) {
+// into scal[3]).  npart: kind whose tiles wrote the partials.
+__global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
   const Box& b = boxes[blockIdx.x];
   double m = 0.0;
-  for (int t = threadIdx.x; t < b.ntile[kLAM]; t += kTPB) {
+  for (int t = threadIdx.x; t < b.ntile[kind]; t += kTPB) {
     const double v = b.lam[t];
     if (v > m) m = v;
   }
@@ -984,14 +1095,14 @@ __global__ __launch_bounds__(kTPB) void k_check_periodic(const double* a, int d,
                                                          int nz, int* bad) {
   // boundary layout extents: n+1 along d
   const int ex = nx + (d == 0), ey = ny + (d == 1);
-  long long P = (long long)(d == 0 ? 1 : nx) * (d == 1 ? 1 : ny) * (d == 2 ? 1 : nz);
-  for (long long p = blockIdx.x * (long long)kTPB + threadIdx.x; p < P;
-       p += (long long)gridDim.x * kTPB) {
-    int ext0 = d == 0 ? 1 : nx, ext1 = d == 1 ? 1 : ny;
-    int i = (int)(p % ext0), j = (int)((p / ext0) % ext1), k = (int)(p / ((long long)ext0 * ext1));
-    int i2 = i, j2 = j, k2 = k;
+  const int ext0 = d == 0 ? 1 : nx, ext1 = d == 1 ? 1 : ny;
+  const int P = ext0 * ext1 * (d == 2 ? 1 : nz);
+  for (int p = blockIdx.x * kTPB + threadIdx.x; p < P; p += gridDim.x * kTPB) {
+    int pos[3];
+    unflatten(p, ext0, ext1, pos);
+    int i2 = pos[0], j2 = pos[1], k2 = pos[2];
     if (d == 0) i2 = nx; else if (d == 1) j2 = ny; else k2 = nz;
-    const size_t a0 = ((size_t)k * ey + j) * ex + i;
+    const size_t a0 = ((size_t)pos[2] * ey + pos[1]) * ex + pos[0];
     const size_t a1 = ((size_t)k2 * ey + j2) * ex + i2;
     if (a[a0] != a[a1]) atomicOr(bad, 1);
   }

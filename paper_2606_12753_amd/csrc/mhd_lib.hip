@@ -5,9 +5,10 @@
 // one SSP-RK2 step (arXiv 2606.12753 §2.2.3: reconstruct, Riemann solve,
 // conservative update per direction, constrained transport, Runge-Kutta):
 //
-//   k_lambda + k_dt            CFL rate max-reduction -> dt, t (per box)
 //   stage 1 and stage 2:
-//     k_sweep_x                x faces (LDS row segments)
+//     k_sweep_x                x faces (LDS row segments); in stage 1 also
+//                              the CFL rate max-reduction of the state,
+//     (stage 1) k_dt           -> dt, t per box
 //     k_sweep_march<y>         y faces (register-window march), residual
 //     k_sweep_march<z>         z faces, residual, RK stage combine
 //     k_ct_edge                contact-upwinded corner EMFs
@@ -23,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -90,8 +92,10 @@ int validate_box(const mhd_box& b, std::string& err) {
     return MHD_E_INVAL;
   }
   const Geom g = geom_of(b);
-  if (g.N > (size_t)1 << 31) {
-    err = "box: more than 2^31 cells";
+  // every cell, face, edge and corner offset is a 32-bit int in the kernels
+  const size_t P = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+  if (g.N > ((size_t)1 << 30) || P >= ((size_t)1 << 31)) {
+    err = "box: more than 2^30 cells";
     return MHD_E_INVAL;
   }
   return MHD_OK;
@@ -110,7 +114,7 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     err = "config: precision must be MHD_FP64 or MHD_MIXED";
     return MHD_E_INVAL;
   }
-  if (cfg->flags & ~(uint32_t)(MHD_F_GRAPH | MHD_F_PERSISTENT | MHD_F_TIMING)) {
+  if (cfg->flags & ~(uint32_t)(MHD_F_GRAPH | MHD_F_PERSISTENT | MHD_F_TIMING | MHD_F_AUTOTUNE)) {
     err = "config: unknown flag bits";
     return MHD_E_INVAL;
   }
@@ -166,10 +170,15 @@ constexpr int kDefaultSeg = 32;
 // byte layout of the workspace
 struct Plan {
   size_t total;
-  size_t boxes_off, base_off, flag_off;
+  size_t boxes_off, base_off, flag_off, backup_off, backup_bytes;
   std::vector<size_t> box_off;  // start of each box's region
   std::vector<size_t> box_bytes;
 };
+
+// bytes of one box's restorable state: U, face B, scalars, counters
+size_t backup_bytes_of(const Geom& g) {
+  return align_up(mhd::kNQ * g.N * 8) + align_up((g.F[0] + g.F[1] + g.F[2]) * 8) + 4 * 8 + 3 * 8;
+}
 
 size_t box_bytes(const Geom& g, const Tiling& t, size_t rs) {
   size_t s = 0;
@@ -180,7 +189,7 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs) {
   for (int d = 0; d < 3; d++) s += 3 * align_up(g.F[d] * rs);  // EF x2 + MF
   s += mhd::kNQ * align_up(g.N * 8);                // R (FP64)
   for (int c = 0; c < 3; c++) s += align_up(g.E[c] * rs);  // ED
-  s += align_up((size_t)t.ntile[mhd::kLAM] * 8);    // lam
+  s += align_up((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8);  // lam
   s += align_up(4 * 8);                             // scal
   s += align_up(3 * 8);                             // cnt
   return s;
@@ -204,6 +213,12 @@ Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
     p.box_bytes.push_back(bb);
     off += bb;
   }
+  p.backup_off = off;
+  p.backup_bytes = 0;
+  if (cfg->flags & MHD_F_AUTOTUNE) {
+    for (int b = 0; b < cfg->nboxes; b++) p.backup_bytes += backup_bytes_of(geom_of(cfg->boxes[b]));
+    off += align_up(p.backup_bytes);
+  }
   p.total = off;
   return p;
 }
@@ -226,6 +241,13 @@ struct mhd_ctx {
   std::vector<int> base;  // 6 * (nboxes + 1)
   int total[6] = {0, 0, 0, 0, 0, 0};
   int grid[6] = {0, 0, 0, 0, 0, 0};
+  // launch variant: register budget of the x sweep and of the marches (min
+  // waves per SIMD), march segment length, persistent grid
+  int var_x = 1, var_m = 1, var_seg = 32, var_pers = 0;
+  int cu_count = 0;
+  bool tuned = false;
+  char* backup = nullptr;  // state copy for the autotuner's trial steps
+  size_t backup_bytes = 0;
   Box* dbox = nullptr;
   int* dbase = nullptr;
   int* dflag = nullptr;
@@ -256,11 +278,30 @@ int fail(mhd_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 template <typename real>
+void launch_x(int wpe, dim3 g, hipStream_t st, const mhd::Launch& L) {
+  switch (wpe) {
+    case 3: hipLaunchKernelGGL((mhd::k_sweep_x<real, 3>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((mhd::k_sweep_x<real, 4>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((mhd::k_sweep_x<real, 1>), g, dim3(kTPB), 0, st, L); break;
+  }
+}
+
+template <typename real, int D>
+void launch_march(int wpe, dim3 g, hipStream_t st, const mhd::Launch& L) {
+  switch (wpe) {
+    case 3: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 3>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 4>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 1>), g, dim3(kTPB), 0, st, L); break;
+  }
+}
+
+template <typename real>
 int enqueue_step_t(mhd_ctx* c) {
   mhd::Launch L;
   L.boxes = c->dbox;
   L.base = c->dbase;
   L.nboxes = (int)c->boxes.size();
+  L.lam = 0;
   auto grid = [&](int kind) {
     int g = c->total[kind];
     if (c->grid[kind] > 0 && c->grid[kind] < g) g = c->grid[kind];
@@ -279,29 +320,28 @@ int enqueue_step_t(mhd_ctx* c) {
       slot++;
     }
   };
-  L.stage = 0;
-  L.ntiles = c->total[mhd::kLAM];
-  mark(MHD_K_LAMBDA, true);
-  hipLaunchKernelGGL(mhd::k_lambda, dim3(grid(mhd::kLAM)), dim3(kTPB), 0, c->stream, L);
-  mark(MHD_K_LAMBDA, false);
-  mark(MHD_K_DT, true);
-  hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 0);
-  mark(MHD_K_DT, false);
   for (int s = 0; s < 2; s++) {
     L.stage = s;
+    // stage 1's x sweep also reduces the CFL rate of the start-of-step state
+    L.lam = s == 0;
     L.ntiles = c->total[mhd::kXS];
     mark(MHD_K_SWEEP_X, true);
-    hipLaunchKernelGGL(mhd::k_sweep_x<real>, dim3(grid(mhd::kXS)), dim3(kTPB), 0, c->stream, L);
+    launch_x<real>(c->var_x, dim3(grid(mhd::kXS)), c->stream, L);
     mark(MHD_K_SWEEP_X, false);
+    L.lam = 0;
+    if (s == 0) {
+      mark(MHD_K_DT, true);
+      hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 0,
+                         (int)mhd::kXS);
+      mark(MHD_K_DT, false);
+    }
     L.ntiles = c->total[mhd::kYS];
     mark(MHD_K_SWEEP_Y, true);
-    hipLaunchKernelGGL((mhd::k_sweep_march<real, 1>), dim3(grid(mhd::kYS)), dim3(kTPB), 0,
-                       c->stream, L);
+    launch_march<real, 1>(c->var_m, dim3(grid(mhd::kYS)), c->stream, L);
     mark(MHD_K_SWEEP_Y, false);
     L.ntiles = c->total[mhd::kZS];
     mark(MHD_K_SWEEP_Z, true);
-    hipLaunchKernelGGL((mhd::k_sweep_march<real, 2>), dim3(grid(mhd::kZS)), dim3(kTPB), 0,
-                       c->stream, L);
+    launch_march<real, 2>(c->var_m, dim3(grid(mhd::kZS)), c->stream, L);
     mark(MHD_K_SWEEP_Z, false);
     L.ntiles = c->total[mhd::kCTE];
     mark(MHD_K_CT_EDGE, true);
@@ -325,7 +365,7 @@ int enqueue_step_t(mhd_ctx* c) {
   return MHD_OK;
 }
 
-constexpr int kLaunchesPerStep = 12;
+constexpr int kLaunchesPerStep = 11;
 
 int enqueue_step(mhd_ctx* c) {
   return c->precision == MHD_FP64 ? enqueue_step_t<double>(c) : enqueue_step_t<float>(c);
@@ -347,6 +387,133 @@ __global__ void k_reset_box(const Box* boxes, int box, double t) {
     b.cnt[1] = 0;
     b.cnt[2] = 0;
   }
+}
+
+void set_persistent(mhd_ctx* c, int on) {
+  c->var_pers = on;
+  // eight resident workgroups per compute unit
+  for (int k = 0; k < 6; k++) c->grid[k] = on ? c->cu_count * 8 : 0;
+}
+
+// re-tile the y/z marches with segment length seg (device tables updated
+// on the context stream)
+int apply_tiling(mhd_ctx* c, int seg) {
+  const int nb = (int)c->boxes.size();
+  c->var_seg = seg;
+  for (int k = 0; k < 6; k++) c->total[k] = 0;
+  for (int bi = 0; bi < nb; bi++) {
+    Tiling t = tiling_of(c->geom[bi], seg, seg);
+    Box& b = c->hbox[bi];
+    b.ysl = t.ysl;
+    b.yseg = t.yseg;
+    b.zsl = t.zsl;
+    b.zseg = t.zseg;
+    for (int k = 0; k < 6; k++) {
+      b.ntile[k] = t.ntile[k];
+      c->base[k * (nb + 1) + bi] = c->total[k];
+      c->total[k] += t.ntile[k];
+    }
+  }
+  for (int k = 0; k < 6; k++) c->base[k * (nb + 1) + nb] = c->total[k];
+  HIPCHK(c, hipMemcpyAsync(c->dbox, c->hbox.data(), sizeof(Box) * nb, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dbase, c->base.data(), sizeof(int) * c->base.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MHD_OK;
+}
+
+// copy every box's state (U, B, t, counters) to (save) or from the backup
+int backup_state(mhd_ctx* c, bool save) {
+  char* p = c->backup;
+  for (size_t bi = 0; bi < c->boxes.size(); bi++) {
+    const Geom& g = c->geom[bi];
+    const Box& b = c->hbox[bi];
+    auto cp = [&](void* dev, size_t bytes) -> int {
+      if (save)
+        HIPCHK(c, hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+      else
+        HIPCHK(c, hipMemcpyAsync(dev, p, bytes, hipMemcpyDeviceToDevice, c->stream));
+      p += bytes;
+      return MHD_OK;
+    };
+    char* start = p;
+    for (int q = 0; q < mhd::kNQ; q++)
+      if (cp(b.U[0][q], g.N * 8)) return MHD_E_DEVICE;
+    p = start + align_up(mhd::kNQ * g.N * 8);
+    start = p;
+    for (int d = 0; d < 3; d++)
+      if (cp(b.B[0][d], g.F[d] * 8)) return MHD_E_DEVICE;
+    p = start + align_up((g.F[0] + g.F[1] + g.F[2]) * 8);
+    if (cp(b.scal, 4 * 8)) return MHD_E_DEVICE;
+    if (cp(b.cnt, 3 * 8)) return MHD_E_DEVICE;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MHD_OK;
+}
+
+int enqueue_step(mhd_ctx* c);
+
+// time `steps` steps of the current variant (state restored afterwards)
+int trial(mhd_ctx* c, int steps, float* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int rc = enqueue_step(c);  // warm-up
+  if (!rc) {
+    (void)hipEventRecord(e0, c->stream);
+    for (int s = 0; s < steps && !rc; s++) rc = enqueue_step(c);
+    (void)hipEventRecord(e1, c->stream);
+  }
+  hipError_t e = hipEventSynchronize(e1);
+  if (!rc && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(c, MHD_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  return backup_state(c, false);
+}
+
+// Coordinate search over the launch variants on the context's own boxes and
+// state: register budget of the x sweep and of the marches, march segment
+// length, persistent grid.  The arithmetic of every variant is the same, so
+// the FP64 results do not depend on the choice.
+int autotune(mhd_ctx* c) {
+  if (!c->backup) return fail(c, MHD_E_STATE, "autotune needs a context created with MHD_F_AUTOTUNE");
+  int rc = backup_state(c, true);
+  if (rc) return rc;
+  const int steps = 2;
+  float best = 0.f;
+  rc = trial(c, steps, &best);
+  if (rc) return rc;
+  auto try_var = [&](int* field, int value, auto apply) -> int {
+    const int old = *field;
+    int r = apply(value);
+    if (r) return r;
+    float ms = 0.f;
+    r = trial(c, steps, &ms);
+    if (r) return r;
+    if (ms < best) {
+      best = ms;
+    } else {
+      r = apply(old);
+      if (r) return r;
+    }
+    return MHD_OK;
+  };
+  auto set_x = [&](int v) { c->var_x = v; return MHD_OK; };
+  auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
+  auto set_seg = [&](int v) { return apply_tiling(c, v); };
+  auto set_pers = [&](int v) { set_persistent(c, v); return MHD_OK; };
+  for (int v : {3, 4})
+    if ((rc = try_var(&c->var_m, v, set_m))) return rc;
+  for (int v : {3, 4})
+    if ((rc = try_var(&c->var_x, v, set_x))) return rc;
+  for (int v : {16, 64, 128})
+    if ((rc = try_var(&c->var_seg, v, set_seg))) return rc;
+  if ((rc = try_var(&c->var_pers, 1 - c->var_pers, set_pers))) return rc;
+  c->tuned = true;
+  return MHD_OK;
 }
 
 int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
@@ -379,7 +546,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
   for (int bi = 0; bi < nb; bi++) {
     const mhd_box& mb = cfg->boxes[bi];
     Geom g = geom_of(mb);
-    Tiling t = tiling_of(g, kDefaultSeg, kDefaultSeg);
+    Tiling t = tiling_of(g, c->var_seg, c->var_seg);
     c->geom[bi] = g;
     Box& b = c->hbox[bi];
     std::memset(&b, 0, sizeof(Box));
@@ -389,8 +556,10 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
       b.per[d] = g.per[d];
       b.act[d] = g.act[d];
       b.dx[d] = (mb.hi[d] - mb.lo[d]) / (double)mb.n[d];
+      b.idx[d] = 1.0 / b.dx[d];
     }
     b.gamma = mb.gamma;
+    b.igm1 = 1.0 / (mb.gamma - 1.0);
     b.cfl = mb.cfl;
     b.pfloor = cfg->p_floor > 0.0 ? cfg->p_floor : 1e-10;
     char* p = c->ws + plan.box_off[bi];
@@ -412,7 +581,8 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     }
     for (int q = 0; q < mhd::kNQ; q++) b.R[q] = reinterpret_cast<double*>(take(g.N * 8));
     for (int cc = 0; cc < 3; cc++) b.ED[cc] = take(g.E[cc] * rs);
-    b.lam = reinterpret_cast<double*>(take((size_t)t.ntile[mhd::kLAM] * 8));
+    b.lam = reinterpret_cast<double*>(
+        take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xw = t.xw;
@@ -439,12 +609,15 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     c->ev_kind.assign(kLaunchesPerStep, 0);
     for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
   }
-  if (c->flags & MHD_F_PERSISTENT) {
+  {
     hipDeviceProp_t prop;
     HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
-    // eight resident workgroups per compute unit
-    for (int k = 0; k < 6; k++) c->grid[k] = prop.multiProcessorCount * 8;
+    c->cu_count = prop.multiProcessorCount;
   }
+  if (c->flags & MHD_F_PERSISTENT) c->var_pers = 1;
+  set_persistent(c, c->var_pers);
+  c->backup = plan.backup_bytes ? c->ws + plan.backup_off : nullptr;
+  c->backup_bytes = plan.backup_bytes;
   HIPCHK(c, hipMemcpyAsync(c->dbox, c->hbox.data(), sizeof(Box) * nb, hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dbase, c->base.data(), sizeof(int) * c->base.size(),
@@ -585,6 +758,17 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     }
     c->own_stream = true;
   }
+  if (const char* v = std::getenv("MHD_VARIANT")) {
+    // "x,m,seg,persistent": fixed launch variant (tests, experiments)
+    int x = 1, m = 1, sg = 32, pe = 0;
+    if (std::sscanf(v, "%d,%d,%d,%d", &x, &m, &sg, &pe) == 4 && (x == 1 || x == 3 || x == 4) &&
+        (m == 1 || m == 3 || m == 4) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
+      c->var_x = x;
+      c->var_m = m;
+      c->var_seg = sg;
+      c->var_pers = pe;
+    }
+  }
   rc = build_ctx(c, cfg);
   if (rc) {
     g_create_error = c->err;
@@ -649,6 +833,10 @@ int mhd_step(mhd_ctx* c, int32_t nsteps, double t_stop) {
     if (!c->state_set[b]) return fail(c, MHD_E_STATE, "mhd_step before mhd_set_state of every box");
   if (nsteps == 0) return MHD_OK;
   const int nb = (int)c->boxes.size();
+  if ((c->flags & MHD_F_AUTOTUNE) && !c->tuned) {
+    int rc = autotune(c);
+    if (rc) return rc;
+  }
   hipLaunchKernelGGL(k_set_scalar, dim3((nb + 255) / 256), dim3(256), 0, c->stream, c->dbox, nb, 2,
                      t_stop > 0.0 ? t_stop : 0.0);
   HIPCHK(c, hipGetLastError());
@@ -682,9 +870,11 @@ int mhd_dt(mhd_ctx* c, int32_t box, double* dt_next, double* t) {
   L.base = c->dbase;
   L.nboxes = (int)c->boxes.size();
   L.stage = 0;
+  L.lam = 0;
   L.ntiles = c->total[mhd::kLAM];
   hipLaunchKernelGGL(mhd::k_lambda, dim3(std::max(1, L.ntiles)), dim3(kTPB), 0, c->stream, L);
-  hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 1);
+  hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 1,
+                     (int)mhd::kLAM);
   HIPCHK(c, hipGetLastError());
   double scal[4];
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -753,6 +943,16 @@ int mhd_kernel_times(mhd_ctx* c, double ms[MHD_NKERNELS], int64_t launches[MHD_N
       c->kcount[k] = 0;
     }
   }
+  return MHD_OK;
+}
+
+int mhd_tuning(mhd_ctx* c, int32_t variant[4]) {
+  if (!c) return MHD_E_INVAL;
+  if (!variant) return fail(c, MHD_E_INVAL, "variant is NULL");
+  variant[0] = c->var_x;
+  variant[1] = c->var_m;
+  variant[2] = c->var_seg;
+  variant[3] = c->var_pers;
   return MHD_OK;
 }
 

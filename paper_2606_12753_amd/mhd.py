@@ -35,11 +35,13 @@ MHD_DEVICE = 1
 MHD_F_GRAPH = 1
 MHD_F_PERSISTENT = 2
 MHD_F_TIMING = 4
+MHD_F_AUTOTUNE = 8
 KERNELS = ["lambda", "dt", "sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 
 EXPORTED = [
     "mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_dt",
-    "mhd_get_state", "mhd_counters", "mhd_kernel_times", "mhd_destroy", "mhd_last_error",
+    "mhd_get_state", "mhd_counters", "mhd_kernel_times", "mhd_tuning",
+    "mhd_destroy", "mhd_last_error",
 ]
 
 
@@ -102,6 +104,7 @@ def load():
                                   C.POINTER(C.c_void_p), _dp, C.c_int32]
     lib.mhd_counters.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.mhd_kernel_times.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_int64), C.c_int32]
+    lib.mhd_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     lib.mhd_destroy.argtypes = [C.c_void_p]
     lib.mhd_destroy.restype = None
     lib.mhd_last_error.argtypes = [C.c_void_p]
@@ -275,6 +278,13 @@ class Sim:
         n = (C.c_int64 * len(KERNELS))()
         self._check(self._lib.mhd_kernel_times(self._h, ms, n, int(bool(reset))))
         return {k: (ms[i], int(n[i])) for i, k in enumerate(KERNELS)}
+
+    def tuning(self):
+        """Launch variant in use: (x-sweep waves/SIMD, march waves/SIMD,
+        march segment length, persistent grid)."""
+        v = (C.c_int32 * 4)()
+        self._check(self._lib.mhd_tuning(self._h, v))
+        return tuple(int(x) for x in v)
 
     def counters(self, box: int = 0):
         c = (C.c_int64 * 3)()

@@ -275,11 +275,24 @@ def test_random_3d_mixed():
 # ---------------------------------------------------------------- full size
 
 def _sub_box(spec, st, centre, r):
-    """(2r+1)^3 neighbourhood of a cell, periodic wrap, as an oracle box with
-    outflow walls; only the centre is exact after one step."""
-    n = 2 * r + 1
-    idx = [np.arange(centre[d] - r, centre[d] + r + 1) % spec.n[d] for d in range(3)]
-    fidx = [np.arange(centre[d] - r, centre[d] + r + 2) % spec.n[d] for d in range(3)]
+    """Neighbourhood of radius r around a cell as an oracle box: periodic axes
+    wrap, outflow axes stop at the real boundary (whose outflow condition the
+    sub-box then applies exactly); every cut side gets an outflow wall whose
+    influence stays r cells away from the centre.  Returns the sub-box, its
+    state and the centre's index inside it."""
+    idx, fidx, off = [], [], []
+    for d in range(3):
+        n = spec.n[d]
+        if spec.bc[d] == W.PERIODIC:
+            a = np.arange(centre[d] - r, centre[d] + r + 1) % n
+            idx.append(a)
+            fidx.append(np.arange(centre[d] - r, centre[d] + r + 2) % n)
+            off.append(r)
+        else:
+            lo, hi = max(0, centre[d] - r), min(n, centre[d] + r + 1)
+            idx.append(np.arange(lo, hi))
+            fidx.append(np.arange(lo, hi + 1))
+            off.append(centre[d] - lo)
     cons = [np.ascontiguousarray(c[np.ix_(idx[2], idx[1], idx[0])]) for c in st.cons]
     bface = [
         np.ascontiguousarray(st.bface[0][np.ix_(idx[2], idx[1], fidx[0])]),
@@ -287,9 +300,30 @@ def _sub_box(spec, st, centre, r):
         np.ascontiguousarray(st.bface[2][np.ix_(fidx[2], idx[1], idx[0])]),
     ]
     dx = spec.dx
-    sub = W.BoxSpec((n, n, n), lo=(0.0, 0.0, 0.0), hi=tuple(n * dx[d] for d in range(3)),
+    nn = tuple(len(a) for a in idx)
+    sub = W.BoxSpec(nn, lo=(0.0, 0.0, 0.0), hi=tuple(nn[d] * dx[d] for d in range(3)),
                     bc=(W.OUTFLOW,) * 3, gamma=spec.gamma, cfl=spec.cfl)
-    return sub, cons, bface
+    return sub, cons, bface, tuple(off)
+
+
+def _check_sampled(spec, st, cons, bface, dt, centres, r=8):
+    """One oracle step with the GPU's dt on the neighbourhood of each sampled
+    cell; compares the cell's conserved state and its three lower faces."""
+    for c in centres:
+        sub, sc, sb, o = _sub_box(spec, st, c, r)
+        ob = O.OracleBox(sub)
+        ob.set_state(sc, sb)
+        ob.step_fixed_dt(dt)
+        oc, obf, _ = ob.get_state()
+        i, j, k = c
+        oi, oj, ok = o
+        for q in range(5):
+            a, b = cons[q][k, j, i], oc[q][ok, oj, oi]
+            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, q, a, b)
+        for d, (a, b) in enumerate([(bface[0][k, j, i], obf[0][ok, oj, oi]),
+                                    (bface[1][k, j, i], obf[1][ok, oj, oi]),
+                                    (bface[2][k, j, i], obf[2][ok, oj, oi])]):
+            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, "B", d, a, b)
 
 
 def test_blast_256_full_size_sampled():
@@ -313,18 +347,80 @@ def test_blast_256_full_size_sampled():
     rng = np.random.default_rng(5)
     centres = [tuple(int(v) for v in rng.integers(0, 256, size=3)) for _ in range(4)]
     centres += [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25)]
-    r = 8
-    for c in centres:
-        sub, sc, sb = _sub_box(spec, st, c, r)
-        ob = O.OracleBox(sub)
-        ob.set_state(sc, sb)
-        ob.step_fixed_dt(dt_gpu)
-        oc, obf, _ = ob.get_state()
-        i, j, k = c
-        for q in range(5):
-            a, b = cons[q][k, j, i], oc[q][r, r, r]
-            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, q, a, b)
-        for d, (a, b) in enumerate([(bface[0][k, j, i], obf[0][r, r, r]),
-                                    (bface[1][k, j, i], obf[1][r, r, r]),
-                                    (bface[2][k, j, i], obf[2][r, r, r])]):
-            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, "B", d, a, b)
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres)
+
+
+def test_kelvin_helmholtz_full_size_sampled():
+    """768 x 384 x 384, periodic x and z, outflow y: one mixed-path-free FP64
+    step at full size; sampled cells at the outflow walls and inside."""
+    wl = W.kelvin_helmholtz()
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt_gpu, _ = sim.dt(0)
+        sim.step(1)
+        cons, bface, t = sim.get_state(0)
+    assert t == dt_gpu
+    centres = [(0, 0, 0), (767, 383, 383), (400, 1, 200), (5, 382, 17), (384, 96, 192),
+               (123, 287, 301), (700, 192, 0)]
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres)
+
+
+def test_ensemble_96_boxes_full_size():
+    """The 96-box ensemble (sizes 32^3..128^3) in one context with graph
+    replay and persistent tiles: per-box dt equals the oracle's; sampled
+    cells of four boxes after one step."""
+    wl = W.ensemble()
+    with mhd.Sim(wl.boxes, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT) as sim:
+        for b, st in enumerate(wl.states):
+            sim.set_state(b, st.cons, st.bface, 0.0)
+        dts = [sim.dt(b)[0] for b in range(len(wl.boxes))]
+        sim.step(1)
+        picks = [0, 1, int(np.argmax([s.n[0] for s in wl.boxes])),
+                 int(np.argmin([s.n[0] for s in wl.boxes]))]
+        outs = {b: sim.get_state(b) for b in picks}
+    for b in picks:
+        spec, st = wl.boxes[b], wl.states[b]
+        ob = O.OracleBox(spec)
+        ob.set_state(st.cons, st.bface)
+        assert dts[b] == ob.dt(), b
+        del ob
+        cons, bface, t = outs[b]
+        assert t == dts[b]
+        n = spec.n[0]
+        centres = [(0, 0, 0), (n - 1, n // 2, 3), (n // 3, n - 1, n // 2)]
+        _check_sampled(spec, st, cons, bface, dts[b], centres)
+
+
+# ---------------------------------------------------------------- variants
+
+@pytest.mark.parametrize("variant", ["1,1,32,0", "3,4,16,1", "4,3,64,0", "1,4,128,1", "4,4,7,0"])
+def test_launch_variants_bitwise_identical(variant, monkeypatch):
+    """Register budgets, segment lengths and grid shapes change scheduling
+    only: FP64 results are identical across all launch variants."""
+    wl = W.random_smooth(n=(40, 33, 29), seed=17, bc=(0, 1, 0))
+    monkeypatch.delenv("MHD_VARIANT", raising=False)
+    ref = gpu_run(wl, 3)[0]
+    monkeypatch.setenv("MHD_VARIANT", variant)
+    g = gpu_run(wl, 3)[0]
+    for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
+        assert np.array_equal(a, b), variant
+    assert g[3] == ref[3]
+
+
+def test_autotune_restores_state_and_matches():
+    """The autotuner's trial steps run on the context's own state and must
+    leave no trace: the tuned run equals the untuned one bit for bit."""
+    wl = W.blast_3d(n=48, steps=4)
+    spec, st = wl.boxes[0], wl.states[0]
+    ref = gpu_run(wl, 4)[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_AUTOTUNE | mhd.MHD_F_GRAPH) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        sim.step(4)
+        cons, bface, t = sim.get_state(0)
+        v = sim.tuning()
+        cnt = sim.counters(0)
+    assert v[0] in (1, 3, 4) and v[1] in (1, 3, 4) and v[2] >= 1 and v[3] in (0, 1)
+    assert t == ref[2] and cnt == ref[3]
+    for a, b in zip(cons + bface, ref[0] + ref[1]):
+        assert np.array_equal(a, b)
