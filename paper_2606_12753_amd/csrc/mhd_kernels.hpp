@@ -149,6 +149,9 @@ __device__ __forceinline__ void st(void* p, int i, T v) {
 // products (the oracle evaluates the same expressions in the same order).
 __device__ __forceinline__ double rcp(double b) { return 1.0 / b; }
 __device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
+// single quotient: IEEE division in FP64, reciprocal and product in FP32
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double ab(double a) { return __builtin_fabs(a); }
@@ -494,8 +497,8 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
           for (int c = 0; c < 7; c++) f[c] = fs[c];
         } else {
           real sql = sq(stl.rho), sqr = sq(str.rho);
-          real ssl = sm - ab(bn) * rcp(sql);
-          real ssr = sm + ab(bn) * rcp(sqr);
+          real ssl = sm - quot(ab(bn), sql);
+          real ssr = sm + quot(ab(bn), sqr);
           real sgn = bn > (real)0 ? (real)1 : (real)-1;
           real iss = rcp(sql + sqr);
           real vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) * iss;
