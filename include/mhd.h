@@ -146,8 +146,13 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
                      int64_t launches[MHD_NKERNELS], int32_t reset);
 
 /* The launch variant in use: [0] min waves per SIMD of the x sweep's
- * register budget (1 = unconstrained, 3, 4), [1] the same for the y/z
- * marches, [2] march segment length (cells), [3] persistent grid (0/1).
+ * register budget (1 = unconstrained, 3, 4), [1] y/z march variant (1:
+ * unconstrained registers with the update inputs prefetched ahead of the
+ * Riemann solve, 2: unconstrained without prefetch, 3 / 4: at least 3 / 4
+ * waves per SIMD without prefetch, 5 / 6 / 7: the sliding window kept in
+ * LDS, with prefetch / without / at least 3 waves per SIMD), [2] march
+ * segment length (cells),
+ * [3] persistent grid (0/1).
  * The variants differ only in scheduling: FP64 results are identical. */
 int mhd_tuning(mhd_ctx *ctx, int32_t variant[4]);
 

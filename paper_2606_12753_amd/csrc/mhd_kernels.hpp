@@ -275,11 +275,18 @@ __device__ __forceinline__ St7<real> rotate(const PrimD& w, int d) {
   return q;
 }
 
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+
+// minmod: the argument of smaller magnitude when both have the same sign,
+// else zero; as max(min(a,b), min(max(a,b),0)), four min/max instructions
+// and no branch (same value as the case-by-case definition; a zero result
+// may carry either sign)
 template <typename real>
 __device__ __forceinline__ real minmod(real a, real b) {
-  if (a > (real)0 && b > (real)0) return a < b ? a : b;
-  if (a < (real)0 && b < (real)0) return a > b ? a : b;
-  return (real)0;
+  return vmax(vmin(a, b), vmin(vmax(a, b), (real)0));
 }
 
 // PLM interface values between cells c-1 and c from q(c-2), q(c-1), q(c),
@@ -430,9 +437,9 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
                                        real gamma, real igm1, real* f, real* fm) {
   real cfl = fast_speed(wl.v[0], wl.v[4], bn, wl.v[5], wl.v[6], gamma);
   real cfr = fast_speed(wr.v[0], wr.v[4], bn, wr.v[5], wr.v[6], gamma);
-  real cmax = cfl > cfr ? cfl : cfr;
-  real umin = wl.v[1] < wr.v[1] ? wl.v[1] : wr.v[1];
-  real umax = wl.v[1] > wr.v[1] ? wl.v[1] : wr.v[1];
+  real cmax = vmax(cfl, cfr);
+  real umin = vmin(wl.v[1], wr.v[1]);
+  real umax = vmax(wl.v[1], wr.v[1]);
   real sl = umin - cmax;
   real sr = umax + cmax;
   int used = 0;
@@ -743,8 +750,69 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 // ahead is loaded before the current face is solved.  Y: adds the x
 // and y flux divergence and writes the residual.  Z: adds the z divergence
 // to the residual and applies the SSP-RK2 stage combine.
-template <typename real, int D>
-__device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr, int j0, int j1) {
+// Window of the march: cells f-1 and f and the limited slope of cell f-1.
+// LW = 0 keeps it in registers; LW = 1 keeps it in a per-lane LDS column
+// (three slots of seven values, no sharing between lanes, so no barrier):
+// fewer registers live across the Riemann solve.
+template <typename real, int LW>
+struct Window;
+
+template <typename real>
+struct Window<real, 0> {
+  St7<real> q1, q2, dm1;
+  __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d) {
+    q1 = a;
+    q2 = b;
+    dm1 = d;
+  }
+  // PLM states of the face between the window's cells given the next cell
+  // q3; then slides the window by one cell
+  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, St7<real>& wl, St7<real>& wr) {
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      const real d0 = minmod(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
+      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
+      wr.v[v] = q2.v[v] - (real)0.5 * d0;
+      dm1.v[v] = d0;
+    }
+    q1 = q2;
+    q2 = q3;
+  }
+};
+
+template <typename real>
+struct Window<real, 1> {
+  real (*lds)[kTPB];  // [21][kTPB]: slots 0-6 and 7-13 cells, 14-20 slope
+  int t, a;           // lane, offset of the slot holding cell f-1
+  __device__ __forceinline__ void init(const St7<real>& q1, const St7<real>& q2, const St7<real>& d) {
+    a = 0;
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      lds[v][t] = q1.v[v];
+      lds[7 + v][t] = q2.v[v];
+      lds[14 + v][t] = d.v[v];
+    }
+  }
+  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, St7<real>& wl, St7<real>& wr) {
+    const int bo = 7 - a;
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      const real x1 = lds[a + v][t];
+      const real x2 = lds[bo + v][t];
+      const real dm = lds[14 + v][t];
+      const real d0 = minmod(x2 - x1, q3.v[v] - x2);
+      wl.v[v] = x1 + (real)0.5 * dm;
+      wr.v[v] = x2 - (real)0.5 * d0;
+      lds[a + v][t] = q3.v[v];  // cell f+1 takes the slot of cell f-1
+      lds[14 + v][t] = d0;
+    }
+    a = bo;
+  }
+};
+
+template <typename real, int D, int PF, int LW>
+__device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr, int j0, int j1,
+                                             real (*lds)[kTPB]) {
   // (i, tr): x index and the index along the remaining axis (z for D=1, y
   // for D=2); cells [j0, j1) along D, faces j0..j1
   const int n = b.n[D];
@@ -753,18 +821,23 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
     const int am = map_cell(a, n, per);
     return D == 1 ? addr_of(b, i, am, tr) : addr_of(b, i, tr, am);
   };
-  // window: cells f-1 and f and the limited slope of cell f-1
-  St7<real> q1, q2, q3, dm1;
+  Window<real, LW> win;
+  if constexpr (LW) {
+    win.lds = lds;
+    win.t = threadIdx.x;
+  }
   {
     PrimD w;
     raw_to_prim(b, load_raw(b, s, addr_at(j0 - 2)), w);
     const St7<real> q0 = rotate<real>(w, D);
     raw_to_prim(b, load_raw(b, s, addr_at(j0 - 1)), w);
-    q1 = rotate<real>(w, D);
+    const St7<real> q1 = rotate<real>(w, D);
     raw_to_prim(b, load_raw(b, s, addr_at(j0)), w);
-    q2 = rotate<real>(w, D);
+    const St7<real> q2 = rotate<real>(w, D);
+    St7<real> dm1;
 #pragma unroll
     for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
+    win.init(q1, q2, dm1);
   }
   Raw next = load_raw(b, s, addr_at(j0 + 1));
   real fprev[kNQ];
@@ -778,13 +851,13 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
   for (int f = j0; f <= j1; ++f) {
     PrimD w;
     raw_to_prim(b, next, w);
-    q3 = rotate<real>(w, D);
+    const St7<real> q3 = rotate<real>(w, D);
     if (f < j1) next = load_raw(b, s, addr_at(f + 2));
-    // inputs of the cell update, issued before the solve
+    // inputs of the cell update: issued before the solve (PF) or after it
     const int cprev = cbase + (f - 1) * cstride;
     double racc[kNQ];
     double u0v[kNQ], u1v[kNQ];
-    if (f > j0) {
+    auto load_update_inputs = [&]() {
       if (D == 1) {
         const int f0 = (tr * b.n[1] + (f - 1)) * b.nf[0] + i;
         const int f1 = (b.per[0] && i + 1 == b.n[0]) ? f0 - i : f0 + 1;
@@ -803,14 +876,10 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
           if (s == 1) u1v[q] = ld<double>(b.U[1][q], cprev);
         }
       }
-    }
-    St7<real> wl, wr, d0;
-#pragma unroll
-    for (int v = 0; v < 7; v++) {
-      d0.v[v] = minmod(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
-      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
-      wr.v[v] = q2.v[v] - (real)0.5 * d0.v[v];
-    }
+    };
+    if (PF && f > j0) load_update_inputs();
+    St7<real> wl, wr;
+    win.face_and_slide(q3, wl, wr);
     // face index f along D is in [0, n]; periodic face n is face 0
     const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
     const real bn = (real)ld<double>(b.B[s][D], fi);
@@ -830,6 +899,7 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
     }
     if (f > j0) {
       // cell f-1 is complete
+      if (!PF) load_update_inputs();
       const double idxD = b.idx[D];
 #pragma unroll
       for (int q = 0; q < kNQ; q++) {
@@ -845,9 +915,6 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
     }
 #pragma unroll
     for (int q = 0; q < kNQ; q++) fprev[q] = fl[q];
-    q1 = q2;
-    q2 = q3;
-    dm1 = d0;
   }
 }
 
@@ -898,9 +965,12 @@ __device__ __forceinline__ void inactive_column(const Box& b, int s, int i, int 
   }
 }
 
-template <typename real, int D, int WPE>
+// PF: prefetch the inputs of the cell update ahead of the Riemann solve
+// (latency hidden, more registers live across the solve)
+template <typename real, int D, int WPE, int PF, int LW>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
+  __shared__ real lds[LW ? 21 : 1][kTPB];
   const int kind = D == 1 ? kYS : kZS;
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
     const int bi = find_box(L.base + kind * (L.nboxes + 1), L.nboxes, tile);
@@ -919,7 +989,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D>(b, L.stage, i, tr, j0, j1);
+      march_column<real, D, PF, LW>(b, L.stage, i, tr, j0, j1, lds);
     } else {
       inactive_column<real, D>(b, L.stage, i, tr);
     }

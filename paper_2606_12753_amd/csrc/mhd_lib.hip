@@ -286,12 +286,22 @@ void launch_x(int wpe, dim3 g, hipStream_t st, const mhd::Launch& L) {
   }
 }
 
+// march variants: 1 = unconstrained registers, update inputs prefetched;
+// 2 = unconstrained, no prefetch; 3, 4 = at least 3 / 4 waves per SIMD, no
+// prefetch; 5, 6, 7 = window in LDS with (5) no register constraint and
+// prefetch, (6) no constraint and no prefetch, (7) at least 3 waves per
+// SIMD and no prefetch
 template <typename real, int D>
-void launch_march(int wpe, dim3 g, hipStream_t st, const mhd::Launch& L) {
-  switch (wpe) {
-    case 3: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 3>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 4>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((mhd::k_sweep_march<real, D, 1>), g, dim3(kTPB), 0, st, L); break;
+void launch_march(int var, dim3 g, hipStream_t st, const mhd::Launch& L) {
+  using mhd::k_sweep_march;
+  switch (var) {
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
@@ -505,7 +515,7 @@ int autotune(mhd_ctx* c) {
   auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
   auto set_seg = [&](int v) { return apply_tiling(c, v); };
   auto set_pers = [&](int v) { set_persistent(c, v); return MHD_OK; };
-  for (int v : {3, 4})
+  for (int v : {2, 3, 5, 6, 7})
     if ((rc = try_var(&c->var_m, v, set_m))) return rc;
   for (int v : {3, 4})
     if ((rc = try_var(&c->var_x, v, set_x))) return rc;
@@ -762,7 +772,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     // "x,m,seg,persistent": fixed launch variant (tests, experiments)
     int x = 1, m = 1, sg = 32, pe = 0;
     if (std::sscanf(v, "%d,%d,%d,%d", &x, &m, &sg, &pe) == 4 && (x == 1 || x == 3 || x == 4) &&
-        (m == 1 || m == 3 || m == 4) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
+        (m >= 1 && m <= 7) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
       c->var_x = x;
       c->var_m = m;
       c->var_seg = sg;

@@ -394,7 +394,8 @@ def test_ensemble_96_boxes_full_size():
 
 # ---------------------------------------------------------------- variants
 
-@pytest.mark.parametrize("variant", ["1,1,32,0", "3,4,16,1", "4,3,64,0", "1,4,128,1", "4,4,7,0"])
+@pytest.mark.parametrize("variant", ["1,1,32,0", "3,4,16,1", "4,3,64,0", "1,2,128,1", "4,5,7,0",
+                                     "1,6,32,1", "3,7,16,0"])
 def test_launch_variants_bitwise_identical(variant, monkeypatch):
     """Register budgets, segment lengths and grid shapes change scheduling
     only: FP64 results are identical across all launch variants."""
