@@ -6,17 +6,28 @@ Workload: the 3D magnetised blast wave, 256^3 periodic unit cube (seeded
 one full SSP-RK2 step of the whole box (both stages, every kernel of the
 path); inputs are resident in HBM before the timed region.  The timed region
 is ``--steps`` graph-replayed steps on the library's stream, bracketed by HIP
-events; ``value`` is cell-updates per second (cells x steps / time).
+events; ``value`` is FP64 cell-updates per second (cells x steps / time).
+The launch variant is chosen by the library's autotuner during the warm-up
+steps (outside the timed region).
 
 Also reported on the same line: the mixed-precision rate on the same
-workload, a roofline object for the dominant kernel (algorithmic bytes per
-launch over its average launch time, the latter measured with HIP events in
-a separate timing pass of the same launches), and the CPU oracle's rate on a
-bounded sample of the same recipe.
+workload and its relative L1 error against the FP64 run after the same step
+count (rho, p, |B|) with max|div B| of both; a roofline object for the
+dominant kernel (algorithmic bytes per launch over its average launch time,
+measured with HIP events around each launch of a timing pass of the same
+kernels on the library's stream); the HBM traffic of that kernel from the
+committed rocprofv3 counter summary when it was taken on the current kernel
+source; and the CPU oracle's rate on a bounded sample of the same recipe.
+
+``--accuracy`` instead runs the mixed path against the FP64 path on the full
+turbulence (512^3, 200 steps), ensemble (96 boxes, 100 steps) and
+Kelvin-Helmholtz (768x384x384, 100 steps) workloads and prints one JSON line
+per workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,21 +37,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_blast_256.json")
 
-# Algorithmic HBM bytes per cell and launch, FP64 path (compulsory reads and
-# writes of each kernel's inputs and outputs, each array element once;
-# stage 1 / stage 2 where they differ).  See DESIGN.md "Kernels and bytes".
+# Algorithmic HBM bytes per cell and launch (compulsory reads and writes of
+# each kernel's inputs and outputs, each array element once; stage 1 /
+# stage 2).  FP64 path:
 BYTES_FP64 = {
-    "lambda": (64, 64),
-    "sweep_x": (152, 152),
+    "sweep_x": (152, 152),    # stage 1 also reduces the CFL rate (no extra bytes)
     "sweep_y": (168, 168),
     "sweep_z": (168, 208),
     "ct_edge": (120, 120),
     "ct_face": (72, 96),
 }
-# mixed path: state FP64, work arrays FP32
+# mixed path: FP64 state and residual, FP32 face fluxes, EMFs, mass fluxes
 BYTES_MIXED = {
-    "lambda": (64, 64),
     "sweep_x": (108, 108),
     "sweep_y": (128, 128),
     "sweep_z": (156, 196),
@@ -57,18 +67,30 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the blast box")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch variant")
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--accuracy", action="store_true")
     return ap.parse_args()
 
 
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("mhd_kernels.hpp", "mhd_lib.hip"):
+        with open(os.path.join(ROOT, "paper_2606_12753_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def run_gpu(wl, precision, steps, warmup, flags):
+    """Warm-up (autotuning included), then `steps` timed steps; returns the
+    time, the final state of box 0 and the launch variant."""
     import torch
     from paper_2606_12753_amd import mhd
-    spec, st = wl.boxes[0], wl.states[0]
     stream = torch.cuda.Stream()
-    sim = mhd.Sim([spec], precision=precision, stream=stream.cuda_stream, flags=flags)
-    sim.set_state(0, st.cons, st.bface, 0.0)
+    sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags)
+    for b, st in enumerate(wl.states):
+        sim.set_state(b, st.cons, st.bface, 0.0)
     sim.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -77,40 +99,54 @@ def run_gpu(wl, precision, steps, warmup, flags):
     sim.step(steps)
     e1.record(stream)
     e1.synchronize()
-    torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    _, t = sim.dt(0)
-    cnt = sim.counters(0)
-    sim.close()
-    return ms, t, cnt
+    state = sim.get_state(0)
+    out = {"ms": ms, "state": state, "variant": sim.tuning(), "counters": sim.counters(0),
+           "sim": sim}
+    return out
 
 
-def kernel_times(wl, precision, steps):
-    """Average launch duration of every kernel kind, from HIP events recorded
-    around each launch on the library's stream (timing pass, same launch
-    configuration, no graph)."""
+def kernel_times(wl, precision, steps, variant):
+    """Average launch duration of every kernel kind: HIP events recorded
+    around each launch on the library's stream (timing pass with the same
+    kernels and launch shapes; steps are not graph-replayed here)."""
     import torch
     from paper_2606_12753_amd import mhd
-    spec, st = wl.boxes[0], wl.states[0]
-    stream = torch.cuda.Stream()
-    sim = mhd.Sim([spec], precision=precision, stream=stream.cuda_stream,
-                  flags=mhd.MHD_F_TIMING)
-    sim.set_state(0, st.cons, st.bface, 0.0)
-    sim.step(2)
-    sim.kernel_times(reset=True)
-    sim.step(steps)
-    kt = sim.kernel_times()
-    sim.close()
+    os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
+    try:
+        stream = torch.cuda.Stream()
+        sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
+                      flags=mhd.MHD_F_TIMING)
+        for b, st in enumerate(wl.states):
+            sim.set_state(b, st.cons, st.bface, 0.0)
+        sim.step(2)
+        sim.kernel_times(reset=True)
+        sim.step(steps)
+        kt = sim.kernel_times()
+        sim.close()
+    finally:
+        del os.environ["MHD_VARIANT"]
     return {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in kt.items()}
 
 
-def roofline(kt, cells, table):
-    # dominant kernel = largest share of the step time
-    per_step = {k: kt[k][0] * (2 if k.startswith(("sweep", "ct")) else 1) for k in table}
+def roofline(kt, cells, table, variant, precision):
+    per_step = {k: kt[k][0] * kt[k][1] for k in table}
     dom = max(per_step, key=per_step.get)
     bytes_per_launch = 0.5 * (table[dom][0] + table[dom][1]) * cells
     avg_ms = kt[dom][0]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        key = "fp64" if precision == 0 else "mixed"
+        if rec.get("source_sha") == source_sha() and list(rec.get("variant", [])) == list(variant) \
+                and key in rec and dom in rec[key]:
+            k = rec[key][dom]
+            traffic = int((k["fetch_kib"] * rec["scale"]["fetch"] +
+                           k["write_kib"] * rec["scale"]["write"]) * 1024)
+    except (OSError, ValueError, KeyError):
+        traffic = None
     return {
         "kernel": dom,
         "bound": "hbm",
@@ -118,10 +154,41 @@ def roofline(kt, cells, table):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "avg_launch_ms": round(avg_ms, 4),
         "bytes_per_launch": int(bytes_per_launch),
     }
+
+
+def derived(spec, cons, bface):
+    """rho, p and |B| (cell-centred, FP64) and div B of a state."""
+    import numpy as np
+    bx = 0.5 * (bface[0][:, :, :-1] + bface[0][:, :, 1:])
+    by = 0.5 * (bface[1][:, :-1, :] + bface[1][:, 1:, :])
+    bz = 0.5 * (bface[2][:-1, :, :] + bface[2][1:, :, :])
+    rho, mx, my, mz, en = cons
+    b2 = bx * bx + by * by + bz * bz
+    p = (spec.gamma - 1.0) * (en - 0.5 * (mx * mx + my * my + mz * mz) / rho - 0.5 * b2)
+    dx = spec.dx
+    div = ((bface[0][:, :, 1:] - bface[0][:, :, :-1]) / dx[0]
+           + (bface[1][:, 1:, :] - bface[1][:, :-1, :]) / dx[1]
+           + (bface[2][1:, :, :] - bface[2][:-1, :, :]) / dx[2])
+    bmax = max(float(np.max(np.abs(b))) for b in bface)
+    dmax = float(np.max(np.abs(div)))
+    return rho, p, np.sqrt(b2), dmax, dmax * min(dx) / max(bmax, 1e-300)
+
+
+def compare(spec, st64, stmx):
+    import numpy as np
+
+    def rel(a, b):
+        return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+    r64, p64, b64, d64, n64 = derived(spec, st64[0], st64[1])
+    rmx, pmx, bmx, dmx, nmx = derived(spec, stmx[0], stmx[1])
+    return {"rel_l1": {"rho": rel(rmx, r64), "p": rel(pmx, p64), "|B|": rel(bmx, b64)},
+            "max_divB_abs": {"fp64": d64, "mixed": dmx},
+            "max_divB_norm": {"fp64": n64, "mixed": nmx}}
 
 
 def cpu_baseline(n, steps):
@@ -138,8 +205,40 @@ def cpu_baseline(n, steps):
         "unit": "Mcell-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"blast recipe {n}^3, {steps} steps, serial FP64 oracle ({el:.1f} s)",
+        "sample": f"blast recipe at {n}^3 (same seed and set-up, smaller grid), {steps} steps, "
+                  f"serial FP64 oracle, {el:.1f} s",
     }
+
+
+def accuracy(flags):
+    """Mixed against FP64 on the full-size secondary workloads."""
+    from paper_2606_12753_amd import mhd, workloads
+    for name, kw in (("turbulence_3d", {}), ("ensemble", {}), ("kelvin_helmholtz", {})):
+        print(f"# accuracy: building {name}", file=sys.stderr, flush=True)
+        wl = workloads.by_name(name, **kw)
+        steps = wl.steps
+        res = {}
+        for prec in (mhd.MHD_FP64, mhd.MHD_MIXED):
+            print(f"# accuracy: {name} precision {prec}", file=sys.stderr, flush=True)
+            r = run_gpu(wl, prec, steps - 1, 1, flags)
+            sim = r["sim"]
+            states = [sim.get_state(b) for b in range(len(wl.boxes))]
+            sim.close()
+            res[prec] = (r["ms"], states, r["variant"])
+        out = {"workload": name, "cells": wl.cells, "steps": steps, "boxes": len(wl.boxes)}
+        for prec, key in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
+            ms = res[prec][0]
+            out[key] = {"Mcell_updates_per_s": round(wl.cells * (steps - 1) / (ms * 1e-3) / 1e6, 1),
+                        "variant": res[prec][2]}
+        out["speedup"] = round(res[mhd.MHD_FP64][0] / res[mhd.MHD_MIXED][0], 3)
+        # error of the mixed run per box, worst box reported
+        worst = None
+        for b, spec in enumerate(wl.boxes):
+            c = compare(spec, res[mhd.MHD_FP64][1][b], res[mhd.MHD_MIXED][1][b])
+            if worst is None or max(c["rel_l1"].values()) > max(worst["rel_l1"].values()):
+                worst = c
+        out.update(worst)
+        print(json.dumps(out), flush=True)
 
 
 def main():
@@ -154,26 +253,38 @@ def main():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    flags = mhd.MHD_F_GRAPH | (0 if a.no_tune else mhd.MHD_F_AUTOTUNE)
+    if a.accuracy:
+        accuracy(flags)
+        return
     print(f"# building blast {a.n}^3 input", file=sys.stderr, flush=True)
     wl = workloads.blast_3d(n=a.n)
+    spec = wl.boxes[0]
     cells = wl.cells
-    flags = mhd.MHD_F_GRAPH
     print("# FP64 timed run", file=sys.stderr, flush=True)
-    ms, t, cnt = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags)
+    r64 = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags)
+    r64["sim"].close()
+    ms = r64["ms"]
     value = cells * a.steps / (ms * 1e-3) / 1e6
     print("# FP64 kernel timing pass", file=sys.stderr, flush=True)
-    kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10))
-    roof = roofline(kt, cells, BYTES_FP64)
+    kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10), r64["variant"])
+    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64)
     mixed = None
     if not a.no_mixed:
         print("# mixed timed run", file=sys.stderr, flush=True)
-        ms_m, t_m, _ = run_gpu(wl, mhd.MHD_MIXED, a.steps, a.warmup, flags)
-        ktm = kernel_times(wl, mhd.MHD_MIXED, min(a.steps, 10))
+        rmx = run_gpu(wl, mhd.MHD_MIXED, a.steps, a.warmup, flags)
+        rmx["sim"].close()
+        ktm = kernel_times(wl, mhd.MHD_MIXED, min(a.steps, 10), rmx["variant"])
+        acc = compare(spec, r64["state"], rmx["state"])
         mixed = {
-            "value": round(cells * a.steps / (ms_m * 1e-3) / 1e6, 2),
-            "ms_per_step": round(ms_m / a.steps, 4),
-            "speedup_vs_fp64": round(ms / ms_m, 3),
-            "roofline": roofline(ktm, cells, BYTES_MIXED),
+            "value": round(cells * a.steps / (rmx["ms"] * 1e-3) / 1e6, 2),
+            "ms_per_step": round(rmx["ms"] / a.steps, 4),
+            "speedup_vs_fp64": round(ms / rmx["ms"], 3),
+            "accuracy_vs_fp64": acc,
+            "after_steps": a.warmup + a.steps,
+            "variant": rmx["variant"],
+            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED),
+            "kernels_ms": {k: round(v[0], 4) for k, v in ktm.items() if v[1]},
         }
     cpu = None
     if not a.no_cpu:
@@ -193,12 +304,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3",
-                   "cells": cells, "launch": "hipGraph replay per step"},
+                   "cells": cells, "launch": "hipGraph replay per step",
+                   "variant": r64["variant"]},
         "roofline": roof,
-        "kernels_ms": {k: round(v[0], 4) for k, v in kt.items()},
+        "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "mixed": mixed,
-        "counters": cnt,
+        "counters": r64["counters"],
         "cpu_baseline": cpu,
+        "source_sha": source_sha(),
     }
     print(json.dumps(line), flush=True)
 

@@ -4,7 +4,9 @@ source tree).
 
 FP64 arithmetic is compiled without FMA contraction: every kernel then
 evaluates each formula in the written order, so results do not depend on the
-tiling or launch shape.  Packed-FP32 instructions are disabled.
+tiling or launch shape and equal the oracle's.  The mixed path's FP32
+kernels are compiled in their own unit with contraction.  Packed-FP32
+instructions are disabled.
 """
 import os
 import subprocess
@@ -12,25 +14,41 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhd355.so")
-SOURCES = [os.path.join(CSRC, "mhd_lib.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "mhd_kernels.hpp"),
-                  os.path.join(os.path.dirname(HERE), "include", "mhd.h")]
+# (source, extra flags): the FP64 kernels and the host runtime are built
+# without FMA contraction (bit-exact with the oracle); the mixed path's FP32
+# kernels with contraction.
+UNITS = [
+    (os.path.join(CSRC, "mhd_lib.hip"), ["-ffp-contract=off"]),
+    (os.path.join(CSRC, "mhd_fp32.hip"), ["-ffp-contract=fast"]),
+]
+SOURCES = [u[0] for u in UNITS]
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("mhd_kernels.hpp", "mhd_step.hpp")] + \
+    [os.path.join(os.path.dirname(HERE), "include", "mhd.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=off",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-o", LIB + ".tmp"] + SOURCES
+    objs = []
+    for src, fl in UNITS:
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + FLAGS + fl + list(extra or []) + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

@@ -1113,7 +1113,7 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
 }
 
 // CFL rate of every cell of state s, reduced to one max per tile
-__global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
+static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
     const int bi = find_box(L.base + kLAM * (L.nboxes + 1), L.nboxes, tile);
     const Box& b = L.boxes[bi];
@@ -1136,7 +1136,7 @@ __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
 // One workgroup per box: max of the tile partials -> time step.  mode 0:
 // step (clamp to t_stop, advance t); mode 1: query (dt of the current state
 // into scal[3]).  npart: kind whose tiles wrote the partials.
-__global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
+static __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
   const Box& b = boxes[blockIdx.x];
   double m = 0.0;
   for (int t = threadIdx.x; t < b.ntile[kind]; t += kTPB) {
@@ -1164,7 +1164,7 @@ __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kin
 
 // Periodic-face check of a caller array in the boundary layout: sets *bad
 // when face n differs from face 0 anywhere along axis d.
-__global__ __launch_bounds__(kTPB) void k_check_periodic(const double* a, int d, int nx, int ny,
+static __global__ __launch_bounds__(kTPB) void k_check_periodic(const double* a, int d, int nx, int ny,
                                                          int nz, int* bad) {
   // boundary layout extents: n+1 along d
   const int ex = nx + (d == 0), ey = ny + (d == 1);

@@ -18,6 +18,7 @@
 // dt and t never leave the device between steps.
 #include "../../include/mhd.h"
 #include "mhd_kernels.hpp"
+#include "mhd_step.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -32,6 +33,9 @@
 
 using mhd::Box;
 using mhd::kTPB;
+
+// defined in mhd_fp32.hip (FP32 kernels of the mixed path)
+int mhd_enqueue_fp32(const mhd::StepCtx& sc);
 
 namespace {
 
@@ -277,95 +281,30 @@ int fail(mhd_ctx* c, int code, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));          \
   } while (0)
 
-template <typename real>
-void launch_x(int wpe, dim3 g, hipStream_t st, const mhd::Launch& L) {
-  switch (wpe) {
-    case 3: hipLaunchKernelGGL((mhd::k_sweep_x<real, 3>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((mhd::k_sweep_x<real, 4>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((mhd::k_sweep_x<real, 1>), g, dim3(kTPB), 0, st, L); break;
-  }
-}
-
-// march variants: 1 = unconstrained registers, update inputs prefetched;
-// 2 = unconstrained, no prefetch; 3, 4 = at least 3 / 4 waves per SIMD, no
-// prefetch; 5, 6, 7 = window in LDS with (5) no register constraint and
-// prefetch, (6) no constraint and no prefetch, (7) at least 3 waves per
-// SIMD and no prefetch
-template <typename real, int D>
-void launch_march(int var, dim3 g, hipStream_t st, const mhd::Launch& L) {
-  using mhd::k_sweep_march;
-  switch (var) {
-    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1>), g, dim3(kTPB), 0, st, L); break;
-    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1>), g, dim3(kTPB), 0, st, L); break;
-    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
-  }
-}
-
-template <typename real>
+// one step's launches (csrc/mhd_step.hpp); the FP32 kernels of the mixed
+// path are instantiated in mhd_fp32.hip, built with FMA contraction
 int enqueue_step_t(mhd_ctx* c) {
-  mhd::Launch L;
-  L.boxes = c->dbox;
-  L.base = c->dbase;
-  L.nboxes = (int)c->boxes.size();
-  L.lam = 0;
-  auto grid = [&](int kind) {
-    int g = c->total[kind];
-    if (c->grid[kind] > 0 && c->grid[kind] < g) g = c->grid[kind];
-    return g < 1 ? 1 : g;
-  };
+  mhd::StepCtx sc;
+  sc.L.boxes = c->dbox;
+  sc.L.base = c->dbase;
+  sc.L.nboxes = (int)c->boxes.size();
+  sc.L.lam = 0;
+  sc.L.stage = 0;
+  sc.L.ntiles = 0;
+  sc.total = c->total;
+  sc.grid = c->grid;
+  sc.var_x = c->var_x;
+  sc.var_m = c->var_m;
+  sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
-  int slot = 0;
-  // event pair around each launch in timing mode
-  auto mark = [&](int kind, bool before) {
-    if (!timing) return;
-    if (before) {
-      c->ev_kind[slot] = kind;
-      (void)hipEventRecord(c->ev[2 * slot], c->stream);
-    } else {
-      (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
-      slot++;
-    }
-  };
-  for (int s = 0; s < 2; s++) {
-    L.stage = s;
-    // stage 1's x sweep also reduces the CFL rate of the start-of-step state
-    L.lam = s == 0;
-    L.ntiles = c->total[mhd::kXS];
-    mark(MHD_K_SWEEP_X, true);
-    launch_x<real>(c->var_x, dim3(grid(mhd::kXS)), c->stream, L);
-    mark(MHD_K_SWEEP_X, false);
-    L.lam = 0;
-    if (s == 0) {
-      mark(MHD_K_DT, true);
-      hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 0,
-                         (int)mhd::kXS);
-      mark(MHD_K_DT, false);
-    }
-    L.ntiles = c->total[mhd::kYS];
-    mark(MHD_K_SWEEP_Y, true);
-    launch_march<real, 1>(c->var_m, dim3(grid(mhd::kYS)), c->stream, L);
-    mark(MHD_K_SWEEP_Y, false);
-    L.ntiles = c->total[mhd::kZS];
-    mark(MHD_K_SWEEP_Z, true);
-    launch_march<real, 2>(c->var_m, dim3(grid(mhd::kZS)), c->stream, L);
-    mark(MHD_K_SWEEP_Z, false);
-    L.ntiles = c->total[mhd::kCTE];
-    mark(MHD_K_CT_EDGE, true);
-    hipLaunchKernelGGL(mhd::k_ct_edge<real>, dim3(grid(mhd::kCTE)), dim3(kTPB), 0, c->stream, L);
-    mark(MHD_K_CT_EDGE, false);
-    L.ntiles = c->total[mhd::kCTF];
-    mark(MHD_K_CT_FACE, true);
-    hipLaunchKernelGGL(mhd::k_ct_face<real>, dim3(grid(mhd::kCTF)), dim3(kTPB), 0, c->stream, L);
-    mark(MHD_K_CT_FACE, false);
-  }
+  sc.ev = timing ? c->ev.data() : nullptr;
+  sc.ev_kind = timing ? c->ev_kind.data() : nullptr;
+  const int slots = c->precision == MHD_FP64 ? mhd::enqueue_step_kernels<double>(sc)
+                                             : mhd_enqueue_fp32(sc);
   HIPCHK(c, hipGetLastError());
   if (timing) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < slot; k++) {
+    for (int k = 0; k < slots; k++) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
       c->kms[c->ev_kind[k]] += ms;
@@ -375,11 +314,9 @@ int enqueue_step_t(mhd_ctx* c) {
   return MHD_OK;
 }
 
-constexpr int kLaunchesPerStep = 11;
+constexpr int kLaunchesPerStep = mhd::kLaunchesPerStep;
 
-int enqueue_step(mhd_ctx* c) {
-  return c->precision == MHD_FP64 ? enqueue_step_t<double>(c) : enqueue_step_t<float>(c);
-}
+int enqueue_step(mhd_ctx* c) { return enqueue_step_t(c); }
 
 __global__ void k_set_scalar(const Box* boxes, int nboxes, int slot, double v) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;

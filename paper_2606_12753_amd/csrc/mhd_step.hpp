@@ -1,0 +1,109 @@
+// mhd_step.hpp -- the launch sequence of one SSP-RK2 step.
+//
+// Stage 1 and stage 2 each run: the x sweep (stage 1 also reduces the CFL
+// rate of the start-of-step state, and the per-box dt follows), the y and z
+// marches (the z march applies the RK stage combine to the cells), the
+// corner-EMF kernel and the face update (RK stage combine of the faces).
+// Included by the two translation units that instantiate the kernels: the
+// FP64 one (no FMA contraction, results reproducible bit for bit) and the
+// FP32 one of the mixed path (contraction allowed).
+#pragma once
+
+#include "../../include/mhd.h"
+#include "mhd_kernels.hpp"
+
+namespace mhd {
+
+constexpr int kLaunchesPerStep = 11;
+
+struct StepCtx {
+  Launch L;            // boxes, tile table, box count
+  const int* total;    // tiles per kernel kind over all boxes
+  const int* grid;     // persistent grid size per kind (0: one group per tile)
+  int var_x, var_m;    // launch variants of the x sweep and the marches
+  hipStream_t stream;
+  hipEvent_t* ev;      // timing: an event pair per launch, or null
+  int* ev_kind;        // timing: kernel kind of each pair
+};
+
+template <typename real>
+inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
+  switch (wpe) {
+    case 3: hipLaunchKernelGGL((k_sweep_x<real, 3>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_x<real, 4>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_x<real, 1>), g, dim3(kTPB), 0, st, L); break;
+  }
+}
+
+// march variants: 1 = unconstrained registers, update inputs prefetched;
+// 2 = unconstrained, no prefetch; 3, 4 = at least 3 / 4 waves per SIMD, no
+// prefetch; 5, 6, 7 = window in LDS with (5) no register constraint and
+// prefetch, (6) no constraint and no prefetch, (7) at least 3 waves per
+// SIMD and no prefetch
+template <typename real, int D>
+inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
+  switch (var) {
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+  }
+}
+
+// Enqueues one step on sc.stream; returns the number of timed launches.
+template <typename real>
+inline int enqueue_step_kernels(const StepCtx& sc) {
+  Launch L = sc.L;
+  auto grid = [&](int kind) {
+    int g = sc.total[kind];
+    if (sc.grid[kind] > 0 && sc.grid[kind] < g) g = sc.grid[kind];
+    return g < 1 ? 1 : g;
+  };
+  int slot = 0;
+  auto mark = [&](int kind, bool before) {
+    if (!sc.ev) return;
+    if (before) {
+      sc.ev_kind[slot] = kind;
+      (void)hipEventRecord(sc.ev[2 * slot], sc.stream);
+    } else {
+      (void)hipEventRecord(sc.ev[2 * slot + 1], sc.stream);
+      slot++;
+    }
+  };
+  for (int s = 0; s < 2; s++) {
+    L.stage = s;
+    L.lam = s == 0;
+    L.ntiles = sc.total[kXS];
+    mark(MHD_K_SWEEP_X, true);
+    launch_x<real>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+    mark(MHD_K_SWEEP_X, false);
+    L.lam = 0;
+    if (s == 0) {
+      mark(MHD_K_DT, true);
+      hipLaunchKernelGGL(k_dt, dim3(L.nboxes), dim3(kTPB), 0, sc.stream, L.boxes, 0, (int)kXS);
+      mark(MHD_K_DT, false);
+    }
+    L.ntiles = sc.total[kYS];
+    mark(MHD_K_SWEEP_Y, true);
+    launch_march<real, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    mark(MHD_K_SWEEP_Y, false);
+    L.ntiles = sc.total[kZS];
+    mark(MHD_K_SWEEP_Z, true);
+    launch_march<real, 2>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+    mark(MHD_K_SWEEP_Z, false);
+    L.ntiles = sc.total[kCTE];
+    mark(MHD_K_CT_EDGE, true);
+    hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+    mark(MHD_K_CT_EDGE, false);
+    L.ntiles = sc.total[kCTF];
+    mark(MHD_K_CT_FACE, true);
+    hipLaunchKernelGGL(k_ct_face<real>, dim3(grid(kCTF)), dim3(kTPB), 0, sc.stream, L);
+    mark(MHD_K_CT_FACE, false);
+  }
+  return slot;
+}
+
+}  // namespace mhd
