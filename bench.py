@@ -69,17 +69,69 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variant")
     ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--accuracy", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="dispatches for a rocprofv3 --pmc run (calibration copy, then "
+                         "--steps unfused steps of each precision)")
+    ap.add_argument("--variant64", default="1,1,32,0", help="x,m,seg,persistent of the FP64 run")
+    ap.add_argument("--variant-mixed", default="1,1,32,0",
+                    help="x,m,seg,persistent of the mixed run")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic record from two counter-pass runs")
+    ap.add_argument("--fetch-command", default="", help="command of the FETCH_SIZE run")
+    ap.add_argument("--write-command", default="", help="command of the WRITE_SIZE run")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
+                    help="write the kernel-trace summary from a rocprofv3 --kernel-trace "
+                         "--stats run of this script")
+    ap.add_argument("--trace-command", default="", help="command of the kernel-trace run")
     return ap.parse_args()
 
 
+SOURCES = ["csrc/mhd_kernels.hpp", "csrc/mhd_step.hpp", "csrc/mhd_lib.hip", "csrc/mhd_fp32.hip",
+           "build.py"]
+TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_blast_256.md")
+KINDS = ["sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
+COPY_BYTES = 1 << 30  # calibration copy of the counter pass
+
+
 def source_sha() -> str:
+    """Hash of the kernel sources and build flags (counter records are only
+    used while it matches)."""
     h = hashlib.sha256()
-    for f in ("mhd_kernels.hpp", "mhd_lib.hip"):
-        with open(os.path.join(ROOT, "paper_2606_12753_amd", "csrc", f), "rb") as fh:
+    for f in SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_12753_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_name(kind, real, variant):
+    """Demangled name of the kernel a launch variant runs for a kernel kind
+    (x sweep: waves per SIMD; marches: waves per SIMD, prefetch, LDS window)."""
+    x, m = variant[0], variant[1]
+    if kind == "sweep_x":
+        return f"mhd::k_sweep_x<{real}, {x}>"
+    if kind in ("sweep_y", "sweep_z"):
+        wpe, pf, lw = {1: (1, 1, 0), 2: (1, 0, 0), 3: (3, 0, 0), 4: (4, 0, 0), 5: (1, 1, 1),
+                       6: (1, 0, 1), 7: (3, 0, 1)}[m]
+        d = 1 if kind == "sweep_y" else 2
+        return f"mhd::k_sweep_march<{real}, {d}, {wpe}, {pf}, {lw}>"
+    return f"mhd::k_{kind}<{real}>"
+
+
+def kind_of(name):
+    """(precision key, kernel kind) of a demangled kernel name, or None."""
+    for real, key in (("double", "fp64"), ("float", "mixed")):
+        if f"k_sweep_x<{real}," in name:
+            return key, "sweep_x"
+        if f"k_sweep_march<{real}, 1," in name:
+            return key, "sweep_y"
+        if f"k_sweep_march<{real}, 2," in name:
+            return key, "sweep_z"
+        for k in ("ct_edge", "ct_face"):
+            if f"k_{k}<{real}>" in name:
+                return key, k
+    return None
 
 
 def run_gpu(wl, precision, steps, warmup, flags):
@@ -140,12 +192,11 @@ def roofline(kt, cells, table, variant, precision):
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
         key = "fp64" if precision == 0 else "mixed"
-        if rec.get("source_sha") == source_sha() and list(rec.get("variant", [])) == list(variant) \
-                and key in rec and dom in rec[key]:
-            k = rec[key][dom]
-            traffic = int((k["fetch_kib"] * rec["scale"]["fetch"] +
-                           k["write_kib"] * rec["scale"]["write"]) * 1024)
-    except (OSError, ValueError, KeyError):
+        run = rec.get(key, {})
+        if rec.get("source_sha") == source_sha() and list(run.get("variant", [])) == list(variant) \
+                and dom in run.get("kernels", {}):
+            traffic = int(run["kernels"][dom]["bytes"])
+    except (OSError, ValueError, KeyError, TypeError):
         traffic = None
     return {
         "kernel": dom,
@@ -155,6 +206,7 @@ def roofline(kt, cells, table, variant, precision):
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
+        "traffic_over_algorithmic": round(traffic / bytes_per_launch, 3) if traffic else None,
         "avg_launch_ms": round(avg_ms, 4),
         "bytes_per_launch": int(bytes_per_launch),
     }
@@ -210,6 +262,168 @@ def cpu_baseline(n, steps):
     }
 
 
+def parse_variant(text):
+    v = [int(t) for t in text.split(",")]
+    if len(v) != 4:
+        raise SystemExit(f"bench.py: variant {text!r} is not x,m,seg,persistent")
+    return v
+
+
+def counter_pass(a):
+    """Dispatches for one rocprofv3 --pmc run: a plain device copy of 1 GiB
+    (the calibration kernel: its counter reading over its known size gives
+    the counter's scale), then ``--steps`` steps of each precision launched
+    one by one (no graph) with the launch variants given on the command line."""
+    import torch
+    from paper_2606_12753_amd import mhd, workloads
+    torch.cuda.set_device(0)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    print("# counter pass: calibration copies done", file=sys.stderr, flush=True)
+    wl = workloads.blast_3d(n=a.n)
+    for prec, text in ((mhd.MHD_FP64, a.variant64), (mhd.MHD_MIXED, a.variant_mixed)):
+        os.environ["MHD_VARIANT"] = ",".join(str(v) for v in parse_variant(text))
+        try:
+            sim = mhd.Sim(wl.boxes, precision=prec)
+            for b, st in enumerate(wl.states):
+                sim.set_state(b, st.cons, st.bface, 0.0)
+            sim.step(a.steps)
+            torch.cuda.synchronize()
+            print(f"# counter pass: precision {prec} variant {sim.tuning()} done",
+                  file=sys.stderr, flush=True)
+            sim.close()
+        finally:
+            del os.environ["MHD_VARIANT"]
+
+
+def read_counters(path, counter):
+    """Rows (dispatch id, kernel name, value in KiB) of one counter from a
+    rocprofv3 counter_collection.csv."""
+    import csv
+    rows = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def ingest_counters(a):
+    """Writes the HBM traffic record from the FETCH_SIZE and WRITE_SIZE runs
+    of the counter pass: the three largest runtime copy dispatches are the
+    1 GiB calibration copies; each counter is scaled by the copy's known size
+    over its reading; per kernel kind, KiB per dispatch averaged over the
+    dispatches of the run (both RK stages)."""
+    fetch_csv, write_csv = a.ingest_counters
+    out = {"workload": f"blast_3d {a.n}^3", "source_sha": source_sha(),
+           "commands": {"fetch": a.fetch_command, "write": a.write_command},
+           "calibration": {"copy_bytes": COPY_BYTES}}
+    per = {}
+    scale = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
+                                ("write", write_csv, "WRITE_SIZE")):
+        rows = read_counters(path, counter)
+        copies = sorted(v for _, k, v in rows if k == "__amd_rocclr_copyBuffer")[-3:]
+        if len(copies) < 3:
+            raise SystemExit(f"bench.py: {path}: calibration copies not found")
+        mean = sum(copies) / 3
+        scale[name] = round(COPY_BYTES / 1024 / mean, 3)
+        out["calibration"][f"{counter}_kib"] = round(mean, 1)
+        for _, k, v in rows:
+            kk = kind_of(k)
+            if kk is None:
+                continue
+            rec = per.setdefault(kk, {"names": set(), "fetch": [], "write": []})
+            rec["names"].add(k)
+            rec[name].append(v)
+    out["scale"] = scale
+    for key, text in (("fp64", a.variant64), ("mixed", a.variant_mixed)):
+        algo = BYTES_FP64 if key == "fp64" else BYTES_MIXED
+        cells = a.n ** 3
+        kernels = {}
+        for kind in KINDS:
+            rec = per.get((key, kind))
+            if not rec or not rec["fetch"] or not rec["write"]:
+                continue
+            f = sum(rec["fetch"]) / len(rec["fetch"])
+            w = sum(rec["write"]) / len(rec["write"])
+            byts = (f * scale["fetch"] + w * scale["write"]) * 1024
+            alg = 0.5 * (algo[kind][0] + algo[kind][1]) * cells
+            kernels[kind] = {"kernel": sorted(rec["names"]), "dispatches": len(rec["fetch"]),
+                             "fetch_kib": round(f, 1), "write_kib": round(w, 1),
+                             "bytes": int(byts), "algorithmic_bytes": int(alg),
+                             "ratio": round(byts / alg, 3)}
+        out[key] = {"variant": parse_variant(text), "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({k: {kk: v["ratio"] for kk, v in out[k]["kernels"].items()}
+                      for k in ("fp64", "mixed")}))
+
+
+def summarize_trace(a):
+    """Writes the kernel-trace summary: rocprofv3's per-kernel statistics and,
+    for the dominant kernel of each precision, the average duration of the
+    dispatches with the launch shape the bench chose, beside the bench's own
+    HIP-event average."""
+    import csv
+    tdir, log = a.summarize_trace
+    bench = None
+    with open(log) as fh:
+        for line in fh:
+            if line.startswith('{"metric"'):
+                bench = json.loads(line)
+    if bench is None:
+        raise SystemExit(f"bench.py: no bench line in {log}")
+    stats = []
+    with open(os.path.join(tdir, "run_kernel_stats.csv"), newline="") as fh:
+        for r in csv.DictReader(fh):
+            stats.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                          float(r["Percentage"])))
+    trace = {}
+    with open(os.path.join(tdir, "run_kernel_trace.csv"), newline="") as fh:
+        for r in csv.DictReader(fh):
+            key = (r["Kernel_Name"], int(r["Grid_Size_X"]))
+            trace.setdefault(key, []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [f"# rocprofv3 kernel trace: blast_3d {a.n}^3, FP64 and mixed", "",
+             "Command (from the repository root):", "", "```", a.trace_command, "```", "",
+             f"Kernel source hash {bench.get('source_sha')}; bench line: FP64 "
+             f"{bench['value']} Mcell-updates/s, variant {bench['config']['variant']}"
+             + (f"; mixed {bench['mixed']['value']} Mcell-updates/s, variant "
+                f"{bench['mixed']['variant']}" if bench.get("mixed") else "") + ".", "",
+             "| kernel | calls | avg us | % time |", "|---|---:|---:|---:|"]
+    for name, calls, avg, pct in stats[:16]:
+        lines.append(f"| `{name}` | {calls} | {avg:.1f} | {pct:.2f} |")
+    lines += ["", "Dominant kernel, launches of the bench's launch shape (rocprofv3) against "
+              "the bench's HIP-event average:", "",
+              "| precision | kernel | grid threads | dispatches | rocprofv3 avg us | "
+              "bench avg us | ratio |", "|---|---|---:|---:|---:|---:|---:|"]
+    for key, real, blk in (("fp64", "double", bench), ("mixed", "float", bench.get("mixed"))):
+        if not blk:
+            continue
+        roof = blk["roofline"]
+        variant = blk["config"]["variant"] if key == "fp64" else blk["variant"]
+        want = kernel_name(roof["kernel"], real, variant)
+        groups = [(len(v), g, v) for (n, g), v in trace.items() if want in n]
+        if not groups:
+            lines.append(f"| {key} | `{want}` | - | 0 | - | {roof['avg_launch_ms'] * 1e3:.1f} | - |")
+            continue
+        cnt, grid, durs = max(groups)
+        avg = sum(durs) / cnt
+        bench_us = roof["avg_launch_ms"] * 1e3
+        lines.append(f"| {key} | `{want}` | {grid} | {cnt} | {avg:.1f} | {bench_us:.1f} | "
+                     f"{avg / bench_us:.3f} |")
+    with open(TRACE_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def accuracy(flags):
     """Mixed against FP64 on the full-size secondary workloads."""
     from paper_2606_12753_amd import mhd, workloads
@@ -243,6 +457,12 @@ def accuracy(flags):
 
 def main():
     a = parse()
+    if a.ingest_counters:
+        ingest_counters(a)
+        return
+    if a.summarize_trace:
+        summarize_trace(a)
+        return
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
               "(the multi-GPU path is a design, see DESIGN.md)", file=sys.stderr)
@@ -253,6 +473,9 @@ def main():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.counter_pass:
+        counter_pass(a)
+        return
     flags = mhd.MHD_F_GRAPH | (0 if a.no_tune else mhd.MHD_F_AUTOTUNE)
     if a.accuracy:
         accuracy(flags)

@@ -424,12 +424,14 @@ int trial(mhd_ctx* c, int steps, float* ms) {
 // Coordinate search over the launch variants on the context's own boxes and
 // state: register budget of the x sweep and of the marches, march segment
 // length, persistent grid.  The arithmetic of every variant is the same, so
-// the FP64 results do not depend on the choice.
+// the FP64 results do not depend on the choice.  A candidate replaces the
+// current variant only when it is more than 1% faster, so that timing noise
+// between near-equal variants does not change the choice from run to run.
 int autotune(mhd_ctx* c) {
   if (!c->backup) return fail(c, MHD_E_STATE, "autotune needs a context created with MHD_F_AUTOTUNE");
   int rc = backup_state(c, true);
   if (rc) return rc;
-  const int steps = 2;
+  const int steps = 3;
   float best = 0.f;
   rc = trial(c, steps, &best);
   if (rc) return rc;
@@ -440,7 +442,7 @@ int autotune(mhd_ctx* c) {
     float ms = 0.f;
     r = trial(c, steps, &ms);
     if (r) return r;
-    if (ms < best) {
+    if (ms < 0.99f * best) {
       best = ms;
     } else {
       r = apply(old);
