@@ -79,6 +79,16 @@ struct Box {
 
 enum Kind { kXS = 0, kYS = 1, kZS = 2, kCTE = 3, kCTF = 4, kLAM = 5 };
 
+// The box descriptors and the tile table are written by the host only (never
+// by a kernel), so kernels read them through the constant address space:
+// the compiler may then load their fields with scalar loads once and keep
+// them in scalar registers across the kernels' global stores, instead of
+// re-reading them through the vector memory path after every store.
+typedef const __attribute__((address_space(4))) Box CBox;
+typedef const __attribute__((address_space(4))) int CInt;
+__device__ __forceinline__ CBox& box_at(const Box* boxes, int i) { return ((CBox*)boxes)[i]; }
+__device__ __forceinline__ CInt* table(const int* p) { return (CInt*)p; }
+
 // Per-launch arguments.
 struct Launch {
   const Box* boxes;
@@ -91,7 +101,7 @@ struct Launch {
 
 // ---------------------------------------------------------------- helpers
 
-__device__ __forceinline__ int find_box(const int* base, int nb, int t) {
+__device__ __forceinline__ int find_box(CInt* base, int nb, int t) {
   int lo = 0, hi = nb - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -112,12 +122,12 @@ __device__ __forceinline__ int face_up(int i, int n, int per) {
   return (per && f == n) ? 0 : f;
 }
 
-__device__ __forceinline__ int cidx(const Box& b, int i, int j, int k) {
+__device__ __forceinline__ int cidx(CBox& b, int i, int j, int k) {
   return (k * b.n[1] + j) * b.n[0] + i;
 }
 
 // element of the face array normal to axis d
-__device__ __forceinline__ int fidx(const Box& b, int d, int i, int j, int k) {
+__device__ __forceinline__ int fidx(CBox& b, int d, int i, int j, int k) {
   int ex = d == 0 ? b.nf[0] : b.n[0];
   int ey = d == 1 ? b.nf[1] : b.n[1];
   return (k * ey + j) * ex + i;
@@ -125,7 +135,7 @@ __device__ __forceinline__ int fidx(const Box& b, int d, int i, int j, int k) {
 
 // element of the corner-EMF array along axis c: face extents on the two
 // other axes, cell extent along c
-__device__ __forceinline__ int eidx(const Box& b, int c, int i, int j, int k) {
+__device__ __forceinline__ int eidx(CBox& b, int c, int i, int j, int k) {
   int ex = c == 0 ? b.n[0] : b.nf[0];
   int ey = c == 1 ? b.n[1] : b.nf[1];
   return (k * ey + j) * ex + i;
@@ -213,7 +223,7 @@ struct Addr {
   int c, bx0, bx1, by0, by1, bz0, bz1;
 };
 
-__device__ __forceinline__ Addr addr_of(const Box& b, int i, int j, int k) {
+__device__ __forceinline__ Addr addr_of(CBox& b, int i, int j, int k) {
   Addr a;
   const int nx = b.n[0], ny = b.n[1];
   a.c = (k * ny + j) * nx + i;
@@ -226,7 +236,7 @@ __device__ __forceinline__ Addr addr_of(const Box& b, int i, int j, int k) {
   return a;
 }
 
-__device__ __forceinline__ Raw load_raw(const Box& b, int s, const Addr& a) {
+__device__ __forceinline__ Raw load_raw(CBox& b, int s, const Addr& a) {
   Raw r;
 #pragma unroll
   for (int q = 0; q < kNQ; q++) r.u[q] = ld<double>(b.U[s][q], a.c);
@@ -239,7 +249,7 @@ __device__ __forceinline__ Raw load_raw(const Box& b, int s, const Addr& a) {
   return r;
 }
 
-__device__ __forceinline__ int raw_to_prim(const Box& b, const Raw& r, PrimD& w) {
+__device__ __forceinline__ int raw_to_prim(CBox& b, const Raw& r, PrimD& w) {
   double bx = 0.5 * (r.bf[0] + r.bf[1]);
   double by = 0.5 * (r.bf[2] + r.bf[3]);
   double bz = 0.5 * (r.bf[4] + r.bf[5]);
@@ -247,7 +257,7 @@ __device__ __forceinline__ int raw_to_prim(const Box& b, const Raw& r, PrimD& w)
 }
 
 // primitives of mapped cell (i, j, k) of state s, with the face-averaged field
-__device__ __forceinline__ int load_prim(const Box& b, int s, int i, int j, int k, PrimD& w) {
+__device__ __forceinline__ int load_prim(CBox& b, int s, int i, int j, int k, PrimD& w) {
   return raw_to_prim(b, load_raw(b, s, addr_of(b, i, j, k)), w);
 }
 
@@ -564,7 +574,7 @@ __device__ __forceinline__ void count(unsigned long long* c, int fl) {
 }
 
 // CFL rate of a cell: max over active axes of (|v_d| + c_f,d) / dx_d
-__device__ __forceinline__ double cfl_rate(const Box& b, const PrimD& w) {
+__device__ __forceinline__ double cfl_rate(CBox& b, const PrimD& w) {
   const double v[3] = {w.vx, w.vy, w.vz};
   const double bc[3] = {w.bx, w.by, w.bz};
   double l = 0.0;
@@ -624,9 +634,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   __shared__ real sw[7][kLdsCells];
   const int s = L.stage;
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
-    const int bi = find_box(L.base + kXS * (L.nboxes + 1), L.nboxes, tile);
-    const Box& b = L.boxes[bi];
-    const int lt = tile - L.base[kXS * (L.nboxes + 1) + bi];
+    const int bi = find_box(table(L.base) + kXS * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kXS * (L.nboxes + 1) + bi];
     const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
     const int nrows = ny * nz;
     int W, R, r0, i0;
@@ -811,7 +821,7 @@ struct Window<real, 1> {
 };
 
 template <typename real, int D, int PF, int LW>
-__device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr, int j0, int j1,
+__device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int j0, int j1,
                                              real (*lds)[kTPB]) {
   // (i, tr): x index and the index along the remaining axis (z for D=1, y
   // for D=2); cells [j0, j1) along D, faces j0..j1
@@ -921,7 +931,7 @@ __device__ __forceinline__ void march_column(const Box& b, int s, int i, int tr,
 // inactive axis D: residual from the earlier axes only, face data from the
 // cell (EMF = cell EMF, mass flux = momentum)
 template <typename real, int D>
-__device__ __forceinline__ void inactive_column(const Box& b, int s, int i, int tr) {
+__device__ __forceinline__ void inactive_column(CBox& b, int s, int i, int tr) {
   auto pos = [&](int a, int& ii, int& jj, int& kk) {
     ii = i;
     if (D == 1) { jj = a; kk = tr; } else { jj = tr; kk = a; }
@@ -973,9 +983,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   __shared__ real lds[LW ? 21 : 1][kTPB];
   const int kind = D == 1 ? kYS : kZS;
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
-    const int bi = find_box(L.base + kind * (L.nboxes + 1), L.nboxes, tile);
-    const Box& b = L.boxes[bi];
-    const int lt = tile - L.base[kind * (L.nboxes + 1) + bi];
+    const int bi = find_box(table(L.base) + kind * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kind * (L.nboxes + 1) + bi];
     const int nseg = D == 1 ? b.yseg : b.zseg;
     const int sl = D == 1 ? b.ysl : b.zsl;
     const int seg = lt % nseg;
@@ -1009,9 +1019,9 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
-    const int bi = find_box(L.base + kCTE * (L.nboxes + 1), L.nboxes, tile);
-    const Box& b = L.boxes[bi];
-    const int lt = tile - L.base[kCTE * (L.nboxes + 1) + bi];
+    const int bi = find_box(table(L.base) + kCTE * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
     const int p = lt * kTPB + (int)threadIdx.x;
     const int P = b.nf[0] * b.nf[1] * b.nf[2];
     if (p >= P) continue;
@@ -1073,9 +1083,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
-    const int bi = find_box(L.base + kCTF * (L.nboxes + 1), L.nboxes, tile);
-    const Box& b = L.boxes[bi];
-    const int lt = tile - L.base[kCTF * (L.nboxes + 1) + bi];
+    const int bi = find_box(table(L.base) + kCTF * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kCTF * (L.nboxes + 1) + bi];
     const int p = lt * kTPB + (int)threadIdx.x;
     const int P = b.nf[0] * b.nf[1] * b.nf[2];
     if (p >= P) continue;
@@ -1115,9 +1125,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
 // CFL rate of every cell of state s, reduced to one max per tile
 static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
   for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
-    const int bi = find_box(L.base + kLAM * (L.nboxes + 1), L.nboxes, tile);
-    const Box& b = L.boxes[bi];
-    const int lt = tile - L.base[kLAM * (L.nboxes + 1) + bi];
+    const int bi = find_box(table(L.base) + kLAM * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kLAM * (L.nboxes + 1) + bi];
     const int p = lt * kTPB + (int)threadIdx.x;
     const int N = b.n[0] * b.n[1] * b.n[2];
     double lmax = 0.0;
@@ -1137,7 +1147,7 @@ static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
 // step (clamp to t_stop, advance t); mode 1: query (dt of the current state
 // into scal[3]).  npart: kind whose tiles wrote the partials.
 static __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
-  const Box& b = boxes[blockIdx.x];
+  CBox& b = box_at(boxes, blockIdx.x);
   double m = 0.0;
   for (int t = threadIdx.x; t < b.ntile[kind]; t += kTPB) {
     const double v = b.lam[t];
