@@ -97,7 +97,21 @@ struct Launch {
   int ntiles;       // tiles of this kind over all boxes
   int stage;        // 0: read state 0 (stage 1); 1: read state 1 (stage 2)
   int lam;          // x sweep: also reduce the CFL rate of the owned cells
+  int xcd;          // XCD-grouped tile order (see tile_of)
 };
+
+// Tile order.  The hardware deals the workgroups of a launch round-robin to
+// the eight XCDs, each with its own L2.  With L.xcd set, slot v (of
+// 8*ceil(ntiles/8) slots) takes tile (v mod 8)*C + v/8, C = ceil(ntiles/8):
+// each XCD then works through one contiguous run of tiles, so the
+// neighbouring rows and planes that a tile's stencil reads were mostly
+// fetched into the same L2.  Slots past the last tile do nothing.
+__device__ __forceinline__ int tile_slots(const Launch& L) {
+  return L.xcd ? ((L.ntiles + 7) >> 3) << 3 : L.ntiles;
+}
+__device__ __forceinline__ int tile_of(const Launch& L, int v) {
+  return L.xcd ? (v & 7) * ((L.ntiles + 7) >> 3) + (v >> 3) : v;
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -633,7 +647,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     Launch L) {
   __shared__ real sw[7][kLdsCells];
   const int s = L.stage;
-  for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
     const int bi = find_box(table(L.base) + kXS * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kXS * (L.nboxes + 1) + bi];
@@ -982,7 +998,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
   const int kind = D == 1 ? kYS : kZS;
-  for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
     const int bi = find_box(table(L.base) + kind * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kind * (L.nboxes + 1) + bi];
@@ -1018,7 +1036,9 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 // each axis c whose range contains it (contact-upwinded average).
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
-  for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
     const int bi = find_box(table(L.base) + kCTE * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
@@ -1082,7 +1102,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
 // cyclic, formed in FP64, then the SSP-RK2 stage combine.
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
-  for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
     const int bi = find_box(table(L.base) + kCTF * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kCTF * (L.nboxes + 1) + bi];
@@ -1124,7 +1146,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
 
 // CFL rate of every cell of state s, reduced to one max per tile
 static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
-  for (int tile = blockIdx.x; tile < L.ntiles; tile += gridDim.x) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
     const int bi = find_box(table(L.base) + kLAM * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kLAM * (L.nboxes + 1) + bi];

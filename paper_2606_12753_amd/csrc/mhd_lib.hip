@@ -248,6 +248,7 @@ struct mhd_ctx {
   // launch variant: register budget of the x sweep and of the marches (min
   // waves per SIMD), march segment length, persistent grid
   int var_x = 1, var_m = 1, var_seg = 32, var_pers = 0;
+  int var_xcd = 0;  // XCD-grouped tile order (measured slower on the 256^3 blast)
   int cu_count = 0;
   bool tuned = false;
   char* backup = nullptr;  // state copy for the autotuner's trial steps
@@ -295,6 +296,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.grid = c->grid;
   sc.var_x = c->var_x;
   sc.var_m = c->var_m;
+  sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
   sc.ev = timing ? c->ev.data() : nullptr;
@@ -718,6 +720,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
       c->var_pers = pe;
     }
   }
+  if (const char* v = std::getenv("MHD_XCD")) c->var_xcd = std::atoi(v) != 0;
   rc = build_ctx(c, cfg);
   if (rc) {
     g_create_error = c->err;
@@ -820,6 +823,7 @@ int mhd_dt(mhd_ctx* c, int32_t box, double* dt_next, double* t) {
   L.nboxes = (int)c->boxes.size();
   L.stage = 0;
   L.lam = 0;
+  L.xcd = 0;
   L.ntiles = c->total[mhd::kLAM];
   hipLaunchKernelGGL(mhd::k_lambda, dim3(std::max(1, L.ntiles)), dim3(kTPB), 0, c->stream, L);
   hipLaunchKernelGGL(mhd::k_dt, dim3(L.nboxes), dim3(kTPB), 0, c->stream, c->dbox, 1,

@@ -21,6 +21,7 @@ struct StepCtx {
   const int* total;    // tiles per kernel kind over all boxes
   const int* grid;     // persistent grid size per kind (0: one group per tile)
   int var_x, var_m;    // launch variants of the x sweep and the marches
+  int xcd;             // XCD-grouped tile order
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
   int* ev_kind;        // timing: kernel kind of each pair
@@ -57,8 +58,9 @@ inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
 template <typename real>
 inline int enqueue_step_kernels(const StepCtx& sc) {
   Launch L = sc.L;
+  L.xcd = sc.xcd;
   auto grid = [&](int kind) {
-    int g = sc.total[kind];
+    int g = sc.xcd ? ((sc.total[kind] + 7) >> 3) << 3 : sc.total[kind];
     if (sc.grid[kind] > 0 && sc.grid[kind] < g) g = sc.grid[kind];
     return g < 1 ? 1 : g;
   };
