@@ -158,6 +158,30 @@ def run_gpu(wl, precision, steps, warmup, flags):
     return out
 
 
+def pcie_inclusive(wl, precision, steps, variant):
+    """Cell-updates per second when the state enters from host memory and is
+    read back to host memory (set_state + steps + get_state, host clock)."""
+    import torch
+    from paper_2606_12753_amd import mhd
+    os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
+    try:
+        sim = mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH)
+        st = wl.states[0]
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        sim.step(1)
+        sim.get_state(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        sim.step(steps)
+        sim.get_state(0)
+        el = time.perf_counter() - t0
+        sim.close()
+    finally:
+        del os.environ["MHD_VARIANT"]
+    return round(wl.cells * steps / el / 1e6, 2)
+
+
 def kernel_times(wl, precision, steps, variant):
     """Average launch duration of every kernel kind: HIP events recorded
     around each launch on the library's stream (timing pass with the same
@@ -213,7 +237,8 @@ def roofline(kt, cells, table, variant, precision):
 
 
 def derived(spec, cons, bface):
-    """rho, p and |B| (cell-centred, FP64) and div B of a state."""
+    """rho, p and |B| (cell-centred, FP64) of a state, and max|div B| both
+    absolute and normalised as dx_min * max|div B| / |B|_rms."""
     import numpy as np
     bx = 0.5 * (bface[0][:, :, :-1] + bface[0][:, :, 1:])
     by = 0.5 * (bface[1][:, :-1, :] + bface[1][:, 1:, :])
@@ -225,9 +250,9 @@ def derived(spec, cons, bface):
     div = ((bface[0][:, :, 1:] - bface[0][:, :, :-1]) / dx[0]
            + (bface[1][:, 1:, :] - bface[1][:, :-1, :]) / dx[1]
            + (bface[2][1:, :, :] - bface[2][:-1, :, :]) / dx[2])
-    bmax = max(float(np.max(np.abs(b))) for b in bface)
+    brms = float(np.sqrt(np.mean(b2)))
     dmax = float(np.max(np.abs(div)))
-    return rho, p, np.sqrt(b2), dmax, dmax * min(dx) / max(bmax, 1e-300)
+    return rho, p, np.sqrt(b2), dmax, dmax * min(dx) / max(brms, 1e-300)
 
 
 def compare(spec, st64, stmx):
@@ -492,6 +517,8 @@ def main():
     print("# FP64 kernel timing pass", file=sys.stderr, flush=True)
     kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10), r64["variant"])
     roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64)
+    print("# FP64 PCIe-inclusive run", file=sys.stderr, flush=True)
+    pcie = pcie_inclusive(wl, mhd.MHD_FP64, a.steps, r64["variant"])
     mixed = None
     if not a.no_mixed:
         print("# mixed timed run", file=sys.stderr, flush=True)
@@ -532,6 +559,8 @@ def main():
         "roofline": roof,
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "mixed": mixed,
+        "pcie_inclusive": {"value": pcie, "unit": "Mcell-updates/s",
+                           "what": f"host set_state + {a.steps} steps + host get_state, FP64"},
         "counters": r64["counters"],
         "cpu_baseline": cpu,
         "source_sha": source_sha(),
