@@ -107,15 +107,19 @@ def source_sha() -> str:
 
 def kernel_name(kind, real, variant):
     """Demangled name of the kernel a launch variant runs for a kernel kind
-    (x sweep: waves per SIMD; marches: waves per SIMD, prefetch, LDS window)."""
+    (x sweep: waves per SIMD; marches: waves per SIMD, prefetch, LDS window,
+    LDS ring of the z march)."""
     x, m = variant[0], variant[1]
     if kind == "sweep_x":
         return f"mhd::k_sweep_x<{real}, {x}>"
     if kind in ("sweep_y", "sweep_z"):
-        wpe, pf, lw = {1: (1, 1, 0), 2: (1, 0, 0), 3: (3, 0, 0), 4: (4, 0, 0), 5: (1, 1, 1),
-                       6: (1, 0, 1), 7: (3, 0, 1)}[m]
         d = 1 if kind == "sweep_y" else 2
-        return f"mhd::k_sweep_march<{real}, {d}, {wpe}, {pf}, {lw}>"
+        if d == 1 and m >= 8:
+            m = {8: 2, 9: 6, 10: 7}[m]
+        wpe, pf, lw, cu = {1: (1, 1, 0, 0), 2: (1, 0, 0, 0), 3: (3, 0, 0, 0), 4: (4, 0, 0, 0),
+                           5: (1, 1, 1, 0), 6: (1, 0, 1, 0), 7: (3, 0, 1, 0), 8: (1, 0, 0, 1),
+                           9: (1, 0, 1, 1), 10: (3, 0, 1, 1)}[m]
+        return f"mhd::k_sweep_march<{real}, {d}, {wpe}, {pf}, {lw}, {cu}>"
     return f"mhd::k_{kind}<{real}>"
 
 

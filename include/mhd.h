@@ -150,7 +150,9 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
  * unconstrained registers with the update inputs prefetched ahead of the
  * Riemann solve, 2: unconstrained without prefetch, 3 / 4: at least 3 / 4
  * waves per SIMD without prefetch, 5 / 6 / 7: the sliding window kept in
- * LDS, with prefetch / without / at least 3 waves per SIMD), [2] march
+ * LDS, with prefetch / without / at least 3 waves per SIMD, 8 / 9 / 10:
+ * variants 2 / 6 / 7 whose z march keeps the swept state of its last three
+ * cells in LDS for the RK combine instead of reading it again), [2] march
  * segment length (cells),
  * [3] persistent grid (0/1).
  * The variants differ only in scheduling: FP64 results are identical. */

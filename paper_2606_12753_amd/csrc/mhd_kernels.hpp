@@ -836,9 +836,16 @@ struct Window<real, 1> {
   }
 };
 
-template <typename real, int D, int PF, int LW>
+// CU (z march only): the swept state of the last three cells loaded is kept
+// in a per-lane LDS ring (no sharing between lanes, so no barrier).  It is
+// the state the RK combine reads (U^n in stage 1, U* in stage 2), three
+// faces after the sweep loaded it, when it has usually left L2; the ring
+// saves that second fetch.
+template <typename real, int D, int PF, int LW, int CU>
 __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int j0, int j1,
-                                             real (*lds)[kTPB]) {
+                                             real (*lds)[kTPB], double (*ring)[kTPB]) {
+  constexpr bool kRing = CU && D == 2;
+  const int lane = threadIdx.x;
   // (i, tr): x index and the index along the remaining axis (z for D=1, y
   // for D=2); cells [j0, j1) along D, faces j0..j1
   const int n = b.n[D];
@@ -858,8 +865,14 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
     const St7<real> q0 = rotate<real>(w, D);
     raw_to_prim(b, load_raw(b, s, addr_at(j0 - 1)), w);
     const St7<real> q1 = rotate<real>(w, D);
-    raw_to_prim(b, load_raw(b, s, addr_at(j0)), w);
+    const Raw r2 = load_raw(b, s, addr_at(j0));
+    raw_to_prim(b, r2, w);
     const St7<real> q2 = rotate<real>(w, D);
+    if constexpr (kRing) {
+      const int slot = j0 % 3;
+#pragma unroll
+      for (int q = 0; q < kNQ; q++) ring[slot * kNQ + q][lane] = r2.u[q];
+    }
     St7<real> dm1;
 #pragma unroll
     for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
@@ -874,15 +887,20 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
   const int cstride = fstride;
   const int cbase = D == 1 ? (tr * b.n[1]) * b.n[0] + i : tr * b.n[0] + i;
   const double dt = D == 2 ? b.scal[0] : 0.0;
+  int cw = (j0 + 1) % 3;  // ring slot of cell f+1 at face f
   for (int f = j0; f <= j1; ++f) {
     PrimD w;
     raw_to_prim(b, next, w);
     const St7<real> q3 = rotate<real>(w, D);
+    if constexpr (kRing) {
+#pragma unroll
+      for (int q = 0; q < kNQ; q++) ring[cw * kNQ + q][lane] = next.u[q];
+    }
     if (f < j1) next = load_raw(b, s, addr_at(f + 2));
     // inputs of the cell update: issued before the solve (PF) or after it
     const int cprev = cbase + (f - 1) * cstride;
     double racc[kNQ];
-    double u0v[kNQ], u1v[kNQ];
+    double usw[kNQ], uold[kNQ];  // swept state of cell f-1; U^n in stage 2
     auto load_update_inputs = [&]() {
       if (D == 1) {
         const int f0 = (tr * b.n[1] + (f - 1)) * b.nf[0] + i;
@@ -895,11 +913,15 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
           racc[q] = r;
         }
       } else {
+        const int cr = cw == 2 ? 0 : cw + 1;  // ring slot of cell f-1
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
           racc[q] = ld<double>(b.R[q], cprev);
-          u0v[q] = ld<double>(b.U[0][q], cprev);
-          if (s == 1) u1v[q] = ld<double>(b.U[1][q], cprev);
+          if constexpr (kRing)
+            usw[q] = ring[cr * kNQ + q][lane];
+          else
+            usw[q] = ld<double>(b.U[s][q], cprev);
+          uold[q] = s == 1 ? ld<double>(b.U[0][q], cprev) : 0.0;
         }
       }
     };
@@ -933,14 +955,15 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
         if (D == 1) {
           st<double>(b.R[q], cprev, r);
         } else if (s == 0) {
-          st<double>(b.U[1][q], cprev, u0v[q] + dt * r);
+          st<double>(b.U[1][q], cprev, usw[q] + dt * r);
         } else {
-          st<double>(b.U[0][q], cprev, 0.5 * (u0v[q] + (u1v[q] + dt * r)));
+          st<double>(b.U[0][q], cprev, 0.5 * (uold[q] + (usw[q] + dt * r)));
         }
       }
     }
 #pragma unroll
     for (int q = 0; q < kNQ; q++) fprev[q] = fl[q];
+    cw = cw == 2 ? 0 : cw + 1;
   }
 }
 
@@ -993,10 +1016,11 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int i, int tr) {
 
 // PF: prefetch the inputs of the cell update ahead of the Riemann solve
 // (latency hidden, more registers live across the solve)
-template <typename real, int D, int WPE, int PF, int LW>
+template <typename real, int D, int WPE, int PF, int LW, int CU>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
+  __shared__ double ring[CU ? 3 * kNQ : 1][kTPB];
   const int kind = D == 1 ? kYS : kZS;
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
     const int tile = tile_of(L, v);
@@ -1017,7 +1041,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW>(b, L.stage, i, tr, j0, j1, lds);
+      march_column<real, D, PF, LW, CU>(b, L.stage, i, tr, j0, j1, lds, ring);
     } else {
       inactive_column<real, D>(b, L.stage, i, tr);
     }

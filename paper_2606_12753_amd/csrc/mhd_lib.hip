@@ -456,7 +456,7 @@ int autotune(mhd_ctx* c) {
   auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
   auto set_seg = [&](int v) { return apply_tiling(c, v); };
   auto set_pers = [&](int v) { set_persistent(c, v); return MHD_OK; };
-  for (int v : {2, 3, 5, 6, 7})
+  for (int v : {2, 3, 5, 6, 7, 8, 9, 10})
     if ((rc = try_var(&c->var_m, v, set_m))) return rc;
   for (int v : {3, 4})
     if ((rc = try_var(&c->var_x, v, set_x))) return rc;
@@ -713,7 +713,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     // "x,m,seg,persistent": fixed launch variant (tests, experiments)
     int x = 1, m = 1, sg = 32, pe = 0;
     if (std::sscanf(v, "%d,%d,%d,%d", &x, &m, &sg, &pe) == 4 && (x == 1 || x == 3 || x == 4) &&
-        (m >= 1 && m <= 7) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
+        (m >= 1 && m <= 10) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
       c->var_x = x;
       c->var_m = m;
       c->var_seg = sg;

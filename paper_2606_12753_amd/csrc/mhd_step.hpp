@@ -40,17 +40,32 @@ inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
 // 2 = unconstrained, no prefetch; 3, 4 = at least 3 / 4 waves per SIMD, no
 // prefetch; 5, 6, 7 = window in LDS with (5) no register constraint and
 // prefetch, (6) no constraint and no prefetch, (7) at least 3 waves per
-// SIMD and no prefetch
+// SIMD and no prefetch; 8, 9, 10 = variants 2, 6, 7 with the z march's
+// swept state kept in an LDS ring for the RK combine (the y march has no
+// combine and runs 2, 6, 7)
 template <typename real, int D>
 inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
+  if (D == 1 && var >= 8) var = var == 8 ? 2 : var == 9 ? 6 : 7;
   switch (var) {
-    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1>), g, dim3(kTPB), 0, st, L); break;
-    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1>), g, dim3(kTPB), 0, st, L); break;
-    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 8:
+      if constexpr (D == 2)
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1>), g, dim3(kTPB), 0, st, L);
+      break;
+    case 9:
+      if constexpr (D == 2)
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1>), g, dim3(kTPB), 0, st, L);
+      break;
+    case 10:
+      if constexpr (D == 2)
+        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1>), g, dim3(kTPB), 0, st, L);
+      break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
