@@ -49,11 +49,11 @@ BYTES_FP64 = {
     "ct_edge": (120, 120),
     "ct_face": (72, 96),
 }
-# mixed path: FP64 state and residual, FP32 face fluxes, EMFs, mass fluxes
+# mixed path: FP64 state, FP32 face fluxes, EMFs, mass fluxes and residual
 BYTES_MIXED = {
     "sweep_x": (108, 108),
-    "sweep_y": (128, 128),
-    "sweep_z": (156, 196),
+    "sweep_y": (108, 108),
+    "sweep_z": (136, 176),
     "ct_edge": (60, 60),
     "ct_face": (60, 84),
 }

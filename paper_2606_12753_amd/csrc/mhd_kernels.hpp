@@ -32,9 +32,9 @@
 // be smaller than the tile count (persistent grid-stride loop).
 //
 // The arithmetic type `real` is double (FP64 path) or float (mixed path:
-// FP32 reconstruction, Riemann solver, face fluxes and EMFs; the state, the
-// primitive recovery, the flux differences and residual, the RK
-// accumulation, the face-field curl and the time step stay FP64).  In
+// FP32 reconstruction, Riemann solver, face fluxes, EMFs and the stored
+// stage residual; the state, the primitive recovery, the flux differences,
+// the RK accumulation, the face-field curl and the time step stay FP64).  In
 // FP64 every operation is written in the order of the method's defining
 // formulas and the library is built without FMA contraction, so that the
 // result does not depend on tiling or launch shape.
@@ -64,9 +64,11 @@ struct Box {
   void* FX[kNQ];      // hydro flux on x faces
   void* EF[3][2];     // EMF (E_t1, E_t2) on the faces normal to each axis
   void* MF[3];        // mass flux for the CT upwinding, per face direction
-  double* R[kNQ];     // cell residual (FP64 in both paths: the flux
-                      // differences telescope exactly, so the update
-                      // conserves to FP64 rounding)
+  void* R[kNQ];       // residual of the x and y fluxes, from the y march to
+                      // the z march: formed in FP64 from the face fluxes,
+                      // stored in the arithmetic type of the path (the
+                      // mixed path rounds it to FP32 once; the RK combine
+                      // itself is FP64)
   void* ED[3];        // corner EMF along each axis
   double* lam;        // per-tile max CFL rate (length: max(x tiles, cell tiles))
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
@@ -916,7 +918,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
         const int cr = cw == 2 ? 0 : cw + 1;  // ring slot of cell f-1
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
-          racc[q] = ld<double>(b.R[q], cprev);
+          racc[q] = (double)ld<real>(b.R[q], cprev);
           if constexpr (kRing)
             usw[q] = ring[cr * kNQ + q][lane];
           else
@@ -953,7 +955,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
       for (int q = 0; q < kNQ; q++) {
         const double r = racc[q] - ((double)fl[q] - (double)fprev[q]) * idxD;
         if (D == 1) {
-          st<double>(b.R[q], cprev, r);
+          st<real>(b.R[q], cprev, (real)r);
         } else if (s == 0) {
           st<double>(b.U[1][q], cprev, usw[q] + dt * r);
         } else {
@@ -998,13 +1000,13 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int i, int tr) {
       double r = 0.0;
       if (b.act[0])
         r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) * b.idx[0];
-      st<double>(b.R[q], c, r);
+      st<real>(b.R[q], c, (real)r);
     }
   } else {
     const double dt = b.scal[0];
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
-      double r = ld<double>(b.R[q], c);
+      double r = (double)ld<real>(b.R[q], c);
       if (s == 0)
         st<double>(b.U[1][q], c, ld<double>(b.U[0][q], c) + dt * r);
       else

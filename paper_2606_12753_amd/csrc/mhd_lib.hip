@@ -191,7 +191,7 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs) {
   s += 3 * align_up(g.N * rs);                      // Ec
   s += mhd::kNQ * align_up(g.F[0] * rs);            // FX
   for (int d = 0; d < 3; d++) s += 3 * align_up(g.F[d] * rs);  // EF x2 + MF
-  s += mhd::kNQ * align_up(g.N * 8);                // R (FP64)
+  s += mhd::kNQ * align_up(g.N * rs);               // R
   for (int c = 0; c < 3; c++) s += align_up(g.E[c] * rs);  // ED
   s += align_up((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8);  // lam
   s += align_up(4 * 8);                             // scal
@@ -530,7 +530,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
       b.EF[d][1] = take(g.F[d] * rs);
       b.MF[d] = take(g.F[d] * rs);
     }
-    for (int q = 0; q < mhd::kNQ; q++) b.R[q] = reinterpret_cast<double*>(take(g.N * 8));
+    for (int q = 0; q < mhd::kNQ; q++) b.R[q] = take(g.N * rs);
     for (int cc = 0; cc < 3; cc++) b.ED[cc] = take(g.E[cc] * rs);
     b.lam = reinterpret_cast<double*>(
         take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));

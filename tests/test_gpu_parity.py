@@ -265,11 +265,17 @@ def test_random_3d_mixed():
     for name, a, b in (("rho", g[0][0], o[0][0]), ("p", gp, op), ("|B|", gb, obm)):
         assert rel_l1(a, b) <= TOLMIX, name
     assert divb_norm(spec, g[1])[0] <= 1e-12
-    # conserved totals are accumulated in FP64 in both paths
+    # Conservation: the flux differences and the RK accumulation are FP64;
+    # the stored stage residual is rounded to FP32 once per stage (2^-24
+    # relative).  A stable stage changes a cell by at most a few times its
+    # neighbours' magnitude, so the drift of a total over `steps` steps is
+    # bounded by 2 stages x steps x 4 x 2^-24 x sum|U|.
+    steps = 10
     for q in range(5):
         s0 = math.fsum(wl.states[0].cons[q].ravel())
         s1 = math.fsum(g[0][q].ravel())
-        assert abs(s1 - s0) <= 1e-12 * math.fsum(np.abs(wl.states[0].cons[q]).ravel())
+        scale = math.fsum(np.abs(wl.states[0].cons[q]).ravel())
+        assert abs(s1 - s0) <= 2 * steps * 4 * 2.0 ** -24 * scale, q
 
 
 # ---------------------------------------------------------------- full size
