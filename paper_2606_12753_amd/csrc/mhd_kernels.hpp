@@ -1198,11 +1198,22 @@ static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
 // into scal[3]).  npart: kind whose tiles wrote the partials.
 static __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
   CBox& b = box_at(boxes, blockIdx.x);
-  double m = 0.0;
-  for (int t = threadIdx.x; t < b.ntile[kind]; t += kTPB) {
-    const double v = b.lam[t];
-    if (v > m) m = v;
+  const int n = b.ntile[kind];
+  // eight independent loads in flight per lane (a 256^3 box has 65536
+  // partials: 256 per lane)
+  double mm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t0 = threadIdx.x; t0 < n; t0 += 8 * kTPB) {
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int t = t0 + u * kTPB;
+      const double v = t < n ? b.lam[t] : 0.0;
+      if (v > mm[u]) mm[u] = v;
+    }
   }
+  double m = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; u++)
+    if (mm[u] > m) m = mm[u];
   m = block_max(m);
   if (threadIdx.x == 0) {
     double dt = b.cfl / m;
