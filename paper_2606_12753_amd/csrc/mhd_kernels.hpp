@@ -1199,16 +1199,19 @@ static __global__ __launch_bounds__(kTPB) void k_lambda(Launch L) {
 static __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, int kind) {
   CBox& b = box_at(boxes, blockIdx.x);
   const int n = b.ntile[kind];
-  // eight independent loads in flight per lane (a 256^3 box has 65536
-  // partials: 256 per lane)
+  // 32 independent loads in flight per lane (a 256^3 box has 65536
+  // partials: 256 per lane, so eight round trips)
   double mm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t0 = threadIdx.x; t0 < n; t0 += 8 * kTPB) {
+  for (int t0 = threadIdx.x; t0 < n; t0 += 32 * kTPB) {
+    double v[32];
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
+    for (int u = 0; u < 32; u++) {
       const int t = t0 + u * kTPB;
-      const double v = t < n ? b.lam[t] : 0.0;
-      if (v > mm[u]) mm[u] = v;
+      v[u] = t < n ? b.lam[t] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < 32; u++)
+      if (v[u] > mm[u & 7]) mm[u & 7] = v[u];
   }
   double m = 0.0;
 #pragma unroll
