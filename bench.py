@@ -123,6 +123,13 @@ def kernel_name(kind, real, variant):
     return f"mhd::k_{kind}<{real}>"
 
 
+def launch_key(kind, real, variant):
+    """What fixes a kernel's code and launch shape: its instance, the march
+    segment length (marches only) and the persistent grid."""
+    seg = f"|seg={variant[2]}" if kind in ("sweep_y", "sweep_z") else ""
+    return f"{kernel_name(kind, real, variant)}{seg}|persistent={variant[3]}"
+
+
 def kind_of(name):
     """(precision key, kernel kind) of a demangled kernel name, or None."""
     for real, key in (("double", "fp64"), ("float", "mixed")):
@@ -220,10 +227,11 @@ def roofline(kt, cells, table, variant, precision):
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
         key = "fp64" if precision == 0 else "mixed"
-        run = rec.get(key, {})
-        if rec.get("source_sha") == source_sha() and list(run.get("variant", [])) == list(variant) \
-                and dom in run.get("kernels", {}):
-            traffic = int(run["kernels"][dom]["bytes"])
+        real = "double" if precision == 0 else "float"
+        k = rec.get(key, {}).get("kernels", {}).get(dom)
+        if rec.get("source_sha") == source_sha() and k \
+                and k.get("launch") == launch_key(dom, real, variant):
+            traffic = int(k["bytes"])
     except (OSError, ValueError, KeyError, TypeError):
         traffic = None
     return {
@@ -383,7 +391,9 @@ def ingest_counters(a):
             w = sum(rec["write"]) / len(rec["write"])
             byts = (f * scale["fetch"] + w * scale["write"]) * 1024
             alg = 0.5 * (algo[kind][0] + algo[kind][1]) * cells
-            kernels[kind] = {"kernel": sorted(rec["names"]), "dispatches": len(rec["fetch"]),
+            real = "double" if key == "fp64" else "float"
+            kernels[kind] = {"launch": launch_key(kind, real, parse_variant(text)),
+                             "kernel": sorted(rec["names"]), "dispatches": len(rec["fetch"]),
                              "fetch_kib": round(f, 1), "write_kib": round(w, 1),
                              "bytes": int(byts), "algorithmic_bytes": int(alg),
                              "ratio": round(byts / alg, 3)}

@@ -153,6 +153,27 @@ def test_graph_persistent_and_plain_launches_identical():
             assert np.array_equal(a, b), flags
 
 
+@pytest.mark.parametrize("precision", [mhd.MHD_FP64, mhd.MHD_MIXED])
+def test_graph_every_replay_matches_eager(precision):
+    """One step per graph replay, with eager work (state read-back, host
+    synchronisation) between replays: every replay equals the eagerly
+    launched step bit for bit."""
+    wl = W.random_smooth(n=(24, 20, 16), seed=31)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], precision=precision, flags=mhd.MHD_F_GRAPH) as g, \
+            mhd.Sim([spec], precision=precision, flags=0) as e:
+        g.set_state(0, st.cons, st.bface, 0.0)
+        e.set_state(0, st.cons, st.bface, 0.0)
+        for k in range(5):
+            g.step(1)
+            e.step(1)
+            cg, bg, tg = g.get_state(0)
+            ce, be, te = e.get_state(0)
+            assert tg == te, k
+            for a, b in zip(cg + bg, ce + be):
+                assert np.array_equal(a, b), k
+
+
 def test_ensemble_of_uneven_boxes():
     boxes, states = [], []
     for n, seed, bc in [((16, 16, 16), 1, (0, 0, 0)), ((24, 12, 20), 2, (0, 1, 0)),
