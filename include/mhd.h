@@ -77,7 +77,9 @@ extern "C" {
 #define MHD_NKERNELS 7
 
 typedef struct {
-  int32_t n[3];            /* cells per axis; n == 1 makes the axis inactive */
+  int32_t n[3];            /* cells per axis, 1..2^20; n == 1 makes the axis
+                              inactive; at least one axis active; at most
+                              2^30 cells per box */
   double lo[3], hi[3];     /* domain corners; dx = (hi - lo) / n */
   int32_t bc_lo[3], bc_hi[3];
   double gamma;            /* ratio of specific heats (> 1) */

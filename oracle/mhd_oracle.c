@@ -485,6 +485,9 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     if (bc[d] != ORC_BC_PERIODIC && bc[d] != ORC_BC_OUTFLOW) return NULL;
   }
   if (!(gamma > 1.0) || !(cfl > 0.0)) return NULL;
+  /* a box with no axis of more than one cell has no wave speed, so the CFL
+     step is undefined: rejected */
+  if (n[0] == 1 && n[1] == 1 && n[2] == 1) return NULL;
   orc_box *b = (orc_box *)calloc(1, sizeof(orc_box));
   if (!b) return NULL;
   for (d = 0; d < 3; d++) {

@@ -30,9 +30,9 @@ extern "C" {
 
 typedef struct orc_box orc_box;
 
-/* n[3] cells per axis (n==1: inactive axis), lo/hi domain corners, bc[3] per
- * axis (both sides alike), gamma, CFL number, pressure floor.  NULL on bad
- * arguments or out of memory. */
+/* n[3] cells per axis (n==1: inactive axis; at least one axis active), lo/hi
+ * domain corners, bc[3] per axis (both sides alike), gamma, CFL number,
+ * pressure floor.  NULL on bad arguments or out of memory. */
 orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
                      const int bc[3], double gamma, double cfl, double pfloor);
 void orc_box_free(orc_box *b);

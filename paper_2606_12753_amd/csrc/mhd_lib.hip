@@ -95,6 +95,11 @@ int validate_box(const mhd_box& b, std::string& err) {
     err = "box: cfl must be > 0";
     return MHD_E_INVAL;
   }
+  if (b.n[0] == 1 && b.n[1] == 1 && b.n[2] == 1) {
+    // no axis carries a wave: the CFL rate is zero and dt undefined
+    err = "box: at least one axis needs more than one cell";
+    return MHD_E_INVAL;
+  }
   const Geom g = geom_of(b);
   // every cell, face, edge and corner offset is a 32-bit int in the kernels
   const size_t P = (size_t)g.nf[0] * g.nf[1] * g.nf[2];

@@ -110,6 +110,9 @@ def test_orszag_tang_2d_fp64_50_steps():
     ((24, 18, 40), (1, 0, 1)),      # outflow in x and z, two z segments
     ((300, 6, 5), (0, 0, 0)),       # x rows longer than one workgroup
     ((40, 70, 3), (0, 0, 0)),       # ragged y segments
+    ((2, 3, 5), (0, 0, 0)),         # shortest active extents: the stencil wraps
+    ((3, 2, 4), (1, 1, 1)),         # shortest active extents, outflow everywhere
+    ((2, 2, 1), (0, 1, 0)),         # 2D, two cells per active axis
 ])
 def test_random_state_fp64(n, bc):
     wl = W.random_smooth(n=n, seed=sum(n), bc=bc)
@@ -124,6 +127,18 @@ def test_inactive_axes_fp64(axis):
     g = gpu_run(wl, 20)[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 20)
     assert_fp64_parity(g, o, f"cp axis {axis}")
+
+
+def test_zero_steps_leave_the_state_alone():
+    wl = W.random_smooth(n=(12, 10, 8), seed=5)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.25)
+        sim.step(0)
+        cons, bface, t = sim.get_state(0)
+    assert t == 0.25
+    for a, b in zip(cons + bface, list(st.cons) + list(st.bface)):
+        assert np.array_equal(a, b)
 
 
 def test_hll_fallback_and_floor_counters_match():

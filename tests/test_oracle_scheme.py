@@ -42,6 +42,14 @@ def test_uniform_state_bitwise(bc, n):
     assert t > 0
 
 
+def test_box_without_active_axis_rejected():
+    """One cell on every axis: no wave speed, so the CFL step is undefined
+    and the box is refused; one active axis is enough."""
+    with pytest.raises(ValueError):
+        O.OracleBox(W.BoxSpec((1, 1, 1)))
+    O.OracleBox(W.BoxSpec((1, 1, 4))).close()
+
+
 def test_uniform_dt_closed_form():
     rho, v, p, bb = 1.3, (0.3, -0.2, 0.1), 0.7, (0.5, -0.4, 0.25)
     wl = W.uniform(n=(6, 5, 4), rho=rho, v=v, p=p, b=bb, cfl=0.3)
