@@ -96,12 +96,17 @@ COPY_BYTES = 1 << 30  # calibration copy of the counter pass
 
 
 def source_sha() -> str:
-    """Hash of the kernel sources and build flags (counter records are only
-    used while it matches)."""
+    """Hash of the kernel and launch sources and the build flags, comments and
+    whitespace removed (counter records are only used while it matches)."""
+    import re
     h = hashlib.sha256()
     for f in SOURCES:
-        with open(os.path.join(ROOT, "paper_2606_12753_amd", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2606_12753_amd", f)) as fh:
+            text = fh.read()
+        if not f.endswith(".py"):
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

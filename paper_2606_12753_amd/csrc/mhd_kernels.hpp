@@ -18,10 +18,11 @@
 // coalesced, whatever the sweep direction:
 //   * the x sweep stages a row segment of primitives in LDS (one load and one
 //     primitive recovery per cell) and computes one x face per lane;
-//   * the y and z sweeps march each lane along its column: a register window
-//     of four cells slides along the strided axis, so the strided access
-//     never reaches HBM as strided; each new cell is one coalesced row load,
-//     issued one face ahead of its use.
+//   * the y and z sweeps march each lane along its column: a window of two
+//     cells and a limited slope (in registers or in a per-lane LDS column)
+//     slides along the strided axis, so the strided access never reaches
+//     HBM as strided; each new cell is one coalesced row load, issued two
+//     faces ahead of its use.
 // Periodic axes wrap cell indices and store n faces per axis (face n is face
 // 0); outflow axes clamp cell indices (ghost = copy of the boundary cell) and
 // store n+1 faces.  All offsets are 32-bit (a box holds at most 2^30 cells).

@@ -9,7 +9,7 @@
 //     k_sweep_x                x faces (LDS row segments); in stage 1 also
 //                              the CFL rate max-reduction of the state,
 //     (stage 1) k_dt           -> dt, t per box
-//     k_sweep_march<y>         y faces (register-window march), residual
+//     k_sweep_march<y>         y faces (column march), x+y residual
 //     k_sweep_march<z>         z faces, residual, RK stage combine
 //     k_ct_edge                contact-upwinded corner EMFs
 //     k_ct_face                face-field update + RK stage combine
