@@ -79,7 +79,8 @@ extern "C" {
 typedef struct {
   int32_t n[3];            /* cells per axis, 1..2^20; n == 1 makes the axis
                               inactive; at least one axis active; at most
-                              2^30 cells per box */
+                              2^29 cells and 2^29 face positions
+                              (product of the face counts) per box */
   double lo[3], hi[3];     /* domain corners; dx = (hi - lo) / n */
   int32_t bc_lo[3], bc_hi[3];
   double gamma;            /* ratio of specific heats (> 1) */

@@ -25,7 +25,8 @@
 //     faces ahead of its use.
 // Periodic axes wrap cell indices and store n faces per axis (face n is face
 // 0); outflow axes clamp cell indices (ghost = copy of the boundary cell) and
-// store n+1 faces.  All offsets are 32-bit (a box holds at most 2^30 cells).
+// store n+1 faces.  All offsets are 32-bit (a box holds at most 2^29 cells
+// and 2^29 face or corner positions).
 //
 // Every kernel takes a tile table: tiles of all boxes of an ensemble are
 // numbered consecutively and a workgroup finds its box by a binary search of
@@ -161,13 +162,22 @@ __device__ __forceinline__ int eidx(CBox& b, int c, int i, int j, int k) {
 // element access through the global address space (the pointers in Box are
 // generic; naming the address space gives global_load / global_store rather
 // than flat accesses)
+//
+// The element offset is formed as a 32-bit byte offset (every array of a box
+// is below 4 GiB: at most 2^29 elements of 8 bytes), so that the load takes
+// the array base from scalar registers and one 32-bit lane offset, shared by
+// all arrays indexed alike, instead of a 64-bit address per array and lane.
+typedef const __attribute__((address_space(1))) char GChar;
+typedef __attribute__((address_space(1))) char GCharW;
 template <typename T>
 __device__ __forceinline__ T ld(const void* p, int i) {
-  return ((const __attribute__((address_space(1))) T*)p)[i];
+  const unsigned off = (unsigned)i * (unsigned)sizeof(T);
+  return *(const __attribute__((address_space(1))) T*)((GChar*)p + off);
 }
 template <typename T>
 __device__ __forceinline__ void st(void* p, int i, T v) {
-  ((__attribute__((address_space(1))) T*)p)[i] = v;
+  const unsigned off = (unsigned)i * (unsigned)sizeof(T);
+  *(__attribute__((address_space(1))) T*)((GCharW*)p + off) = v;
 }
 
 // reciprocal and square root: IEEE in FP64; hardware reciprocal / square

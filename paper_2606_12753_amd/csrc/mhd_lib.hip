@@ -101,10 +101,11 @@ int validate_box(const mhd_box& b, std::string& err) {
     return MHD_E_INVAL;
   }
   const Geom g = geom_of(b);
-  // every cell, face, edge and corner offset is a 32-bit int in the kernels
+  // the kernels address every cell, face, edge and corner array with a
+  // 32-bit byte offset: at most 2^29 elements of 8 bytes per array
   const size_t P = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
-  if (g.N > ((size_t)1 << 30) || P >= ((size_t)1 << 31)) {
-    err = "box: more than 2^30 cells";
+  if (g.N > ((size_t)1 << 29) || P > ((size_t)1 << 29)) {
+    err = "box: more than 2^29 cells or face positions";
     return MHD_E_INVAL;
   }
   return MHD_OK;

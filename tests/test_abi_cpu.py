@@ -74,7 +74,8 @@ def test_validation_before_device(lib):
         W.BoxSpec((8, 8, 8), bc=(0, 2, 0)),
         W.BoxSpec((1, 1, 1)),                    # no active axis: dt undefined
         W.BoxSpec(((1 << 20) + 1, 2, 1)),        # axis longer than 2^20 cells
-        W.BoxSpec((1024, 1024, 1025)),           # more than 2^30 cells
+        W.BoxSpec((1024, 1024, 513)),            # more than 2^29 cells
+        W.BoxSpec((1024, 1024, 512), bc=(1, 0, 0)),  # 2^29 cells, more face positions
     ]
     for spec in bad_cases:
         with pytest.raises(mhd.MhdError) as ei:
@@ -89,9 +90,9 @@ def test_validation_before_device(lib):
     with pytest.raises(mhd.MhdError) as ei:
         mhd.mhd_workspace_bytes([])
     assert ei.value.code == mhd.MHD_E_INVAL
-    # the largest accepted box: 2^30 cells (periodic), and one active axis
-    big = mhd.mhd_workspace_bytes([W.BoxSpec((1024, 1024, 1024))])
-    assert big > (1 << 30) * 8 * 16
+    # the largest accepted box: 2^29 cells (periodic), and one active axis
+    big = mhd.mhd_workspace_bytes([W.BoxSpec((1024, 1024, 512))])
+    assert big > (1 << 29) * 8 * 16
     assert mhd.mhd_workspace_bytes([W.BoxSpec((1, 1, 7))]) > 0
 
 
