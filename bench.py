@@ -52,7 +52,7 @@ BYTES_FP64 = {
 # mixed path: FP64 state, FP32 face fluxes, EMFs, mass fluxes and residual
 BYTES_MIXED = {
     "sweep_x": (108, 108),
-    "sweep_y": (108, 108),
+    "sweep_y": (116, 116),
     "sweep_z": (136, 176),
     "ct_edge": (60, 60),
     "ct_face": (60, 84),

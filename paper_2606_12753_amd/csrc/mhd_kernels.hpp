@@ -336,9 +336,10 @@ __device__ __forceinline__ void plm(real qm2, real qm1, real q0, real qp1, real&
   qr = q0 - (real)0.5 * d0;
 }
 
+// square of the fast magnetosonic speed along n
 template <typename real>
-__device__ __forceinline__ real fast_speed(real rho, real p, real bn, real bt1, real bt2,
-                                           real gamma) {
+__device__ __forceinline__ real fast_speed_sq(real rho, real p, real bn, real bt1, real bt2,
+                                              real gamma) {
   real ir = rcp(rho);
   real a2 = gamma * p * ir;
   real b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * ir;
@@ -346,7 +347,13 @@ __device__ __forceinline__ real fast_speed(real rho, real p, real bn, real bt1, 
   real s = a2 + b2;
   real disc = s * s - (real)4 * a2 * bn2;
   if (disc < (real)0) disc = (real)0;
-  return sq((real)0.5 * (s + sq(disc)));
+  return (real)0.5 * (s + sq(disc));
+}
+
+template <typename real>
+__device__ __forceinline__ real fast_speed(real rho, real p, real bn, real bt1, real bt2,
+                                           real gamma) {
+  return sq(fast_speed_sq(rho, p, bn, bt1, bt2, gamma));
 }
 
 // total energy of a face-frame state (igm1 = 1/(gamma-1))
@@ -358,16 +365,14 @@ __device__ __forceinline__ real energy(const St7<real>& w, real bn, real igm1) {
          (real)0.5 * bsq;
 }
 
-// physical flux F and conserved vector U of a face-frame state
+// physical flux F and conserved vector U of a face-frame state whose total
+// energy en and total pressure pt are known
 template <typename real>
-__device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real igm1, real* f,
-                                          real* u) {
-  const real rho = w.v[0], vn = w.v[1], vt1 = w.v[2], vt2 = w.v[3], p = w.v[4];
+__device__ __forceinline__ void phys_flux_ep(const St7<real>& w, real bn, real en, real pt,
+                                             real* f, real* u) {
+  const real rho = w.v[0], vn = w.v[1], vt1 = w.v[2], vt2 = w.v[3];
   const real b1 = w.v[5], b2 = w.v[6];
-  real bsq = bn * bn + b1 * b1 + b2 * b2;
-  real pt = p + (real)0.5 * bsq;
   real vb = vn * bn + vt1 * b1 + vt2 * b2;
-  real en = p * igm1 + (real)0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) + (real)0.5 * bsq;
   u[0] = rho;
   u[1] = rho * vn;
   u[2] = rho * vt1;
@@ -382,6 +387,18 @@ __device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real igm1
   f[4] = (en + pt) * vn - bn * vb;
   f[5] = vn * b1 - vt1 * bn;
   f[6] = vn * b2 - vt2 * bn;
+}
+
+// physical flux F and conserved vector U of a face-frame state
+template <typename real>
+__device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real igm1, real* f,
+                                          real* u) {
+  const real p = w.v[4], b1 = w.v[5], b2 = w.v[6];
+  const real rho = w.v[0], vn = w.v[1], vt1 = w.v[2], vt2 = w.v[3];
+  real bsq = bn * bn + b1 * b1 + b2 * b2;
+  real pt = p + (real)0.5 * bsq;
+  real en = p * igm1 + (real)0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) + (real)0.5 * bsq;
+  phys_flux_ep(w, bn, en, pt, f, u);
 }
 
 template <typename real>
@@ -472,9 +489,11 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 template <typename real>
 __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr, real bn,
                                        real gamma, real igm1, real* f, real* fm) {
-  real cfl = fast_speed(wl.v[0], wl.v[4], bn, wl.v[5], wl.v[6], gamma);
-  real cfr = fast_speed(wr.v[0], wr.v[4], bn, wr.v[5], wr.v[6], gamma);
-  real cmax = vmax(cfl, cfr);
+  // max(c_fL, c_fR) as the square root of the larger square: a correctly
+  // rounded square root is monotone, so this is the same value with one
+  // square root fewer
+  real cmax = sq(vmax(fast_speed_sq(wl.v[0], wl.v[4], bn, wl.v[5], wl.v[6], gamma),
+                      fast_speed_sq(wr.v[0], wr.v[4], bn, wr.v[5], wr.v[6], gamma)));
   real umin = vmin(wl.v[1], wr.v[1]);
   real umax = vmax(wl.v[1], wr.v[1]);
   real sl = umin - cmax;
@@ -523,7 +542,8 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
         sa.vb = sel(left, stl.vb, str.vb);
         const real s_out = sel(left, sl, sr);
         real fa[7], ua[7];
-        phys_flux(w, bn, igm1, fa, ua);
+        // the side's total energy and pressure as already formed above
+        phys_flux_ep(w, bn, sel(left, enl, enr), sel(left, ptl, ptr), fa, ua);
         real us[7];
         us[0] = sa.rho;
         us[1] = sa.rho * sm;
