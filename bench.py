@@ -198,6 +198,36 @@ def pcie_inclusive(wl, precision, steps, variant):
     return round(wl.cells * steps / el / 1e6, 2)
 
 
+def stream_bandwidth():
+    """Achievable HBM bandwidth on this GPU for context: a plain device copy
+    (read + write) and an a = b + s*c triad, 1 GiB operands, with torch's own
+    kernels (no part of the MHD path); best of 5, GB/s of compulsory traffic."""
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.ones(n, dtype=torch.float64, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def best(fn, nbytes):
+        fn()
+        ms = []
+        for _ in range(5):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return round(nbytes / (min(ms) * 1e-3) / 1e9, 1)
+
+    out = {"copy_GBs": best(lambda: a.copy_(b), 2 * COPY_BYTES),
+           "triad_GBs": best(lambda: torch.add(b, c, alpha=0.5, out=a), 3 * COPY_BYTES)}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_times(wl, precision, steps, variant):
     """Average launch duration of every kernel kind: HIP events recorded
     around each launch on the library's stream (timing pass with the same
@@ -528,6 +558,8 @@ def main():
     wl = workloads.blast_3d(n=a.n)
     spec = wl.boxes[0]
     cells = wl.cells
+    print("# HBM stream reference", file=sys.stderr, flush=True)
+    stream = stream_bandwidth()
     print("# FP64 timed run", file=sys.stderr, flush=True)
     r64 = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags)
     r64["sim"].close()
@@ -578,6 +610,7 @@ def main():
         "roofline": roof,
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "mixed": mixed,
+        "hbm_stream": stream,
         "pcie_inclusive": {"value": pcie, "unit": "Mcell-updates/s",
                            "what": f"host set_state + {a.steps} steps + host get_state, FP64"},
         "counters": r64["counters"],

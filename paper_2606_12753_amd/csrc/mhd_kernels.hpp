@@ -669,6 +669,25 @@ __device__ __forceinline__ double block_max(double v) {
 
 // ---------------------------------------------------------------- kernels
 
+// Slot q of an x-sweep tile of R rows of width wd starting at row r0 (whose
+// (j, k) are j0, k0): row offset r, offset o in the row, and the row's (j, k).
+// A one-row tile (every box with at least 86 x faces) needs no division.
+__device__ __forceinline__ void tile_slot(int q, int R, int wd, int r0, int ny, int j0, int k0,
+                                          int& r, int& o, int& j, int& k) {
+  if (R == 1) {
+    r = 0;
+    o = q;
+    j = j0;
+    k = k0;
+  } else {
+    r = q / wd;
+    o = q - r * wd;
+    const int row = r0 + r;
+    j = row % ny;
+    k = row / ny;
+  }
+}
+
 // x sweep: row segments staged in LDS; one x face per lane.  Writes the
 // hydro flux, the face EMFs (E_y, E_z), the CT mass flux and the cell EMF of
 // every owned cell; with L.lam also the tile's max CFL rate (stage 1, the
@@ -701,16 +720,15 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       i0 = seg * b.xw;
       W = min(b.xw, b.nf[0] - i0);
     }
+    const int j00 = r0 % ny, k00 = r0 / ny;  // first row of the tile (uniform)
     double lmax = 0.0;
     if (b.act[0]) {
       const int WL = W + 3;
       const int ncell = R * WL;
       for (int sidx = threadIdx.x; sidx < ncell; sidx += kTPB) {
-        const int r = sidx / WL;
-        const int o = sidx - r * WL;
-        const int row = r0 + r;
-        if (row >= nrows) continue;
-        const int j = row % ny, k = row / ny;
+        int r, o, j, k;
+        tile_slot(sidx, R, WL, r0, ny, j00, k00, r, o, j, k);
+        if (r0 + r >= nrows) continue;
         const int i = i0 - 2 + o;
         const int im = map_cell(i, nx, b.per[0]);
         PrimD w;
@@ -736,12 +754,11 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       }
       __syncthreads();
       for (int t = threadIdx.x; t < R * W; t += kTPB) {
-        const int r = t / W;
-        const int f = i0 + (t - r * W);
-        const int row = r0 + r;
-        if (row >= nrows) continue;
-        const int j = row % ny, k = row / ny;
-        const int o = r * WL + (f - i0);
+        int r, fo, j, k;
+        tile_slot(t, R, W, r0, ny, j00, k00, r, fo, j, k);
+        if (r0 + r >= nrows) continue;
+        const int f = i0 + fo;
+        const int o = r * WL + fo;
         St7<real> q[4];
 #pragma unroll
         for (int m = 0; m < 4; m++)
@@ -766,11 +783,10 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     } else {
       // inactive x: the face carries the cell's physical flux (no divergence)
       for (int t = threadIdx.x; t < R * W; t += kTPB) {
-        const int r = t / W;
-        const int f = i0 + (t - r * W);
-        const int row = r0 + r;
-        if (row >= nrows) continue;
-        const int j = row % ny, k = row / ny;
+        int r, fo, j, k;
+        tile_slot(t, R, W, r0, ny, j00, k00, r, fo, j, k);
+        if (r0 + r >= nrows) continue;
+        const int f = i0 + fo;
         const int im = map_cell(f, nx, b.per[0]);
         PrimD w;
         const int fl = load_prim(b, s, im, j, k, w);
