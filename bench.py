@@ -6,9 +6,13 @@ Workload: the 3D magnetised blast wave, 256^3 periodic unit cube (seeded
 one full SSP-RK2 step of the whole box (both stages, every kernel of the
 path); inputs are resident in HBM before the timed region.  The timed region
 is ``--steps`` graph-replayed steps on the library's stream, bracketed by HIP
-events; ``value`` is FP64 cell-updates per second (cells x steps / time).
-The launch variant is chosen by the library's autotuner during the warm-up
-steps (outside the timed region).
+events, repeated ``--repeats`` times (each repeat re-sets the initial state
+and runs ``--warmup`` untimed steps first); ``value`` is FP64 cell-updates per
+second (cells x steps / median time).  The launch variant is chosen by the
+library's autotuner during the first warm-up (outside the timed region).
+``fractions`` gives the step time against the per-direction design's
+algorithmic bytes at 8 TB/s and against the method's compulsory traffic or
+flops.
 
 Also reported on the same line: the mixed-precision rate on the same
 workload and its relative L1 error against the FP64 run after the same step
@@ -64,6 +68,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats (each re-sets the state); the median is reported")
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the blast box")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
@@ -93,6 +99,13 @@ SOURCES = ["csrc/mhd_kernels.hpp", "csrc/mhd_step.hpp", "csrc/mhd_lib.hip", "csr
 TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_blast_256.md")
 KINDS = ["sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 COPY_BYTES = 1 << 30  # calibration copy of the counter pass
+# Floating-point operations of one cell-update (one full SSP-RK2 step of one
+# cell), counted on the oracle by oracle/flopcount.py (+, -, *, /, sqrt one
+# each): blast recipe 3837 at 64^3 and 3700 at 128^3, falling as 1/n with the
+# share of boundary faces, so about 3630 at 256^3.
+FLOPS_PER_CELL_UPDATE = 3630
+FP64_PEAK_FLOPS = 78.6e12
+FP32_PEAK_FLOPS = 157.3e12
 
 
 def source_sha() -> str:
@@ -150,28 +163,44 @@ def kind_of(name):
     return None
 
 
-def run_gpu(wl, precision, steps, warmup, flags):
-    """Warm-up (autotuning included), then `steps` timed steps; returns the
-    time, the final state of box 0 and the launch variant."""
+def run_gpu(wl, precision, steps, warmup, flags, repeats=1):
+    """Per repeat: set the initial state, `warmup` untimed steps (the first
+    repeat's include the autotuner's trials), then `steps` timed steps.
+    Returns the median time, every repeat's time, the final state of box 0
+    and the launch variant."""
     import torch
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
     sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags)
-    for b, st in enumerate(wl.states):
-        sim.set_state(b, st.cons, st.bface, 0.0)
-    sim.step(warmup)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(steps)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1)
+    times = []
+    for _ in range(repeats):
+        for b, st in enumerate(wl.states):
+            sim.set_state(b, st.cons, st.bface, 0.0)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
     state = sim.get_state(0)
-    out = {"ms": ms, "state": state, "variant": sim.tuning(), "counters": sim.counters(0),
-           "sim": sim}
+    ms = sorted(times)[len(times) // 2]
+    out = {"ms": ms, "times": times, "state": state, "variant": sim.tuning(),
+           "counters": sim.counters(0), "sim": sim}
     return out
+
+
+def fractions(ms_per_step, cells, table, peak_flops):
+    """Roofline fractions of a whole step: the per-direction design's
+    algorithmic bytes (every kernel, both stages) at 8 TB/s, and the method's
+    compulsory state traffic (320 B per cell-update) or its flops, whichever
+    bounds, over the measured step time."""
+    t = ms_per_step * 1e-3
+    design = sum(b1 + b2 for b1, b2 in table.values()) * cells / (HBM_PEAK_GBS * 1e9)
+    method = max(320 * cells / (HBM_PEAK_GBS * 1e9), FLOPS_PER_CELL_UPDATE * cells / peak_flops)
+    return {"design_hbm": round(design / t, 4), "method": round(method / t, 4)}
 
 
 def pcie_inclusive(wl, precision, steps, variant):
@@ -561,7 +590,7 @@ def main():
     print("# HBM stream reference", file=sys.stderr, flush=True)
     stream = stream_bandwidth()
     print("# FP64 timed run", file=sys.stderr, flush=True)
-    r64 = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags)
+    r64 = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags, a.repeats)
     r64["sim"].close()
     ms = r64["ms"]
     value = cells * a.steps / (ms * 1e-3) / 1e6
@@ -573,7 +602,7 @@ def main():
     mixed = None
     if not a.no_mixed:
         print("# mixed timed run", file=sys.stderr, flush=True)
-        rmx = run_gpu(wl, mhd.MHD_MIXED, a.steps, a.warmup, flags)
+        rmx = run_gpu(wl, mhd.MHD_MIXED, a.steps, a.warmup, flags, a.repeats)
         rmx["sim"].close()
         ktm = kernel_times(wl, mhd.MHD_MIXED, min(a.steps, 10), rmx["variant"])
         acc = compare(spec, r64["state"], rmx["state"])
@@ -581,6 +610,8 @@ def main():
             "value": round(cells * a.steps / (rmx["ms"] * 1e-3) / 1e6, 2),
             "ms_per_step": round(rmx["ms"] / a.steps, 4),
             "speedup_vs_fp64": round(ms / rmx["ms"], 3),
+            "ms_per_step_repeats": [round(t / a.steps, 4) for t in rmx["times"]],
+            "fractions": fractions(rmx["ms"] / a.steps, cells, BYTES_MIXED, FP32_PEAK_FLOPS),
             "accuracy_vs_fp64": acc,
             "after_steps": a.warmup + a.steps,
             "variant": rmx["variant"],
@@ -599,6 +630,8 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms / a.steps, 4),
+        "repeats": a.repeats,
+        "ms_per_step_repeats": [round(t / a.steps, 4) for t in r64["times"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -608,6 +641,7 @@ def main():
                    "cells": cells, "launch": "hipGraph replay per step",
                    "variant": r64["variant"]},
         "roofline": roof,
+        "fractions": fractions(ms / a.steps, cells, BYTES_FP64, FP64_PEAK_FLOPS),
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "mixed": mixed,
         "hbm_stream": stream,
