@@ -18,7 +18,8 @@
  *     falling back to HLL (Harten, Lax & van Leer 1983) on unphysical stars;
  *   - CT corner EMF: contact-upwinded average of Gardiner & Stone (2005,
  *     J. Comput. Phys. 205), face update as the discrete curl;
- *   - time stepping: two-stage SSP Runge-Kutta (Shu & Osher 1988);
+ *   - time stepping: two- or three-stage SSP Runge-Kutta (Shu & Osher 1988;
+ *     the paper runs the third-order scheme by default);
  *   - time step: CFL condition on the fast magnetosonic speed.
  *
  * Readings of points the paper leaves open (all shared with the GPU library,
@@ -65,6 +66,7 @@ struct orc_box {
   int n[3];
   int bc[3];
   int active[3];
+  int rk;               /* Runge-Kutta stages: 2 (SSP-RK2) or 3 (SSP-RK3) */
   double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
@@ -494,6 +496,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->n[d] = n[d];
     b->bc[d] = bc[d];
     b->active[d] = n[d] > 1;
+    b->rk = 2;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
     b->idx[d] = 1.0 / b->dx[d];
   }
@@ -866,18 +869,32 @@ double orc_dt(orc_box *b) {
   return b->cfl / lmax;
 }
 
-static void stage_update(orc_box *b, double dt, int second) {
+/* Stage combine of the strong-stability-preserving Runge-Kutta schemes of
+ * Shu & Osher (1988), with L the stage operator just evaluated and U0 the
+ * state at the start of the step:
+ *   first stage (both):   U = U0 + dt L
+ *   RK2, second stage:    U = 1/2 (U0 + (U + dt L))
+ *   RK3, second stage:    U = 3/4 U0 + 1/4 (U + dt L)
+ *   RK3, third stage:     U = 1/3 U0 + 2/3 (U + dt L)
+ * (kind 0, 1, 2, 3 below; the RK3 weights are the double nearest 3/4, 1/4,
+ * 1/3, 2/3, in the form a U0 + b (U + dt L)). */
+static double combine(int kind, double u0, double u, double dtl) {
+  switch (kind) {
+    case 0: return u0 + dtl;
+    case 1: return 0.5 * (u0 + (u + dtl));
+    case 2: return 0.75 * u0 + 0.25 * (u + dtl);
+    default: return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (u + dtl);
+  }
+}
+
+static void stage_update(orc_box *b, double dt, int kind) {
   int i, j, k, q, d;
   for (k = 0; k < b->n[2]; k++)
     for (j = 0; j < b->n[1]; j++)
       for (i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
-        for (q = 0; q < NQ; q++) {
-          if (!second)
-            b->U[q][c] = b->U0[q][c] + dt * b->R[q][c];
-          else
-            b->U[q][c] = 0.5 * (b->U0[q][c] + (b->U[q][c] + dt * b->R[q][c]));
-        }
+        for (q = 0; q < NQ; q++)
+          b->U[q][c] = combine(kind, b->U0[q][c], b->U[q][c], dt * b->R[q][c]);
       }
   for (d = 0; d < 3; d++) {
     int ex = b->n[0] + (d == 0), ey = b->n[1] + (d == 1), ez = b->n[2] + (d == 2);
@@ -885,10 +902,7 @@ static void stage_update(orc_box *b, double dt, int second) {
       for (j = 0; j < ey; j++)
         for (i = 0; i < ex; i++) {
           size_t c = IX(b, i, j, k);
-          if (!second)
-            b->B[d][c] = b->B0[d][c] + dt * b->RB[d][c];
-          else
-            b->B[d][c] = 0.5 * (b->B0[d][c] + (b->B[d][c] + dt * b->RB[d][c]));
+          b->B[d][c] = combine(kind, b->B0[d][c], b->B[d][c], dt * b->RB[d][c]);
         }
   }
 }
@@ -903,9 +917,22 @@ void orc_step_fixed_dt(orc_box *b, double dt) {
   save_start(b);
   stage_operator(b);
   stage_update(b, dt, 0);
-  stage_operator(b);
-  stage_update(b, dt, 1);
+  if (b->rk == 3) {
+    stage_operator(b);
+    stage_update(b, dt, 2);
+    stage_operator(b);
+    stage_update(b, dt, 3);
+  } else {
+    stage_operator(b);
+    stage_update(b, dt, 1);
+  }
   b->t = b->t + dt;
+}
+
+int orc_set_rk(orc_box *b, int stages) {
+  if (stages != 2 && stages != 3) return -1;
+  b->rk = stages;
+  return 0;
 }
 
 void orc_step(orc_box *b, int nsteps, double t_stop) {

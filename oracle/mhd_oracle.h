@@ -44,9 +44,12 @@ int orc_set_state(orc_box *b, const double *const cons[5],
 void orc_get_state(const orc_box *b, double *const cons[5],
                    double *const bface[3], double *t);
 
-/* Advances nsteps full SSP-RK2 steps with the CFL time step of each step's
- * starting state (clamped to t_stop - t when t_stop > 0). */
+/* Advances nsteps full Runge-Kutta steps (SSP-RK2 unless orc_set_rk chose
+ * SSP-RK3) with the CFL time step of each step's starting state (clamped to
+ * t_stop - t when t_stop > 0). */
 void orc_step(orc_box *b, int nsteps, double t_stop);
+/* Integrator: 2 (SSP-RK2, the default) or 3 (SSP-RK3) stages; -1 otherwise. */
+int orc_set_rk(orc_box *b, int stages);
 /* One step with a caller-given dt (used for sampled parity on sub-boxes). */
 void orc_step_fixed_dt(orc_box *b, double dt);
 /* CFL time step of the current state (no t_stop clamp). */

@@ -39,6 +39,8 @@ def _lib():
         lib.orc_get_state.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp), _dp]
         lib.orc_step.argtypes = [C.c_void_p, C.c_int, C.c_double]
         lib.orc_step_fixed_dt.argtypes = [C.c_void_p, C.c_double]
+        lib.orc_set_rk.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_rk.restype = C.c_int
         lib.orc_dt.argtypes = [C.c_void_p]
         lib.orc_dt.restype = C.c_double
         lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
@@ -78,7 +80,7 @@ def _vec(x, n):
 class OracleBox:
     """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
 
-    def __init__(self, spec, pfloor: float = 1e-10):
+    def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2):
         lib = _lib()
         self.spec = spec
         self.n = tuple(int(v) for v in spec.n)
@@ -89,6 +91,9 @@ class OracleBox:
         self._h = lib.orc_box_new(n, lo, hi, bc, spec.gamma, spec.cfl, pfloor)
         if not self._h:
             raise ValueError("oracle: bad box description or out of memory")
+        if lib.orc_set_rk(self._h, int(rk)) != 0:
+            self.close()
+            raise ValueError("oracle: rk must be 2 or 3")
 
     def close(self):
         if self._h:

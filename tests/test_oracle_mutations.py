@@ -36,9 +36,15 @@ MUTATIONS = [
     ("bc_wrong_index", "b->Bc[1][c] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i, j + 1, k)]);",
      "b->Bc[1][c] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i + 1, j, k)]);",
      "test_oracle_scheme.py::test_cp_alfven_axes_equivalent"),
-    ("rk2_combine", "0.5 * (b->U0[q][c] + (b->U[q][c] + dt * b->R[q][c]))",
-     "0.5 * (b->U0[q][c] + b->U[q][c]) + dt * b->R[q][c]",
+    ("rk2_combine", "case 1: return 0.5 * (u0 + (u + dtl));",
+     "case 1: return 0.5 * (u0 + u) + dtl;",
      "test_oracle_scheme.py::test_sod_shock_tube_against_exact"),
+    ("rk3_second_weights", "case 2: return 0.75 * u0 + 0.25 * (u + dtl);",
+     "case 2: return 0.25 * u0 + 0.75 * (u + dtl);",
+     "test_oracle_scheme.py::test_rk_temporal_order"),
+    ("rk3_third_weights", "default: return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (u + dtl);",
+     "default: return 0.5 * u0 + 0.5 * (u + dtl);",
+     "test_oracle_scheme.py::test_rk_temporal_order"),
     ("divergence_sign", "r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];",
      "r = r + (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];",
      "test_oracle_scheme.py::test_sod_shock_tube_against_exact"),

@@ -14,8 +14,8 @@ import oracle as O
 from paper_2606_12753_amd import workloads as W
 
 
-def make(wl, i=0, pfloor=1e-10):
-    b = O.OracleBox(wl.boxes[i], pfloor=pfloor)
+def make(wl, i=0, pfloor=1e-10, rk=2):
+    b = O.OracleBox(wl.boxes[i], pfloor=pfloor, rk=rk)
     st = wl.states[i]
     b.set_state(st.cons, st.bface, st.t)
     return b
@@ -42,6 +42,46 @@ def test_uniform_state_bitwise(bc, n):
     assert t > 0
 
 
+def test_uniform_state_rk3_to_rounding():
+    """SSP-RK3: the stage weights 3/4, 1/4 and 1/3, 2/3 are rounded, so a
+    uniform state is kept to a few ulp per step rather than bit for bit."""
+    wl = W.uniform(n=(6, 5, 4), bc=(0, 1, 0))
+    b = make(wl, rk=3)
+    b.step(4)
+    cons, bf, t = b.get_state()
+    for c, c0 in zip(list(cons) + list(bf), list(wl.states[0].cons) + list(wl.states[0].bface)):
+        assert np.allclose(c, c0, rtol=4 * 4 * 2.0 ** -52, atol=0.0)
+
+
+@pytest.mark.parametrize("rk,lo,hi", [(2, 1.8, 2.3), (3, 2.7, 3.5)])
+def test_rk_temporal_order(rk, lo, hi):
+    """Order in time of the SSP-RK integrators (Shu & Osher 1988): on a fixed
+    grid the error of a smooth circularly polarised Alfven wave after a fixed
+    time, against the same run with a 32 times smaller step, falls by 2^rk
+    when the step is halved."""
+    wl = W.cp_alfven(32, axis=0)
+    spec, st = wl.boxes[0], wl.states[0]
+
+    def run(dt, nsteps):
+        b = O.OracleBox(spec, rk=rk)
+        b.set_state(st.cons, st.bface, 0.0)
+        for _ in range(nsteps):
+            b.step_fixed_dt(dt)
+        cons, _, _ = b.get_state()
+        b.close()
+        return cons
+
+    b = O.OracleBox(spec)
+    b.set_state(st.cons, st.bface, 0.0)
+    dt = b.dt()
+    b.close()
+    ref = run(dt / 32, 16 * 32)
+    err = [sum(float(np.abs(c - r).sum()) for c, r in zip(run(dt / m, 16 * m), ref))
+           for m in (1, 2)]
+    order = math.log2(err[0] / err[1])
+    assert lo <= order <= hi, (rk, order, err)
+
+
 def test_box_without_active_axis_rejected():
     """One cell on every axis: no wave speed, so the CFL step is undefined
     and the box is refused; one active axis is enough."""
@@ -66,10 +106,10 @@ def test_uniform_dt_closed_form():
     assert b.dt() == pytest.approx(0.3 / max(rates), rel=4e-16 * 8)
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_conservation_divb_mean_field(seed):
+@pytest.mark.parametrize("seed,rk", [(1, 2), (2, 2), (3, 3)])
+def test_conservation_divb_mean_field(seed, rk):
     wl = W.random_smooth(n=(12, 10, 8), seed=seed)
-    b = make(wl)
+    b = make(wl, rk=rk)
     st0 = wl.states[0]
     d0 = b.divb_max()
     b.step(6)
