@@ -100,6 +100,10 @@ typedef struct {
                               mhd_destroy; NULL: the library allocates */
   uint64_t workspace_bytes;
   uint32_t flags;          /* MHD_F_* */
+  int32_t rk_stages;       /* time integrator: 2 (SSP-RK2; also when 0) or 3
+                              (SSP-RK3, Shu & Osher 1988: the paper's default
+                              third-order scheme; one more state copy in the
+                              workspace) */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;

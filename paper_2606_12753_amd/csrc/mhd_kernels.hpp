@@ -10,7 +10,7 @@
 //   * HLLD (Miyoshi & Kusano 2005) with an HLL fallback on unphysical stars;
 //   * contact-upwinded CT corner EMFs (Gardiner & Stone 2005) and the face
 //     update as the discrete curl;
-//   * two-stage SSP Runge-Kutta (Shu & Osher 1988) and the CFL time step from
+//   * two- or three-stage SSP Runge-Kutta (Shu & Osher 1988) and the CFL time step from
 //     the fast magnetosonic rate.
 //
 // Layout in HBM: structure of arrays, C order [z][y][x], x fastest; every
@@ -60,8 +60,9 @@ struct Box {
   int act[3];    // active axis (n > 1)
   double dx[3], idx[3];  // cell size and its reciprocal
   double gamma, igm1, cfl, pfloor;  // igm1 = 1/(gamma-1)
-  double* U[2][kNQ];  // conserved state: [0] start of step, [1] stage state
-  double* B[2][3];    // face field, same two copies
+  double* U[3][kNQ];  // conserved state: [0] start of step, [1], [2] stage
+                      // states ([2] only for the three-stage integrator)
+  double* B[3][3];    // face field, same copies
   void* Ec[3];        // cell EMF  E = -v x B
   void* FX[kNQ];      // hydro flux on x faces
   void* EF[3][2];     // EMF (E_t1, E_t2) on the faces normal to each axis
@@ -99,7 +100,9 @@ struct Launch {
   const int* base;  // base[kind*(nboxes+1) + b]: first tile of box b
   int nboxes;
   int ntiles;       // tiles of this kind over all boxes
-  int stage;        // 0: read state 0 (stage 1); 1: read state 1 (stage 2)
+  int stage;        // state the stage sweeps (0: start of step, 1, 2: stage states)
+  int dst;          // state the stage's combine writes
+  int comb;         // stage combine (rk_combine)
   int lam;          // x sweep: also reduce the CFL rate of the owned cells
   int xcd;          // XCD-grouped tile order (see tile_of)
 };
@@ -818,6 +821,22 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   }
 }
 
+// Stage combine of the strong-stability-preserving Runge-Kutta schemes
+// (Shu & Osher 1988): uold is the state at the start of the step, usw the
+// state the stage swept, dtl = dt times its residual.
+//   0: first stage            usw + dtl
+//   1: RK2 second stage       1/2 (uold + (usw + dtl))
+//   2: RK3 second stage       3/4 uold + 1/4 (usw + dtl)
+//   3: RK3 third stage        1/3 uold + 2/3 (usw + dtl)
+// (the RK3 weights are the doubles nearest 3/4, 1/4, 1/3, 2/3; FP64 results
+// are identical to the oracle's).
+__device__ __forceinline__ double rk_combine(int kind, double uold, double usw, double dtl) {
+  if (kind == 0) return usw + dtl;
+  if (kind == 1) return 0.5 * (uold + (usw + dtl));
+  if (kind == 2) return 0.75 * uold + 0.25 * (usw + dtl);
+  return (1.0 / 3.0) * uold + (2.0 / 3.0) * (usw + dtl);
+}
+
 // Marching sweep along axis D (1 = y, 2 = z).  Each lane owns one column of
 // cells along D (lanes run along x) and slides a register window (two cells,
 // the limited slope of the older one and the incoming cell) down its
@@ -891,8 +910,9 @@ struct Window<real, 1> {
 // faces after the sweep loaded it, when it has usually left L2; the ring
 // saves that second fetch.
 template <typename real, int D, int PF, int LW, int CU>
-__device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int j0, int j1,
-                                             real (*lds)[kTPB], double (*ring)[kTPB]) {
+__device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, int i, int tr,
+                                             int j0, int j1, real (*lds)[kTPB],
+                                             double (*ring)[kTPB]) {
   constexpr bool kRing = CU && D == 2;
   const int lane = threadIdx.x;
   // (i, tr): x index and the index along the remaining axis (z for D=1, y
@@ -970,7 +990,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
             usw[q] = ring[cr * kNQ + q][lane];
           else
             usw[q] = ld<double>(b.U[s][q], cprev);
-          uold[q] = s == 1 ? ld<double>(b.U[0][q], cprev) : 0.0;
+          uold[q] = comb ? ld<double>(b.U[0][q], cprev) : 0.0;
         }
       }
     };
@@ -1001,13 +1021,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
 #pragma unroll
       for (int q = 0; q < kNQ; q++) {
         const double r = racc[q] - ((double)fl[q] - (double)fprev[q]) * idxD;
-        if (D == 1) {
+        if (D == 1)
           st<real>(b.R[q], cprev, (real)r);
-        } else if (s == 0) {
-          st<double>(b.U[1][q], cprev, usw[q] + dt * r);
-        } else {
-          st<double>(b.U[0][q], cprev, 0.5 * (uold[q] + (usw[q] + dt * r)));
-        }
+        else
+          st<double>(b.U[dst][q], cprev, rk_combine(comb, uold[q], usw[q], dt * r));
       }
     }
 #pragma unroll
@@ -1019,7 +1036,8 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int i, int tr, int 
 // inactive axis D: residual from the earlier axes only, face data from the
 // cell (EMF = cell EMF, mass flux = momentum)
 template <typename real, int D>
-__device__ __forceinline__ void inactive_column(CBox& b, int s, int i, int tr) {
+__device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int comb, int i,
+                                                int tr) {
   auto pos = [&](int a, int& ii, int& jj, int& kk) {
     ii = i;
     if (D == 1) { jj = a; kk = tr; } else { jj = tr; kk = a; }
@@ -1054,11 +1072,8 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int i, int tr) {
 #pragma unroll
     for (int q = 0; q < kNQ; q++) {
       double r = (double)ld<real>(b.R[q], c);
-      if (s == 0)
-        st<double>(b.U[1][q], c, ld<double>(b.U[0][q], c) + dt * r);
-      else
-        st<double>(b.U[0][q], c,
-                   0.5 * (ld<double>(b.U[0][q], c) + (ld<double>(b.U[1][q], c) + dt * r)));
+      const double uold = comb ? ld<double>(b.U[0][q], c) : 0.0;
+      st<double>(b.U[dst][q], c, rk_combine(comb, uold, ld<double>(b.U[s][q], c), dt * r));
     }
   }
 }
@@ -1090,9 +1105,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW, CU>(b, L.stage, i, tr, j0, j1, lds, ring);
+      march_column<real, D, PF, LW, CU>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
     } else {
-      inactive_column<real, D>(b, L.stage, i, tr);
+      inactive_column<real, D>(b, L.stage, L.dst, L.comb, i, tr);
     }
   }
 }
@@ -1172,7 +1187,7 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
 
 // Face update: dB_d/dt = -[(E_f(e+1/2) - E_f(e-1/2))/dx_e
 //                          - (E_e(f+1/2) - E_e(f-1/2))/dx_f], (d, e, f)
-// cyclic, formed in FP64, then the SSP-RK2 stage combine.
+// cyclic, formed in FP64, then the Runge-Kutta stage combine.
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -1208,11 +1223,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
       }
       const double rate = -(t1 - t2);
       const int fi = fidx(b, d, pos[0], pos[1], pos[2]);
-      if (L.stage == 0)
-        st<double>(b.B[1][d], fi, ld<double>(b.B[0][d], fi) + dt * rate);
-      else
-        st<double>(b.B[0][d], fi,
-                   0.5 * (ld<double>(b.B[0][d], fi) + (ld<double>(b.B[1][d], fi) + dt * rate)));
+      const double bold = L.comb ? ld<double>(b.B[0][d], fi) : 0.0;
+      st<double>(b.B[L.dst][d], fi,
+                 rk_combine(L.comb, bold, ld<double>(b.B[L.stage][d], fi), dt * rate));
     }
   }
 }

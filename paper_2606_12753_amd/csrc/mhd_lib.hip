@@ -132,6 +132,10 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     err = "config: p_floor must be finite";
     return MHD_E_INVAL;
   }
+  if (cfg->rk_stages != 0 && cfg->rk_stages != 2 && cfg->rk_stages != 3) {
+    err = "config: rk_stages must be 2 or 3 (0: 2)";
+    return MHD_E_INVAL;
+  }
   for (int b = 0; b < cfg->nboxes; b++) {
     int rc = validate_box(cfg->boxes[b], err);
     if (rc) {
@@ -190,10 +194,14 @@ size_t backup_bytes_of(const Geom& g) {
   return align_up(mhd::kNQ * g.N * 8) + align_up((g.F[0] + g.F[1] + g.F[2]) * 8) + 4 * 8 + 3 * 8;
 }
 
-size_t box_bytes(const Geom& g, const Tiling& t, size_t rs) {
+// state copies: the start of the step and one stage state (SSP-RK2), or two
+// stage states (SSP-RK3)
+int state_copies(const mhd_config* cfg) { return cfg->rk_stages == 3 ? 3 : 2; }
+
+size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies) {
   size_t s = 0;
-  s += 2 * mhd::kNQ * align_up(g.N * 8);
-  for (int d = 0; d < 3; d++) s += 2 * align_up(g.F[d] * 8);
+  s += copies * mhd::kNQ * align_up(g.N * 8);
+  for (int d = 0; d < 3; d++) s += copies * align_up(g.F[d] * 8);
   s += 3 * align_up(g.N * rs);                      // Ec
   s += mhd::kNQ * align_up(g.F[0] * rs);            // FX
   for (int d = 0; d < 3; d++) s += 3 * align_up(g.F[d] * rs);  // EF x2 + MF
@@ -218,7 +226,7 @@ Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
   for (int b = 0; b < cfg->nboxes; b++) {
     Geom g = geom_of(cfg->boxes[b]);
     Tiling t = tiling_of(g, ysl, zsl);
-    size_t bb = box_bytes(g, t, rs);
+    size_t bb = box_bytes(g, t, rs, state_copies(cfg));
     p.box_off.push_back(off);
     p.box_bytes.push_back(bb);
     off += bb;
@@ -238,6 +246,7 @@ Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
 struct mhd_ctx {
   std::vector<mhd_box> boxes;
   int precision = MHD_FP64;
+  int rk = 2;  // Runge-Kutta stages
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -302,6 +311,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.grid = c->grid;
   sc.var_x = c->var_x;
   sc.var_m = c->var_m;
+  sc.rk = c->rk;
   sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
@@ -525,10 +535,13 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
       p += align_up(bytes);
       return q;
     };
-    for (int s = 0; s < 2; s++)
-      for (int q = 0; q < mhd::kNQ; q++) b.U[s][q] = reinterpret_cast<double*>(take(g.N * 8));
-    for (int s = 0; s < 2; s++)
-      for (int d = 0; d < 3; d++) b.B[s][d] = reinterpret_cast<double*>(take(g.F[d] * 8));
+    const int copies = state_copies(cfg);
+    for (int s = 0; s < 3; s++)
+      for (int q = 0; q < mhd::kNQ; q++)
+        b.U[s][q] = s < copies ? reinterpret_cast<double*>(take(g.N * 8)) : nullptr;
+    for (int s = 0; s < 3; s++)
+      for (int d = 0; d < 3; d++)
+        b.B[s][d] = s < copies ? reinterpret_cast<double*>(take(g.F[d] * 8)) : nullptr;
     for (int d = 0; d < 3; d++) b.Ec[d] = take(g.N * rs);
     for (int q = 0; q < mhd::kNQ; q++) b.FX[q] = take(g.F[0] * rs);
     for (int d = 0; d < 3; d++) {
@@ -699,6 +712,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->precision = cfg->precision;
   c->pfloor = cfg->p_floor > 0.0 ? cfg->p_floor : 1e-10;
   c->flags = cfg->flags;
+  c->rk = cfg->rk_stages == 3 ? 3 : 2;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";

@@ -1,7 +1,8 @@
 // mhd_step.hpp -- the launch sequence of one SSP-RK2 step.
 //
-// Stage 1 and stage 2 each run: the x sweep (stage 1 also reduces the CFL
-// rate of the start-of-step state, and the per-box dt follows), the y and z
+// Every stage (two, or three for SSP-RK3) runs: the x sweep (stage 1 also
+// reduces the CFL rate of the start-of-step state, and the per-box dt
+// follows), the y and z
 // marches (the z march applies the RK stage combine to the cells), the
 // corner-EMF kernel and the face update (RK stage combine of the faces).
 // Included by the two translation units that instantiate the kernels: the
@@ -14,13 +15,15 @@
 
 namespace mhd {
 
-constexpr int kLaunchesPerStep = 11;
+// launches of one step: five per stage, plus the time step after stage 1
+constexpr int kLaunchesPerStep = 3 * 5 + 1;
 
 struct StepCtx {
   Launch L;            // boxes, tile table, box count
   const int* total;    // tiles per kernel kind over all boxes
   const int* grid;     // persistent grid size per kind (0: one group per tile)
   int var_x, var_m;    // launch variants of the x sweep and the marches
+  int rk;              // Runge-Kutta stages: 2 or 3
   int xcd;             // XCD-grouped tile order
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
@@ -90,8 +93,17 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
       slot++;
     }
   };
-  for (int s = 0; s < 2; s++) {
-    L.stage = s;
+  // per stage: the state swept, the state written and the combine kind
+  // (SSP-RK2: 0 -> 1 first, 1 -> 0 half; SSP-RK3: 0 -> 1 first, 1 -> 2
+  // three quarters / one quarter, 2 -> 0 one third / two thirds)
+  static const int kSrc[2][3] = {{0, 1, 0}, {0, 1, 2}};
+  static const int kDst[2][3] = {{1, 0, 0}, {1, 2, 0}};
+  static const int kComb[2][3] = {{0, 1, 0}, {0, 2, 3}};
+  const int r = sc.rk == 3 ? 1 : 0;
+  for (int s = 0; s < (r ? 3 : 2); s++) {
+    L.stage = kSrc[r][s];
+    L.dst = kDst[r][s];
+    L.comb = kComb[r][s];
     L.lam = s == 0;
     L.ntiles = sc.total[kXS];
     mark(MHD_K_SWEEP_X, true);

@@ -73,6 +73,7 @@ class mhd_config(C.Structure):
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_uint64),
         ("flags", C.c_uint32),
+        ("rk_stages", C.c_int32),
     ]
 
 
@@ -130,7 +131,8 @@ def _box_struct(spec) -> mhd_box:
 
 
 def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
-                stream=None, workspace=None, workspace_bytes: int = 0, flags: int = 0):
+                stream=None, workspace=None, workspace_bytes: int = 0, flags: int = 0,
+                rk: int = 2):
     arr = (mhd_box * len(boxes))(*[_box_struct(s) for s in boxes])
     cfg = mhd_config()
     cfg.nboxes = len(boxes)
@@ -141,12 +143,13 @@ def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0
     cfg.workspace = workspace
     cfg.workspace_bytes = int(workspace_bytes)
     cfg.flags = int(flags)
+    cfg.rk_stages = int(rk)
     return cfg, arr  # keep arr alive with cfg
 
 
-def mhd_workspace_bytes(boxes, precision=MHD_FP64, flags=0) -> int:
+def mhd_workspace_bytes(boxes, precision=MHD_FP64, flags=0, rk=2) -> int:
     lib = load()
-    cfg, _keep = make_config(boxes, precision, flags=flags)
+    cfg, _keep = make_config(boxes, precision, flags=flags, rk=rk)
     out = C.c_uint64()
     rc = lib.mhd_workspace_bytes(C.byref(cfg), C.byref(out))
     if rc != MHD_OK:
@@ -162,7 +165,7 @@ class Sim:
     """One library context: an ensemble of boxes advanced together."""
 
     def __init__(self, boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
-                 stream=None, workspace=None, flags: int = 0):
+                 stream=None, workspace=None, flags: int = 0, rk: int = 2):
         self._lib = load()
         self.boxes = list(boxes)
         self._h = None
@@ -171,7 +174,7 @@ class Sim:
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         self._workspace = workspace
         cfg, self._keep = make_config(self.boxes, precision, p_floor, stream, ws_ptr, ws_bytes,
-                                      flags)
+                                      flags, rk)
         h = C.c_void_p()
         rc = self._lib.mhd_create(C.byref(cfg), C.byref(h))
         if rc != MHD_OK:

@@ -38,11 +38,11 @@ def rel_l1(a, b):
     return num / den if den > 0 else num / max(1, b.size)
 
 
-def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None):
+def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2):
     idx = range(len(wl.boxes)) if boxes is None else boxes
     specs = [wl.boxes[i] for i in idx]
     out = []
-    with mhd.Sim(specs, precision=precision, flags=flags) as sim:
+    with mhd.Sim(specs, precision=precision, flags=flags, rk=rk) as sim:
         for k, i in enumerate(idx):
             st = wl.states[i]
             sim.set_state(k, st.cons, st.bface, st.t)
@@ -53,8 +53,8 @@ def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None)
     return out
 
 
-def oracle_run(spec, st, nsteps, t_stop=0.0):
-    b = O.OracleBox(spec)
+def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2):
+    b = O.OracleBox(spec, rk=rk)
     b.set_state(st.cons, st.bface, st.t)
     b.step(nsteps, t_stop)
     cons, bface, t = b.get_state()
@@ -119,6 +119,46 @@ def test_random_state_fp64(n, bc):
     g = gpu_run(wl, 4)[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4)
     assert_fp64_parity(g, o, f"random {n} {bc}")
+
+
+@pytest.mark.parametrize("n,bc,flags", [
+    ((37, 23, 19), (0, 0, 0), 0),
+    ((33, 20, 17), (0, 1, 0), mhd.MHD_F_GRAPH),
+    ((24, 18, 40), (1, 0, 1), mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT),
+    ((40, 36, 1), (0, 0, 0), 0),
+])
+def test_rk3_fp64(n, bc, flags):
+    """Three-stage SSP Runge-Kutta: the library's FP64 steps equal the
+    oracle's bit for bit (stage states, combines and the extra state copy)."""
+    wl = W.random_smooth(n=n, seed=sum(n) + 7, bc=bc)
+    g = gpu_run(wl, 4, flags=flags, rk=3)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=3)
+    assert_fp64_parity(g, o, f"rk3 {n} {bc}")
+
+
+@pytest.mark.parametrize("variant", ["1,9,16,1", "3,2,7,0", "4,10,64,0"])
+def test_rk3_launch_variants_bitwise(variant, monkeypatch):
+    wl = W.random_smooth(n=(30, 26, 22), seed=23, bc=(1, 0, 0))
+    monkeypatch.delenv("MHD_VARIANT", raising=False)
+    ref = gpu_run(wl, 3, rk=3)[0]
+    monkeypatch.setenv("MHD_VARIANT", variant)
+    g = gpu_run(wl, 3, rk=3)[0]
+    for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
+        assert np.array_equal(a, b), variant
+
+
+def test_rk3_orszag_tang_and_mixed():
+    wl = W.orszag_tang_2d(n=64, steps=20)
+    spec = wl.boxes[0]
+    o = oracle_run(spec, wl.states[0], 20, rk=3)
+    g = gpu_run(wl, 20, flags=mhd.MHD_F_GRAPH, rk=3)[0]
+    assert_fp64_parity(g, o, "OT2D rk3")
+    m = gpu_run(wl, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, rk=3)[0]
+    mp, mb = pressure_bmag(spec, m[0], m[1])
+    op, ob = pressure_bmag(spec, o[0], o[1])
+    for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+        assert rel_l1(a, b) <= TOLMIX, name
+    assert divb_norm(spec, m[1])[0] <= 1e-12
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
