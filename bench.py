@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--accuracy", action="store_true")
+    ap.add_argument("--paper-workload", action="store_true",
+                    help="the paper's 3D Orszag-Tang case (10 SSP-RK3 steps) instead")
+    ap.add_argument("--ot-n", type=int, default=352, help="cells per axis of that case")
     ap.add_argument("--counter-pass", action="store_true",
                     help="dispatches for a rocprofv3 --pmc run (calibration copy, then "
                          "--steps unfused steps of each precision)")
@@ -163,7 +166,7 @@ def kind_of(name):
     return None
 
 
-def run_gpu(wl, precision, steps, warmup, flags, repeats=1):
+def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2):
     """Per repeat: set the initial state, `warmup` untimed steps (the first
     repeat's include the autotuner's trials), then `steps` timed steps.
     Returns the median time, every repeat's time, the final state of box 0
@@ -171,7 +174,7 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1):
     import torch
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
-    sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags)
+    sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     times = []
@@ -527,6 +530,42 @@ def summarize_trace(a):
     print("\n".join(lines))
 
 
+# The paper's Figure 1: wall time of 10 steps of its 3D Orszag-Tang run on
+# 352^3 cells (whole application, third-order Runge-Kutta), by hardware and
+# programming model.  Context only: other hardware, other code.
+PAPER_OT3D_10_STEPS_S = {"A100, OpenACC": 13.9, "A100, OpenMP": 17.2,
+                         "MI250X (one GCD), OpenMP": 48.1}
+
+
+def paper_workload(a, flags):
+    """The paper's profiled case on this library: 3D Orszag-Tang, 352^3
+    cells, 10 SSP-RK3 steps, FP64 and mixed, median of the timed repeats."""
+    from paper_2606_12753_amd import mhd, workloads
+    print("# paper workload: building 3D Orszag-Tang", file=sys.stderr, flush=True)
+    wl = workloads.orszag_tang_3d(n=a.ot_n, steps=10)
+    res = {}
+    for prec, key in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
+        print(f"# paper workload: {key}", file=sys.stderr, flush=True)
+        r = run_gpu(wl, prec, 10, 2, flags, repeats=3, rk=3)
+        r["sim"].close()
+        res[key] = r
+    spec = wl.boxes[0]
+    out = {
+        "workload": f"orszag_tang_3d {a.ot_n}^3, SSP-RK3, 10 steps, PLM-minmod+HLLD+CT, CFL 0.3",
+        "cells": wl.cells,
+        "fp64": {"s_10_steps": round(res["fp64"]["ms"] * 1e-3, 4),
+                 "Mcell_updates_per_s": round(wl.cells * 10 / (res["fp64"]["ms"] * 1e-3) / 1e6, 1),
+                 "variant": res["fp64"]["variant"]},
+        "mixed": {"s_10_steps": round(res["mixed"]["ms"] * 1e-3, 4),
+                  "Mcell_updates_per_s": round(wl.cells * 10 / (res["mixed"]["ms"] * 1e-3) / 1e6, 1),
+                  "variant": res["mixed"]["variant"]},
+        "speedup_mixed": round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
+        "paper_s_10_steps": PAPER_OT3D_10_STEPS_S,
+    }
+    out.update(compare(spec, res["fp64"]["state"], res["mixed"]["state"]))
+    print(json.dumps(out), flush=True)
+
+
 def accuracy(flags):
     """Mixed against FP64 on the full-size secondary workloads."""
     from paper_2606_12753_amd import mhd, workloads
@@ -582,6 +621,9 @@ def main():
     flags = mhd.MHD_F_GRAPH | (0 if a.no_tune else mhd.MHD_F_AUTOTUNE)
     if a.accuracy:
         accuracy(flags)
+        return
+    if a.paper_workload:
+        paper_workload(a, flags)
         return
     print(f"# building blast {a.n}^3 input", file=sys.stderr, flush=True)
     wl = workloads.blast_3d(n=a.n)

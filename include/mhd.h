@@ -8,9 +8,9 @@
  * field; Runge-Kutta stepping.  Concretely: PLM-minmod reconstruction, HLLD
  * fluxes with HLL fallback, the flux-divergence update, contact-upwinded CT
  * corner EMFs with the face-field update, the CFL time step from a
- * max-reduction of the fast magnetosonic rate and the two-stage SSP
- * Runge-Kutta combine, on 3D structured boxes (2D and 1D as boxes with
- * inactive axes of one cell).
+ * max-reduction of the fast magnetosonic rate and the SSP Runge-Kutta
+ * stage combines (two or three stages), on 3D structured boxes (2D and 1D as
+ * boxes with inactive axes of one cell).
  *
  * All entry points return MHD_OK (0) or a negative status and never throw,
  * abort or exit across the ABI.  A context is used by one host thread at a
@@ -122,7 +122,8 @@ int mhd_create(const mhd_config *cfg, mhd_ctx **out);
 int mhd_set_state(mhd_ctx *ctx, int32_t box, const double *const cons[5],
                   const double *const bface[3], double t, int32_t where);
 
-/* Enqueues nsteps full SSP-RK2 steps of every box on the context stream.
+/* Enqueues nsteps full Runge-Kutta steps (rk_stages stages each) of every box
+ * on the context stream.
  * Each box steps with its own CFL time step computed on the device from its
  * state at the start of the step, clamped to t_stop - t when t_stop > 0
  * (steps at t >= t_stop are no-ops).  Returns without waiting; device errors

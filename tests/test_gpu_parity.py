@@ -388,12 +388,12 @@ def _sub_box(spec, st, centre, r):
     return sub, cons, bface, tuple(off)
 
 
-def _check_sampled(spec, st, cons, bface, dt, centres, r=8):
+def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2):
     """One oracle step with the GPU's dt on the neighbourhood of each sampled
     cell; compares the cell's conserved state and its three lower faces."""
     for c in centres:
         sub, sc, sb, o = _sub_box(spec, st, c, r)
-        ob = O.OracleBox(sub)
+        ob = O.OracleBox(sub, rk=rk)
         ob.set_state(sc, sb)
         ob.step_fixed_dt(dt)
         oc, obf, _ = ob.get_state()
@@ -430,6 +430,30 @@ def test_blast_256_full_size_sampled():
     centres = [tuple(int(v) for v in rng.integers(0, 256, size=3)) for _ in range(4)]
     centres += [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25)]
     _check_sampled(spec, st, cons, bface, dt_gpu, centres)
+
+
+def test_orszag_tang_352_rk3_full_size_sampled():
+    """The paper's profiled case, 3D Orszag-Tang on 352^3 cells with SSP-RK3,
+    at full size with graph replay and the autotuned launch variant: one step
+    on the GPU; the oracle recomputes the time step over the whole grid and
+    the step of sampled cells on neighbourhoods of radius 11 (three stages
+    reach 9 cells)."""
+    wl = W.orszag_tang_3d(n=352)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE, rk=3) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt_gpu, _ = sim.dt(0)
+        sim.step(1)
+        cons, bface, t = sim.get_state(0)
+    ob = O.OracleBox(spec)
+    ob.set_state(st.cons, st.bface)
+    assert dt_gpu == ob.dt()
+    assert t == dt_gpu
+    del ob
+    rng = np.random.default_rng(11)
+    centres = [tuple(int(v) for v in rng.integers(0, 352, size=3)) for _ in range(3)]
+    centres += [(0, 0, 0), (351, 175, 351), (88, 264, 100)]
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3)
 
 
 def test_kelvin_helmholtz_full_size_sampled():
