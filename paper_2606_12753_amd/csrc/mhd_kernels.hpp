@@ -76,7 +76,7 @@ struct Box {
   double* lam;        // per-tile max CFL rate (length: max(x tiles, cell tiles))
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
-  int xw, xr, xseg;   // x sweep: faces per segment, rows per tile, segments/row
+  int xft;            // x sweep: faces per tile
   int ysl, yseg;      // y march: cells per segment, segments
   int zsl, zseg;      // z march
   int ntile[6];       // tiles per kernel kind
@@ -672,29 +672,85 @@ __device__ __forceinline__ double block_max(double v) {
 
 // ---------------------------------------------------------------- kernels
 
-// Slot q of an x-sweep tile of R rows of width wd starting at row r0 (whose
-// (j, k) are j0, k0): row offset r, offset o in the row, and the row's (j, k).
-// A one-row tile (every box with at least 86 x faces) needs no division.
-__device__ __forceinline__ void tile_slot(int q, int R, int wd, int r0, int ny, int j0, int k0,
-                                          int& r, int& o, int& j, int& k) {
-  if (R == 1) {
-    r = 0;
-    o = q;
-    j = j0;
-    k = k0;
-  } else {
-    r = q / wd;
-    o = q - r * wd;
-    const int row = r0 + r;
-    j = row % ny;
-    k = row / ny;
+// x-sweep tile: xft consecutive faces of the box's x faces numbered row by
+// row (row = j + ny*k, face f, number row*nf + f).  The faces of one row
+// within the tile form a piece; piece p is staged in LDS as its cells from
+// two before its first face to one after its last (width + 3 slots), the
+// pieces one after another.  A tile of 256 faces touches at most
+// 2 + 255/nf rows, and the host keeps 256 + 3 pieces within the LDS capacity
+// (for rows of fewer than 13 faces, where it cannot, a tile is whole rows),
+// so every lane has a face in every tile but the box's last.
+struct XTile {
+  int nf, ny;
+  int nF;          // faces in this tile
+  int row0, fa;    // row and face of the tile's first face
+  int W0;          // faces of the first piece
+  int j0, k0;      // (j, k) of row0
+};
+
+__device__ __forceinline__ XTile x_tile(CBox& b, int lt) {
+  XTile x;
+  x.nf = b.nf[0];
+  x.ny = b.n[1];
+  const int F0 = lt * b.xft;
+  x.nF = min(b.xft, b.n[1] * b.n[2] * x.nf - F0);
+  x.row0 = F0 / x.nf;
+  x.fa = F0 - x.row0 * x.nf;
+  x.W0 = min(x.nf - x.fa, x.nF);
+  x.j0 = x.row0 % x.ny;
+  x.k0 = x.row0 / x.ny;
+  return x;
+}
+
+// (j, k) of the tile's piece p
+__device__ __forceinline__ void x_row(const XTile& x, int p, int& j, int& k) {
+  j = x.j0;
+  k = x.k0;
+  if (p) {
+    const int jj = x.j0 + p;
+    k += jj / x.ny;
+    j = jj - (jj / x.ny) * x.ny;
   }
 }
 
-// x sweep: row segments staged in LDS; one x face per lane.  Writes the
-// hydro flux, the face EMFs (E_y, E_z), the CT mass flux and the cell EMF of
-// every owned cell; with L.lam also the tile's max CFL rate (stage 1, the
-// state at the start of the step).
+// Staging slot s: piece p, cell index i in the row, and whether the tile
+// owns the cell (the cell's index is one of the piece's faces).
+__device__ __forceinline__ void x_slot(const XTile& x, int s, int& p, int& i, int& own) {
+  int c, w;
+  if (s < x.W0 + 3) {
+    p = 0;
+    c = s;
+    w = x.W0;
+    i = x.fa - 2 + c;
+  } else {
+    const int s2 = s - (x.W0 + 3);
+    p = 1 + s2 / (x.nf + 3);
+    c = s2 - (p - 1) * (x.nf + 3);
+    w = min(x.nf, x.nF - x.W0 - (p - 1) * x.nf);
+    i = c - 2;
+  }
+  own = c >= 2 && c < w + 2;
+}
+
+// Face t of the tile: piece p, face f in the row, and the slot o of the
+// first of its four stencil cells (cells f-2 .. f+1).
+__device__ __forceinline__ void x_face(const XTile& x, int t, int& p, int& f, int& o) {
+  if (t < x.W0) {
+    p = 0;
+    f = x.fa + t;
+    o = t;
+  } else {
+    const int t2 = t - x.W0;
+    p = 1 + t2 / x.nf;
+    f = t2 - (p - 1) * x.nf;
+    o = x.W0 + 3 + (p - 1) * (x.nf + 3) + f;
+  }
+}
+
+// x sweep: tiles of consecutive x faces staged in LDS; one x face per lane.
+// Writes the hydro flux, the face EMFs (E_y, E_z), the CT mass flux and the
+// cell EMF of every owned cell; with L.lam also the tile's max CFL rate
+// (stage 1, the state at the start of the step).
 // WPE: minimum resident wavefronts per SIMD the register allocation must
 // allow (1 = unconstrained); one of the tunable launch variants.
 template <typename real, int WPE>
@@ -708,31 +764,16 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const int bi = find_box(table(L.base) + kXS * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kXS * (L.nboxes + 1) + bi];
-    const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
-    const int nrows = ny * nz;
-    int W, R, r0, i0;
-    if (b.xseg == 1) {
-      W = b.nf[0];
-      R = b.xr;
-      r0 = lt * R;
-      i0 = 0;
-    } else {
-      const int seg = lt % b.xseg;
-      r0 = lt / b.xseg;
-      R = 1;
-      i0 = seg * b.xw;
-      W = min(b.xw, b.nf[0] - i0);
-    }
-    const int j00 = r0 % ny, k00 = r0 / ny;  // first row of the tile (uniform)
+    const int nx = b.n[0];
+    const XTile x = x_tile(b, lt);
     double lmax = 0.0;
     if (b.act[0]) {
-      const int WL = W + 3;
-      const int ncell = R * WL;
+      const int npieces = 1 + (x.nF - x.W0 + x.nf - 1) / x.nf;
+      const int ncell = x.nF + 3 * npieces;
       for (int sidx = threadIdx.x; sidx < ncell; sidx += kTPB) {
-        int r, o, j, k;
-        tile_slot(sidx, R, WL, r0, ny, j00, k00, r, o, j, k);
-        if (r0 + r >= nrows) continue;
-        const int i = i0 - 2 + o;
+        int p, i, own, j, k;
+        x_slot(x, sidx, p, i, own);
+        x_row(x, p, j, k);
         const int im = map_cell(i, nx, b.per[0]);
         PrimD w;
         const int fl = load_prim(b, s, im, j, k, w);
@@ -743,7 +784,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         sw[4][sidx] = (real)w.p;
         sw[5][sidx] = (real)w.by;
         sw[6][sidx] = (real)w.bz;
-        if (o >= 2 && o < W + 2 && i >= 0 && i < nx) {
+        if (own && i >= 0 && i < nx) {
           const int c = cidx(b, i, j, k);
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
           st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
@@ -756,12 +797,10 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         }
       }
       __syncthreads();
-      for (int t = threadIdx.x; t < R * W; t += kTPB) {
-        int r, fo, j, k;
-        tile_slot(t, R, W, r0, ny, j00, k00, r, fo, j, k);
-        if (r0 + r >= nrows) continue;
-        const int f = i0 + fo;
-        const int o = r * WL + fo;
+      for (int t = threadIdx.x; t < x.nF; t += kTPB) {
+        int p, f, o, j, k;
+        x_face(x, t, p, f, o);
+        x_row(x, p, j, k);
         St7<real> q[4];
 #pragma unroll
         for (int m = 0; m < 4; m++)
@@ -785,11 +824,10 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       }
     } else {
       // inactive x: the face carries the cell's physical flux (no divergence)
-      for (int t = threadIdx.x; t < R * W; t += kTPB) {
-        int r, fo, j, k;
-        tile_slot(t, R, W, r0, ny, j00, k00, r, fo, j, k);
-        if (r0 + r >= nrows) continue;
-        const int f = i0 + fo;
+      for (int t = threadIdx.x; t < x.nF; t += kTPB) {
+        int p, f, o, j, k;
+        x_face(x, t, p, f, o);
+        x_row(x, p, j, k);
         const int im = map_cell(f, nx, b.per[0]);
         PrimD w;
         const int fl = load_prim(b, s, im, j, k, w);

@@ -148,28 +148,28 @@ int validate_config(const mhd_config* cfg, std::string& err) {
 
 // tiling of one box (the y/z march segment lengths are tunable)
 struct Tiling {
-  int xw, xr, xseg, ysl, yseg, zsl, zseg;
+  int xft, ysl, yseg, zsl, zseg;
   int ntile[6];
 };
 
 Tiling tiling_of(const Geom& g, int ysl, int zsl) {
   Tiling t;
-  if (g.nf[0] <= kTPB) {
-    t.xw = g.nf[0];
-    t.xr = std::min(kTPB / g.nf[0], mhd::kLdsCells / (g.nf[0] + 3));
-    if (t.xr < 1) t.xr = 1;
-    t.xseg = 1;
+  // x sweep: kTPB consecutive faces of the rows per tile when the pieces of
+  // rows they touch fit the LDS, else whole rows
+  const int nf = g.nf[0];
+  const int pieces = (kTPB - 1) / nf + 2;
+  if (kTPB + 3 * pieces <= mhd::kLdsCells) {
+    t.xft = kTPB;
   } else {
-    t.xw = kTPB;
-    t.xr = 1;
-    t.xseg = (g.nf[0] + kTPB - 1) / kTPB;
+    const int R = std::max(1, std::min(kTPB / nf, mhd::kLdsCells / (nf + 3)));
+    t.xft = R * nf;
   }
   t.ysl = g.act[1] ? std::max(1, std::min(ysl, g.n[1])) : 1;
   t.yseg = (g.n[1] + t.ysl - 1) / t.ysl;
   t.zsl = g.act[2] ? std::max(1, std::min(zsl, g.n[2])) : 1;
   t.zseg = (g.n[2] + t.zsl - 1) / t.zsl;
   const long long nrows = (long long)g.n[1] * g.n[2];
-  t.ntile[mhd::kXS] = (int)(t.xseg == 1 ? (nrows + t.xr - 1) / t.xr : nrows * t.xseg);
+  t.ntile[mhd::kXS] = (int)((nrows * nf + t.xft - 1) / t.xft);
   t.ntile[mhd::kYS] = (int)(((long long)g.n[0] * g.n[2] + kTPB - 1) / kTPB * t.yseg);
   t.ntile[mhd::kZS] = (int)(((long long)g.n[0] * g.n[1] + kTPB - 1) / kTPB * t.zseg);
   const long long P = (long long)g.nf[0] * g.nf[1] * g.nf[2];
@@ -555,9 +555,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
         take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
-    b.xw = t.xw;
-    b.xr = t.xr;
-    b.xseg = t.xseg;
+    b.xft = t.xft;
     b.ysl = t.ysl;
     b.yseg = t.yseg;
     b.zsl = t.zsl;
