@@ -67,6 +67,7 @@ struct orc_box {
   int bc[3];
   int active[3];
   int rk;               /* Runge-Kutta stages: 2 (SSP-RK2) or 3 (SSP-RK3) */
+  int solver;           /* Riemann solver: ORC_HLLD (HLL fallback) or ORC_HLL */
   double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
@@ -497,6 +498,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->bc[d] = bc[d];
     b->active[d] = n[d] > 1;
     b->rk = 2;
+    b->solver = ORC_HLLD;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
     b->idx[d] = 1.0 / b->dx[d];
   }
@@ -746,7 +748,17 @@ static void sweep(orc_box *b, int d) {
         }
         double bn = b->B[d][fidx];
         double f[7], fm;
-        int used_hll = riemann(wl, wr, bn, b->gamma, f, &fm);
+        int used_hll;
+        if (b->solver == ORC_HLL) {
+          /* HLL at every face (the paper's 2D Riemann runs use it) */
+          double sl, sr;
+          orc_hll(wl, wr, bn, b->gamma, f);
+          wave_speeds(wl, wr, bn, b->gamma, &sl, &sr);
+          fm = ct_mass_flux(f[0], wl, wr, sl, sr);
+          used_hll = 0;
+        } else {
+          used_hll = riemann(wl, wr, bn, b->gamma, f, &fm);
+        }
         /* count each distinct interior face once */
         int interior = 1;
         for (a = 0; a < 3; a++) {
@@ -932,6 +944,12 @@ void orc_step_fixed_dt(orc_box *b, double dt) {
 int orc_set_rk(orc_box *b, int stages) {
   if (stages != 2 && stages != 3) return -1;
   b->rk = stages;
+  return 0;
+}
+
+int orc_set_solver(orc_box *b, int solver) {
+  if (solver != ORC_HLLD && solver != ORC_HLL) return -1;
+  b->solver = solver;
   return 0;
 }
 

@@ -50,6 +50,11 @@ void orc_get_state(const orc_box *b, double *const cons[5],
 void orc_step(orc_box *b, int nsteps, double t_stop);
 /* Integrator: 2 (SSP-RK2, the default) or 3 (SSP-RK3) stages; -1 otherwise. */
 int orc_set_rk(orc_box *b, int stages);
+/* Riemann solver of every face: ORC_HLLD (the default; HLL where the HLLD
+ * star states are not physical) or ORC_HLL (HLL everywhere); -1 otherwise. */
+#define ORC_HLLD 0
+#define ORC_HLL 1
+int orc_set_solver(orc_box *b, int solver);
 /* One step with a caller-given dt (used for sampled parity on sub-boxes). */
 void orc_step_fixed_dt(orc_box *b, double dt);
 /* CFL time step of the current state (no t_stop clamp). */

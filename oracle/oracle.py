@@ -18,6 +18,9 @@ _LIB = None
 
 _dp = C.POINTER(C.c_double)
 
+# Riemann solvers of the scheme (values of ORC_HLLD / ORC_HLL)
+SOLVERS = {"hlld": 0, "hll": 1}
+
 
 def _lib():
     global _LIB
@@ -41,6 +44,8 @@ def _lib():
         lib.orc_step_fixed_dt.argtypes = [C.c_void_p, C.c_double]
         lib.orc_set_rk.argtypes = [C.c_void_p, C.c_int]
         lib.orc_set_rk.restype = C.c_int
+        lib.orc_set_solver.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_solver.restype = C.c_int
         lib.orc_dt.argtypes = [C.c_void_p]
         lib.orc_dt.restype = C.c_double
         lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
@@ -80,7 +85,7 @@ def _vec(x, n):
 class OracleBox:
     """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
 
-    def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2):
+    def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2, solver: str = "hlld"):
         lib = _lib()
         self.spec = spec
         self.n = tuple(int(v) for v in spec.n)
@@ -94,6 +99,9 @@ class OracleBox:
         if lib.orc_set_rk(self._h, int(rk)) != 0:
             self.close()
             raise ValueError("oracle: rk must be 2 or 3")
+        if solver not in SOLVERS or lib.orc_set_solver(self._h, SOLVERS[solver]) != 0:
+            self.close()
+            raise ValueError("oracle: solver must be 'hlld' or 'hll'")
 
     def close(self):
         if self._h:

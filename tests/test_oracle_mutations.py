@@ -53,6 +53,11 @@ MUTATIONS = [
      "test_oracle_scheme.py::test_uniform_dt_closed_form"),
     ("periodic_ghost_off_by_one", "while (i < 0) i += n;", "while (i < 0) i += n - 1;",
      "test_oracle_scheme.py::test_conservation_divb_mean_field"),
+    ("hll_switch_ignored", "if (b->solver == ORC_HLL) {", "if (0) {",
+     "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
+    ("hll_upwind_term_sign", "f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;",
+     "f[c] = (sr * fL[c] - sl * fR[c] - sl * sr * (uR[c] - uL[c])) * isd;",
+     "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
 ]
 
 

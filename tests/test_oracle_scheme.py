@@ -14,8 +14,8 @@ import oracle as O
 from paper_2606_12753_amd import workloads as W
 
 
-def make(wl, i=0, pfloor=1e-10, rk=2):
-    b = O.OracleBox(wl.boxes[i], pfloor=pfloor, rk=rk)
+def make(wl, i=0, pfloor=1e-10, rk=2, solver="hlld"):
+    b = O.OracleBox(wl.boxes[i], pfloor=pfloor, rk=rk, solver=solver)
     st = wl.states[i]
     b.set_state(st.cons, st.bface, st.t)
     return b
@@ -28,11 +28,12 @@ def rel_l1(a, b):
 
 # ---------------------------------------------------------------- invariants
 
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0), (1, 1, 1)])
 @pytest.mark.parametrize("n", [(6, 5, 4), (8, 6, 1)])
-def test_uniform_state_bitwise(bc, n):
+def test_uniform_state_bitwise(bc, n, solver):
     wl = W.uniform(n=n, bc=bc)
-    b = make(wl)
+    b = make(wl, solver=solver)
     b.step(4)
     cons, bf, t = b.get_state()
     for c, c0 in zip(cons, wl.states[0].cons):
@@ -106,10 +107,11 @@ def test_uniform_dt_closed_form():
     assert b.dt() == pytest.approx(0.3 / max(rates), rel=4e-16 * 8)
 
 
-@pytest.mark.parametrize("seed,rk", [(1, 2), (2, 2), (3, 3)])
-def test_conservation_divb_mean_field(seed, rk):
+@pytest.mark.parametrize("seed,rk,solver", [(1, 2, "hlld"), (2, 2, "hlld"), (3, 3, "hlld"),
+                                           (4, 2, "hll"), (5, 3, "hll")])
+def test_conservation_divb_mean_field(seed, rk, solver):
     wl = W.random_smooth(n=(12, 10, 8), seed=seed)
-    b = make(wl, rk=rk)
+    b = make(wl, rk=rk, solver=solver)
     st0 = wl.states[0]
     d0 = b.divb_max()
     b.step(6)
@@ -345,6 +347,38 @@ def _sod_exact(x, t, gamma, wl, wr, x0=0.5):
     return rho
 
 
+def test_hll_stationary_contact_closed_form():
+    """HLL everywhere: at an isolated stationary contact (v = 0, equal total
+    pressure, uniform transverse field) the minmod slopes next to the jump
+    vanish, both face states are the cell values, and the HLL flux with
+    S = -/+ c (c the larger fast speed, sqrt(a^2 + b^2) for a field normal
+    to the axis) smears the density alone: F_rho = -c (rho_R - rho_L) / 2,
+    every other flux equals its uniform value.  HLLD keeps the contact
+    exactly (zero residual)."""
+    gamma, p, by = 5.0 / 3.0, 0.6, 0.8
+    rl, rr = 1.0, 0.25
+    n = 16
+    spec = W.BoxSpec((n, 1, 1), bc=(W.OUTFLOW, 0, 0), gamma=gamma)
+    x = W.centres(spec, 0)
+    rho = np.where(x < 0.5, rl, rr).reshape(1, 1, n)
+    bface = [np.zeros(sh) for sh in W.face_shapes(spec)]
+    bface[1][...] = by
+    st = W.conserved(spec, rho, 0.0, 0.0, 0.0, p, bface)
+    i = n // 2 - 1  # last cell of the left state
+    c = math.sqrt(gamma * p / rr + by * by / rr)
+    expect = c * (rr - rl) / 2 / spec.dx[0]
+    for solver in ("hll", "hlld"):
+        b = O.OracleBox(spec, solver=solver)
+        b.set_state(st.cons, st.bface)
+        res, rb = b.rhs()
+        want = np.zeros(n)
+        if solver == "hll":
+            want[i], want[i + 1] = expect, -expect
+        assert np.allclose(res[0].ravel(), want, rtol=1e-14, atol=1e-14 * abs(expect)), solver
+        for q in range(1, 5):
+            assert np.max(np.abs(res[q])) <= 1e-14 * abs(expect), (solver, q)
+
+
 @pytest.mark.parametrize("axis", [0, 2])
 def test_sod_shock_tube_against_exact(axis):
     """B = 0: the scheme is a hydrodynamic Godunov scheme; its density
@@ -375,3 +409,29 @@ def test_sod_shock_tube_against_exact(axis):
     assert errs[2] < errs[1] < errs[0]
     assert errs[1] < 0.01, errs
     assert math.log2(errs[0] / errs[2]) / 2 > 0.6, errs
+
+
+def test_sod_hll_converges_and_smears_more_than_hlld():
+    """HLL everywhere on the Sod tube: the density still converges to the
+    exact solution, and at every resolution its error exceeds that of HLLD
+    (which for B = 0 resolves the contact as HLLC does; HLL smears it)."""
+    gamma = 1.4
+    errs = {"hll": [], "hlld": []}
+    for n in (100, 200, 400):
+        spec = W.BoxSpec((n, 1, 1), bc=(W.OUTFLOW, 0, 0), gamma=gamma, cfl=0.4)
+        x = W.centres(spec, 0)
+        left = (x < 0.5).reshape(1, 1, n)
+        rho = np.where(left, 1.0, 0.125)
+        p = np.where(left, 1.0, 0.1)
+        bface = [np.zeros(s) for s in W.face_shapes(spec)]
+        st = W.conserved(spec, rho, 0.0, 0.0, 0.0, p, bface)
+        exact = _sod_exact(x, 0.2, gamma, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+        for solver in errs:
+            b = O.OracleBox(spec, solver=solver)
+            b.set_state(st.cons, st.bface)
+            _run_to(b, 0.2)
+            cons, _, _ = b.get_state()
+            errs[solver].append(float(np.mean(np.abs(cons[0].ravel() - exact))))
+    e = errs["hll"]
+    assert e[2] < e[1] < e[0] and e[1] < 0.015, errs
+    assert all(a > 1.02 * b for a, b in zip(errs["hll"], errs["hlld"])), errs
