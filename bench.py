@@ -78,8 +78,11 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--accuracy", action="store_true")
     ap.add_argument("--paper-workload", action="store_true",
-                    help="the paper's 3D Orszag-Tang case (10 SSP-RK3 steps) instead")
-    ap.add_argument("--ot-n", type=int, default=352, help="cells per axis of that case")
+                    help="the paper's 3D Orszag-Tang and 2D Riemann cases instead")
+    ap.add_argument("--paper-case", choices=["orszag_tang_3d", "riemann_2d"], default=None,
+                    help="only this one of the paper's cases")
+    ap.add_argument("--ot-n", type=int, default=352, help="cells per axis of the 3D case")
+    ap.add_argument("--riemann-n", type=int, default=3200, help="cells per axis of the 2D case")
     ap.add_argument("--counter-pass", action="store_true",
                     help="dispatches for a rocprofv3 --pmc run (calibration copy, then "
                          "--steps unfused steps of each precision)")
@@ -166,7 +169,7 @@ def kind_of(name):
     return None
 
 
-def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2):
+def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld"):
     """Per repeat: set the initial state, `warmup` untimed steps (the first
     repeat's include the autotuner's trials), then `steps` timed steps.
     Returns the median time, every repeat's time, the final state of box 0
@@ -174,7 +177,8 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2):
     import torch
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
-    sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk)
+    sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk,
+                  solver=solver)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     times = []
@@ -532,38 +536,72 @@ def summarize_trace(a):
 
 # The paper's Figure 1: wall time of 10 steps of its 3D Orszag-Tang run on
 # 352^3 cells (whole application, third-order Runge-Kutta), by hardware and
-# programming model.  Context only: other hardware, other code.
+# programming model; Table 3: one invocation (one direction, one stage) of
+# its reconstruction and HLL kernels on the 3200^2 2D Riemann problem, A100.
+# Context only: other hardware, other code.
 PAPER_OT3D_10_STEPS_S = {"A100, OpenACC": 13.9, "A100, OpenMP": 17.2,
                          "MI250X (one GCD), OpenMP": 48.1}
+PAPER_RIEMANN2D_INVOCATION_MS = {"Reconstruct, A100 OpenACC": 1.24,
+                                 "Reconstruct, A100 OpenMP": 58.0,
+                                 "HLL, A100 OpenACC": 1.63, "HLL, A100 OpenMP": 9.84}
+
+
+def kernel_times_of(wl, precision, steps, variant, rk, solver):
+    """kernel_times for a given integrator and Riemann solver."""
+    import torch
+    from paper_2606_12753_amd import mhd
+    os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
+    try:
+        stream = torch.cuda.Stream()
+        sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
+                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver)
+        for b, st in enumerate(wl.states):
+            sim.set_state(b, st.cons, st.bface, 0.0)
+        sim.step(1)
+        sim.kernel_times(reset=True)
+        sim.step(steps)
+        kt = sim.kernel_times()
+        sim.close()
+    finally:
+        del os.environ["MHD_VARIANT"]
+    return {k: round(v[0] / v[1], 4) for k, v in kt.items() if v[1]}
 
 
 def paper_workload(a, flags):
-    """The paper's profiled case on this library: 3D Orszag-Tang, 352^3
-    cells, 10 SSP-RK3 steps, FP64 and mixed, median of the timed repeats."""
+    """The paper's two profiled cases on this library, FP64 and mixed, 10
+    steps each, median of three timed repeats: the 3D Orszag-Tang vortex on
+    352^3 cells (HLLD, SSP-RK3) and the thin 2D Riemann problem on 3200^2
+    cells (HLL, SSP-RK3), with per-launch kernel times (ms) of each."""
     from paper_2606_12753_amd import mhd, workloads
-    print("# paper workload: building 3D Orszag-Tang", file=sys.stderr, flush=True)
-    wl = workloads.orszag_tang_3d(n=a.ot_n, steps=10)
-    res = {}
-    for prec, key in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
-        print(f"# paper workload: {key}", file=sys.stderr, flush=True)
-        r = run_gpu(wl, prec, 10, 2, flags, repeats=3, rk=3)
-        r["sim"].close()
-        res[key] = r
-    spec = wl.boxes[0]
-    out = {
-        "workload": f"orszag_tang_3d {a.ot_n}^3, SSP-RK3, 10 steps, PLM-minmod+HLLD+CT, CFL 0.3",
-        "cells": wl.cells,
-        "fp64": {"s_10_steps": round(res["fp64"]["ms"] * 1e-3, 4),
-                 "Mcell_updates_per_s": round(wl.cells * 10 / (res["fp64"]["ms"] * 1e-3) / 1e6, 1),
-                 "variant": res["fp64"]["variant"]},
-        "mixed": {"s_10_steps": round(res["mixed"]["ms"] * 1e-3, 4),
-                  "Mcell_updates_per_s": round(wl.cells * 10 / (res["mixed"]["ms"] * 1e-3) / 1e6, 1),
-                  "variant": res["mixed"]["variant"]},
-        "speedup_mixed": round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
-        "paper_s_10_steps": PAPER_OT3D_10_STEPS_S,
-    }
-    out.update(compare(spec, res["fp64"]["state"], res["mixed"]["state"]))
-    print(json.dumps(out), flush=True)
+    cases = [("orszag_tang_3d", lambda: workloads.orszag_tang_3d(n=a.ot_n, steps=10), "hlld",
+              f"orszag_tang_3d {a.ot_n}^3, SSP-RK3, 10 steps, PLM-minmod+HLLD+CT, CFL 0.3",
+              {"paper_s_10_steps": PAPER_OT3D_10_STEPS_S}),
+             ("riemann_2d", lambda: workloads.riemann_2d(n=a.riemann_n, steps=10), "hll",
+              f"riemann_2d {a.riemann_n}x{a.riemann_n}x1, SSP-RK3, 10 steps, PLM-minmod+HLL+CT, CFL 0.4",
+              {"paper_ms_per_invocation": PAPER_RIEMANN2D_INVOCATION_MS})]
+    for name, make, solver, desc, ctx in cases:
+        if a.paper_case and name != a.paper_case:
+            continue
+        print(f"# paper workload: building {name}", file=sys.stderr, flush=True)
+        wl = make()
+        res = {}
+        for prec, key in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
+            print(f"# paper workload: {name} {key}", file=sys.stderr, flush=True)
+            r = run_gpu(wl, prec, 10, 2, flags, repeats=3, rk=3, solver=solver)
+            r["sim"].close()
+            r["kernels_ms"] = kernel_times_of(wl, prec, 3, r["variant"], 3, solver)
+            res[key] = r
+        out = {"workload": desc, "cells": wl.cells}
+        for key in ("fp64", "mixed"):
+            r = res[key]
+            out[key] = {"s_10_steps": round(r["ms"] * 1e-3, 4),
+                        "Mcell_updates_per_s": round(wl.cells * 10 / (r["ms"] * 1e-3) / 1e6, 1),
+                        "variant": r["variant"], "kernels_ms_per_launch": r["kernels_ms"]}
+        out["speedup_mixed"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+        out.update(ctx)
+        out.update(compare(wl.boxes[0], res["fp64"]["state"], res["mixed"]["state"]))
+        print(json.dumps(out), flush=True)
+        del wl, res
 
 
 def accuracy(flags):

@@ -6,7 +6,7 @@
  * primitive variables, a Riemann solve at every interface and a
  * flux-conservative update; constrained transport (CT) for the magnetic
  * field; Runge-Kutta stepping.  Concretely: PLM-minmod reconstruction, HLLD
- * fluxes with HLL fallback, the flux-divergence update, contact-upwinded CT
+ * fluxes with HLL fallback (or HLL alone), the flux-divergence update, contact-upwinded CT
  * corner EMFs with the face-field update, the CFL time step from a
  * max-reduction of the fast magnetosonic rate and the SSP Runge-Kutta
  * stage combines (two or three stages), on 3D structured boxes (2D and 1D as
@@ -51,6 +51,13 @@ extern "C" {
 #define MHD_FP64 0  /* everything FP64 */
 #define MHD_MIXED 1 /* FP32 reconstruction, fluxes, EMFs, residual; FP64
                        state, pressure recovery, RK accumulation, dt */
+
+/* Riemann solver of every face (the paper's 3D runs use HLLD, its 2D
+ * Riemann runs HLL) */
+#define MHD_RS_HLLD 0 /* HLLD (Miyoshi & Kusano 2005); HLL where its star
+                         states are not physical */
+#define MHD_RS_HLL 1  /* HLL (Harten, Lax & van Leer 1983) with the same
+                         outer wave speeds */
 
 /* where caller arrays live */
 #define MHD_HOST 0
@@ -104,6 +111,7 @@ typedef struct {
                               (SSP-RK3, Shu & Osher 1988: the paper's default
                               third-order scheme; one more state copy in the
                               workspace) */
+  int32_t riemann;         /* MHD_RS_HLLD (0) or MHD_RS_HLL */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;

@@ -479,17 +479,18 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
   }
 }
 
-// Riemann flux at one face: HLLD, HLL when the HLLD star states are not
-// physical.  f[7] = (mass, mom n, mom t1, mom t2, energy, B_t1, B_t2); *fm is
-// the mass flux handed to the CT upwinding (zero when zero up to rounding).
-// Returns 1 when HLL was used.
+// Riemann flux at one face.  RS = 0: HLLD, HLL when the HLLD star states are
+// not physical; RS = 1: HLL at every face.  f[7] = (mass, mom n, mom t1,
+// mom t2, energy, B_t1, B_t2); *fm is the mass flux handed to the CT
+// upwinding (zero when zero up to rounding).  Returns 1 when HLLD fell back
+// to HLL.
 //
 // The flux of the Riemann fan at x/t = 0 lies on the side of the contact
 // given by sign(S_M): the solver computes both single-star states (both
 // enter the double-star average and the positivity check), then selects the
 // side once and assembles F*, and F** when the rotational wave of that side
 // is left of (right of) x/t = 0, with selects instead of divergent branches.
-template <typename real>
+template <typename real, int RS>
 __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr, real bn,
                                        real gamma, real igm1, real* f, real* fm) {
   // max(c_fL, c_fR) as the square root of the larger square: a correctly
@@ -502,7 +503,9 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
   real sl = umin - cmax;
   real sr = umax + cmax;
   int used = 0;
-  if (sl > (real)0 || sr < (real)0) {
+  if (RS == 1) {
+    hll_flux(wl, wr, bn, igm1, sl, sr, f);
+  } else if (sl > (real)0 || sr < (real)0) {
     // supersonic: physical flux of the upwind state
     St7<real> w;
     const bool left = sl > (real)0;
@@ -752,8 +755,9 @@ __device__ __forceinline__ void x_face(const XTile& x, int t, int& p, int& f, in
 // cell EMF of every owned cell; with L.lam also the tile's max CFL rate
 // (stage 1, the state at the start of the step).
 // WPE: minimum resident wavefronts per SIMD the register allocation must
-// allow (1 = unconstrained); one of the tunable launch variants.
-template <typename real, int WPE>
+// allow (1 = unconstrained); one of the tunable launch variants.  RS: the
+// Riemann solver (see riemann).
+template <typename real, int WPE, int RS>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_x(
     Launch L) {
   __shared__ real sw[7][kLdsCells];
@@ -811,7 +815,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         const int fi = fidx(b, 0, f, j, k);
         const real bn = (real)ld<double>(b.B[s][0], fi);
         real F[7], fm;
-        const int used = riemann(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
+        const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
         st<real>(b.FX[0], fi, F[0]);
         st<real>(b.FX[1], fi, F[1]);
         st<real>(b.FX[2], fi, F[2]);
@@ -947,7 +951,7 @@ struct Window<real, 1> {
 // the state the RK combine reads (U^n in stage 1, U* in stage 2), three
 // faces after the sweep loaded it, when it has usually left L2; the ring
 // saves that second fetch.
-template <typename real, int D, int PF, int LW, int CU>
+template <typename real, int D, int PF, int LW, int CU, int RS>
 __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, int i, int tr,
                                              int j0, int j1, real (*lds)[kTPB],
                                              double (*ring)[kTPB]) {
@@ -1039,7 +1043,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
     const real bn = (real)ld<double>(b.B[s][D], fi);
     real F[7], fm;
-    const int used = riemann(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
+    const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
     // lab-frame hydro flux: (rho, mx, my, mz, E)
     real fl[kNQ];
     fl[0] = F[0];
@@ -1117,8 +1121,9 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int com
 }
 
 // PF: prefetch the inputs of the cell update ahead of the Riemann solve
-// (latency hidden, more registers live across the solve)
-template <typename real, int D, int WPE, int PF, int LW, int CU>
+// (latency hidden, more registers live across the solve); RS: the Riemann
+// solver (see riemann)
+template <typename real, int D, int WPE, int PF, int LW, int CU, int RS>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
@@ -1143,7 +1148,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW, CU>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
+      march_column<real, D, PF, LW, CU, RS>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
     } else {
       inactive_column<real, D>(b, L.stage, L.dst, L.comb, i, tr);
     }

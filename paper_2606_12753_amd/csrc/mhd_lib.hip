@@ -136,6 +136,10 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     err = "config: rk_stages must be 2 or 3 (0: 2)";
     return MHD_E_INVAL;
   }
+  if (cfg->riemann != MHD_RS_HLLD && cfg->riemann != MHD_RS_HLL) {
+    err = "config: riemann must be MHD_RS_HLLD or MHD_RS_HLL";
+    return MHD_E_INVAL;
+  }
   for (int b = 0; b < cfg->nboxes; b++) {
     int rc = validate_box(cfg->boxes[b], err);
     if (rc) {
@@ -247,6 +251,7 @@ struct mhd_ctx {
   std::vector<mhd_box> boxes;
   int precision = MHD_FP64;
   int rk = 2;  // Runge-Kutta stages
+  int rs = 0;  // Riemann solver (MHD_RS_*)
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -312,6 +317,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.var_x = c->var_x;
   sc.var_m = c->var_m;
   sc.rk = c->rk;
+  sc.rs = c->rs;
   sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
@@ -711,6 +717,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->pfloor = cfg->p_floor > 0.0 ? cfg->p_floor : 1e-10;
   c->flags = cfg->flags;
   c->rk = cfg->rk_stages == 3 ? 3 : 2;
+  c->rs = cfg->riemann;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";

@@ -1,4 +1,4 @@
-// mhd_step.hpp -- the launch sequence of one SSP-RK2 step.
+// mhd_step.hpp -- the launch sequence of one Runge-Kutta step.
 //
 // Every stage (two, or three for SSP-RK3) runs: the x sweep (stage 1 also
 // reduces the CFL rate of the start-of-step state, and the per-box dt
@@ -24,18 +24,19 @@ struct StepCtx {
   const int* grid;     // persistent grid size per kind (0: one group per tile)
   int var_x, var_m;    // launch variants of the x sweep and the marches
   int rk;              // Runge-Kutta stages: 2 or 3
+  int rs;              // Riemann solver: 0 HLLD (HLL fallback), 1 HLL
   int xcd;             // XCD-grouped tile order
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
   int* ev_kind;        // timing: kernel kind of each pair
 };
 
-template <typename real>
+template <typename real, int RS>
 inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
   switch (wpe) {
-    case 3: hipLaunchKernelGGL((k_sweep_x<real, 3>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_x<real, 4>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((k_sweep_x<real, 1>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_x<real, 3, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_x<real, 4, RS>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_x<real, 1, RS>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
@@ -46,29 +47,29 @@ inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
 // SIMD and no prefetch; 8, 9, 10 = variants 2, 6, 7 with the z march's
 // swept state kept in an LDS ring for the RK combine (the y march has no
 // combine and runs 2, 6, 7)
-template <typename real, int D>
+template <typename real, int D, int RS>
 inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
   if (D == 1 && var >= 8) var = var == 8 ? 2 : var == 9 ? 6 : 7;
   switch (var) {
-    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0>), g, dim3(kTPB), 0, st, L); break;
-    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
     case 8:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1, RS>), g, dim3(kTPB), 0, st, L);
       break;
     case 9:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1, RS>), g, dim3(kTPB), 0, st, L);
       break;
     case 10:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1, RS>), g, dim3(kTPB), 0, st, L);
       break;
-    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
@@ -107,7 +108,10 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     L.lam = s == 0;
     L.ntiles = sc.total[kXS];
     mark(MHD_K_SWEEP_X, true);
-    launch_x<real>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+    if (sc.rs)
+      launch_x<real, 1>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+    else
+      launch_x<real, 0>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
     mark(MHD_K_SWEEP_X, false);
     L.lam = 0;
     if (s == 0) {
@@ -117,11 +121,17 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     }
     L.ntiles = sc.total[kYS];
     mark(MHD_K_SWEEP_Y, true);
-    launch_march<real, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    if (sc.rs)
+      launch_march<real, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    else
+      launch_march<real, 1, 0>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
     mark(MHD_K_SWEEP_Y, false);
     L.ntiles = sc.total[kZS];
     mark(MHD_K_SWEEP_Z, true);
-    launch_march<real, 2>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+    if (sc.rs)
+      launch_march<real, 2, 1>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+    else
+      launch_march<real, 2, 0>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
     mark(MHD_K_SWEEP_Z, false);
     L.ntiles = sc.total[kCTE];
     mark(MHD_K_CT_EDGE, true);

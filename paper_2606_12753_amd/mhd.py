@@ -36,6 +36,9 @@ MHD_F_GRAPH = 1
 MHD_F_PERSISTENT = 2
 MHD_F_TIMING = 4
 MHD_F_AUTOTUNE = 8
+MHD_RS_HLLD = 0
+MHD_RS_HLL = 1
+SOLVERS = {"hlld": MHD_RS_HLLD, "hll": MHD_RS_HLL}
 KERNELS = ["lambda", "dt", "sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 
 EXPORTED = [
@@ -74,6 +77,7 @@ class mhd_config(C.Structure):
         ("workspace_bytes", C.c_uint64),
         ("flags", C.c_uint32),
         ("rk_stages", C.c_int32),
+        ("riemann", C.c_int32),
     ]
 
 
@@ -132,7 +136,7 @@ def _box_struct(spec) -> mhd_box:
 
 def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
                 stream=None, workspace=None, workspace_bytes: int = 0, flags: int = 0,
-                rk: int = 2):
+                rk: int = 2, solver: str = "hlld"):
     arr = (mhd_box * len(boxes))(*[_box_struct(s) for s in boxes])
     cfg = mhd_config()
     cfg.nboxes = len(boxes)
@@ -144,12 +148,13 @@ def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0
     cfg.workspace_bytes = int(workspace_bytes)
     cfg.flags = int(flags)
     cfg.rk_stages = int(rk)
+    cfg.riemann = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     return cfg, arr  # keep arr alive with cfg
 
 
-def mhd_workspace_bytes(boxes, precision=MHD_FP64, flags=0, rk=2) -> int:
+def mhd_workspace_bytes(boxes, precision=MHD_FP64, flags=0, rk=2, solver="hlld") -> int:
     lib = load()
-    cfg, _keep = make_config(boxes, precision, flags=flags, rk=rk)
+    cfg, _keep = make_config(boxes, precision, flags=flags, rk=rk, solver=solver)
     out = C.c_uint64()
     rc = lib.mhd_workspace_bytes(C.byref(cfg), C.byref(out))
     if rc != MHD_OK:
@@ -165,7 +170,8 @@ class Sim:
     """One library context: an ensemble of boxes advanced together."""
 
     def __init__(self, boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
-                 stream=None, workspace=None, flags: int = 0, rk: int = 2):
+                 stream=None, workspace=None, flags: int = 0, rk: int = 2,
+                 solver: str = "hlld"):
         self._lib = load()
         self.boxes = list(boxes)
         self._h = None
@@ -174,7 +180,7 @@ class Sim:
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         self._workspace = workspace
         cfg, self._keep = make_config(self.boxes, precision, p_floor, stream, ws_ptr, ws_bytes,
-                                      flags, rk)
+                                      flags, rk, solver)
         h = C.c_void_p()
         rc = self._lib.mhd_create(C.byref(cfg), C.byref(h))
         if rc != MHD_OK:

@@ -252,6 +252,28 @@ def orszag_tang_3d(n: int = 352, steps: int = 10) -> Workload:
     return Workload("orszag_tang_3d", [spec], [st], steps, {"rk": 3})
 
 
+def riemann_2d(n: int = 3200, steps: int = 10) -> Workload:
+    """The paper's thin 2D case: a four-quadrant Riemann problem on n x n x 1
+    cells of the unit square (3200^2 in the paper, solved with HLL at every
+    face).  Its initial data are not published; these quadrant states are
+    this code's own: rho = 1, p = 1 in the upper-right and lower-left
+    quadrants, rho = 0.5, p = 0.35 in the other two; v = (0.75 left of
+    x = 1/2, 0.75 below y = 1/2) componentwise, v_z = 0; uniform
+    B = (0.5, 0.5, 0.25); gamma = 5/3, outflow walls, CFL 0.4, SSP-RK3.  The
+    data are symmetric under the reflection x <-> y."""
+    spec = BoxSpec((n, n, 1), bc=(OUTFLOW, OUTFLOW, PERIODIC), cfl=0.4)
+    z, y, x = _grid(spec)
+    right, top = x > 0.5, y > 0.5
+    diag = right == top
+    rho = np.where(diag, 1.0, 0.5) + 0 * z
+    p = np.where(diag, 1.0, 0.35) + 0 * z
+    vx = np.where(right, 0.0, 0.75) + 0 * y + 0 * z
+    vy = np.where(top, 0.0, 0.75) + 0 * x + 0 * z
+    bface = [np.full(s, v) for s, v in zip(face_shapes(spec), (0.5, 0.5, 0.25))]
+    st = conserved(spec, rho, vx, vy, 0.0, p, bface)
+    return Workload("riemann_2d", [spec], [st], steps, {"rk": 3, "solver": "hll"})
+
+
 def kelvin_helmholtz(nx: int = 768, ny: int = 384, nz: int = 384, seed: int = 2609,
                      steps: int = 100) -> Workload:
     """Shear layer on [-1,1]x[-0.5,0.5]^2, periodic in x and z, outflow in y:
@@ -419,6 +441,7 @@ def by_name(name: str, **kw) -> Workload:
         "turbulence_3d": turbulence_3d,
         "ensemble": ensemble,
         "orszag_tang_3d": orszag_tang_3d,
+        "riemann_2d": riemann_2d,
         "kelvin_helmholtz": kelvin_helmholtz,
     }
     return table[name](**kw)

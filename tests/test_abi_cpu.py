@@ -46,9 +46,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mhd_box), offsetof(mhd_box, lo),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mhd_box), offsetof(mhd_box, lo),
          offsetof(mhd_box, bc_lo), offsetof(mhd_box, gamma), sizeof(mhd_config),
-         offsetof(mhd_config, stream), offsetof(mhd_config, flags));
+         offsetof(mhd_config, stream), offsetof(mhd_config, flags),
+         offsetof(mhd_config, rk_stages), offsetof(mhd_config, riemann));
   return 0;
 }}''')
     exe = tmp_path / "layout"
@@ -58,7 +59,8 @@ int main(void) {{
     import ctypes as C
     got = [C.sizeof(mhd.mhd_box), mhd.mhd_box.lo.offset, mhd.mhd_box.bc_lo.offset,
            mhd.mhd_box.gamma.offset, C.sizeof(mhd.mhd_config), mhd.mhd_config.stream.offset,
-           mhd.mhd_config.flags.offset]
+           mhd.mhd_config.flags.offset, mhd.mhd_config.rk_stages.offset,
+           mhd.mhd_config.riemann.offset]
     assert vals == got
 
 
@@ -90,6 +92,11 @@ def test_validation_before_device(lib):
     with pytest.raises(mhd.MhdError) as ei:
         mhd.mhd_workspace_bytes([])
     assert ei.value.code == mhd.MHD_E_INVAL
+    for kw in ({"rk": 4}, {"solver": 2}):
+        with pytest.raises(mhd.MhdError) as ei:
+            mhd.mhd_workspace_bytes([good], **kw)
+        assert ei.value.code == mhd.MHD_E_INVAL, kw
+    assert mhd.mhd_workspace_bytes([good], solver="hll") == nbytes
     # the largest accepted box: 2^29 cells (periodic), and one active axis
     big = mhd.mhd_workspace_bytes([W.BoxSpec((1024, 1024, 512))])
     assert big > (1 << 29) * 8 * 16

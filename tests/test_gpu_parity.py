@@ -38,11 +38,12 @@ def rel_l1(a, b):
     return num / den if den > 0 else num / max(1, b.size)
 
 
-def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2):
+def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2,
+            solver="hlld"):
     idx = range(len(wl.boxes)) if boxes is None else boxes
     specs = [wl.boxes[i] for i in idx]
     out = []
-    with mhd.Sim(specs, precision=precision, flags=flags, rk=rk) as sim:
+    with mhd.Sim(specs, precision=precision, flags=flags, rk=rk, solver=solver) as sim:
         for k, i in enumerate(idx):
             st = wl.states[i]
             sim.set_state(k, st.cons, st.bface, st.t)
@@ -53,8 +54,8 @@ def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None,
     return out
 
 
-def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2):
-    b = O.OracleBox(spec, rk=rk)
+def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld"):
+    b = O.OracleBox(spec, rk=rk, solver=solver)
     b.set_state(st.cons, st.bface, st.t)
     b.step(nsteps, t_stop)
     cons, bface, t = b.get_state()
@@ -154,6 +155,47 @@ def test_rk3_orszag_tang_and_mixed():
     g = gpu_run(wl, 20, flags=mhd.MHD_F_GRAPH, rk=3)[0]
     assert_fp64_parity(g, o, "OT2D rk3")
     m = gpu_run(wl, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, rk=3)[0]
+    mp, mb = pressure_bmag(spec, m[0], m[1])
+    op, ob = pressure_bmag(spec, o[0], o[1])
+    for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+        assert rel_l1(a, b) <= TOLMIX, name
+    assert divb_norm(spec, m[1])[0] <= 1e-12
+
+
+@pytest.mark.parametrize("rk", [2, 3])
+@pytest.mark.parametrize("n,bc", [((30, 26, 22), (1, 0, 0)), ((17, 9, 1), (0, 1, 0)),
+                                  ((5, 40, 33), (1, 1, 1))])
+def test_hll_everywhere_fp64(n, bc, rk):
+    """HLL at every face (MHD_RS_HLL): the library's FP64 steps equal the
+    oracle's bit for bit, with a zero fallback counter."""
+    wl = W.random_smooth(n=n, seed=sum(n) + rk, bc=bc)
+    g = gpu_run(wl, 4, rk=rk, solver="hll")[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=rk, solver="hll")
+    assert_fp64_parity(g, o, f"hll {n} {bc} rk{rk}")
+    assert g[3]["hll"] == 0
+
+
+@pytest.mark.parametrize("variant", ["3,9,16,1", "4,4,7,0", "1,10,64,0"])
+def test_hll_launch_variants_bitwise(variant, monkeypatch):
+    wl = W.riemann_2d(n=72)
+    monkeypatch.delenv("MHD_VARIANT", raising=False)
+    ref = gpu_run(wl, 3, rk=3, solver="hll")[0]
+    monkeypatch.setenv("MHD_VARIANT", variant)
+    g = gpu_run(wl, 3, rk=3, solver="hll")[0]
+    for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
+        assert np.array_equal(a, b), variant
+
+
+def test_riemann_2d_hll_fp64_and_mixed():
+    """The thin 2D case at 96 x 96 (ragged against every tile shape), HLL
+    and SSP-RK3, 40 steps with graph replay: FP64 bit for bit; the mixed path
+    within its bar."""
+    wl = W.riemann_2d(n=96)
+    spec = wl.boxes[0]
+    o = oracle_run(spec, wl.states[0], 40, rk=3, solver="hll")
+    g = gpu_run(wl, 40, flags=mhd.MHD_F_GRAPH, rk=3, solver="hll")[0]
+    assert_fp64_parity(g, o, "riemann 2d")
+    m = gpu_run(wl, 40, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, rk=3, solver="hll")[0]
     mp, mb = pressure_bmag(spec, m[0], m[1])
     op, ob = pressure_bmag(spec, o[0], o[1])
     for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
@@ -388,12 +430,12 @@ def _sub_box(spec, st, centre, r):
     return sub, cons, bface, tuple(off)
 
 
-def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2):
+def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2, solver="hlld"):
     """One oracle step with the GPU's dt on the neighbourhood of each sampled
     cell; compares the cell's conserved state and its three lower faces."""
     for c in centres:
         sub, sc, sb, o = _sub_box(spec, st, c, r)
-        ob = O.OracleBox(sub, rk=rk)
+        ob = O.OracleBox(sub, rk=rk, solver=solver)
         ob.set_state(sc, sb)
         ob.step_fixed_dt(dt)
         oc, obf, _ = ob.get_state()
@@ -454,6 +496,30 @@ def test_orszag_tang_352_rk3_full_size_sampled():
     centres = [tuple(int(v) for v in rng.integers(0, 352, size=3)) for _ in range(3)]
     centres += [(0, 0, 0), (351, 175, 351), (88, 264, 100)]
     _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3)
+
+
+def test_riemann_2d_3200_hll_full_size_sampled():
+    """The paper's thin 2D case, 3200 x 3200 x 1 with HLL and SSP-RK3, at
+    full size with graph replay and the autotuned launch variant: one step on
+    the GPU; the oracle recomputes the time step over the whole grid and the
+    step of sampled cells at the walls, the corners, the quadrant junction
+    and inside (neighbourhoods of radius 11)."""
+    wl = W.riemann_2d(n=3200)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE, rk=3, solver="hll") as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt_gpu, _ = sim.dt(0)
+        sim.step(1)
+        cons, bface, t = sim.get_state(0)
+        assert sim.counters(0)["hll"] == 0
+    ob = O.OracleBox(spec, rk=3, solver="hll")
+    ob.set_state(st.cons, st.bface)
+    assert dt_gpu == ob.dt()
+    assert t == dt_gpu
+    del ob
+    centres = [(0, 0, 0), (3199, 3199, 0), (0, 3199, 0), (1599, 1600, 0), (1600, 1599, 0),
+               (1599, 1599, 0), (1600, 5, 0), (2345, 1600, 0), (777, 2999, 0)]
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3, solver="hll")
 
 
 def test_kelvin_helmholtz_full_size_sampled():

@@ -435,3 +435,21 @@ def test_sod_hll_converges_and_smears_more_than_hlld():
     e = errs["hll"]
     assert e[2] < e[1] < e[0] and e[1] < 0.015, errs
     assert all(a > 1.02 * b for a, b in zip(errs["hll"], errs["hlld"])), errs
+
+
+def test_riemann_2d_diagonal_mirror():
+    """The four-quadrant Riemann problem is symmetric under x <-> y (with
+    v_x <-> v_y, B_x <-> B_y; ideal MHD is invariant under this mirror with
+    B mapped like v, since B -> -B is also a symmetry).  With HLL everywhere
+    and SSP-RK3 the solution keeps the symmetry to rounding (the x and y
+    residuals are summed in a fixed order, so not bit for bit)."""
+    wl = W.riemann_2d(n=40)
+    b = make(wl, rk=3, solver="hll")
+    b.step(30)
+    cons, bf, _ = b.get_state()
+    T = lambda a: a[0].T
+    scale = [np.max(np.abs(c)) for c in cons]
+    for qa, qb in ((0, 0), (1, 2), (2, 1), (3, 3), (4, 4)):
+        assert np.max(np.abs(T(cons[qa]) - cons[qb][0])) <= 1e-12 * max(scale[qa], 1e-300), (qa, qb)
+    assert np.max(np.abs(bf[0][0].T - bf[1][0])) <= 1e-12
+    assert b.counters() == {"floor": 0, "hll": 0, "bad": 0}
