@@ -951,7 +951,7 @@ struct Window<real, 1> {
 // the state the RK combine reads (U^n in stage 1, U* in stage 2), three
 // faces after the sweep loaded it, when it has usually left L2; the ring
 // saves that second fetch.
-template <typename real, int D, int PF, int LW, int CU, int RS>
+template <typename real, int D, int PF, int LW, int CU, int RS, int FZ>
 __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, int i, int tr,
                                              int j0, int j1, real (*lds)[kTPB],
                                              double (*ring)[kTPB]) {
@@ -997,7 +997,8 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
   const int fbase = D == 1 ? (tr * b.nf[1]) * b.n[0] + i : tr * b.n[0] + i;
   const int cstride = fstride;
   const int cbase = D == 1 ? (tr * b.n[1]) * b.n[0] + i : tr * b.n[0] + i;
-  const double dt = D == 2 ? b.scal[0] : 0.0;
+  constexpr bool kFin = D == 2 || FZ;  // this march applies the RK combine
+  const double dt = kFin ? b.scal[0] : 0.0;
   int cw = (j0 + 1) % 3;  // ring slot of cell f+1 at face f
   for (int f = j0; f <= j1; ++f) {
     PrimD w;
@@ -1022,6 +1023,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
           if (b.act[0])
             r = r - ((double)ld<real>(b.FX[q], f1) - (double)ld<real>(b.FX[q], f0)) * b.idx[0];
           racc[q] = r;
+          if constexpr (FZ) {
+            usw[q] = ld<double>(b.U[s][q], cprev);
+            uold[q] = comb ? ld<double>(b.U[0][q], cprev) : 0.0;
+          }
         }
       } else {
         const int cr = cw == 2 ? 0 : cw + 1;  // ring slot of cell f-1
@@ -1063,10 +1068,23 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
 #pragma unroll
       for (int q = 0; q < kNQ; q++) {
         const double r = racc[q] - ((double)fl[q] - (double)fprev[q]) * idxD;
-        if (D == 1)
-          st<real>(b.R[q], cprev, (real)r);
-        else
+        if (kFin)
           st<double>(b.U[dst][q], cprev, rk_combine(comb, uold[q], usw[q], dt * r));
+        else
+          st<real>(b.R[q], cprev, (real)r);
+      }
+      if constexpr (FZ) {
+        // z faces of the cell (one cell along z: no z flux divergence): the
+        // face EMFs are the cell EMF and the mass flux is the momentum
+        const real ex = ld<real>(b.Ec[0], cprev), ey = ld<real>(b.Ec[1], cprev);
+        const real mz = (real)ld<double>(b.U[s][3], cprev);
+        const int nxy = b.n[0] * b.n[1];
+        for (int kf = 0; kf < b.nf[2]; ++kf) {
+          const int fz = kf * nxy + (f - 1) * b.n[0] + i;
+          st<real>(b.EF[2][0], fz, ex);
+          st<real>(b.EF[2][1], fz, ey);
+          st<real>(b.MF[2], fz, mz);
+        }
       }
     }
 #pragma unroll
@@ -1122,8 +1140,10 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int com
 
 // PF: prefetch the inputs of the cell update ahead of the Riemann solve
 // (latency hidden, more registers live across the solve); RS: the Riemann
-// solver (see riemann)
-template <typename real, int D, int WPE, int PF, int LW, int CU, int RS>
+// solver (see riemann); FZ (y march only, every box with one cell along z
+// and more than one along y): the y march completes the stage, RK combine
+// and z-face data included, and no z march runs.
+template <typename real, int D, int WPE, int PF, int LW, int CU, int RS, int FZ>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
@@ -1148,7 +1168,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW, CU, RS>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
+      march_column<real, D, PF, LW, CU, RS, FZ>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
     } else {
       inactive_column<real, D>(b, L.stage, L.dst, L.comb, i, tr);
     }

@@ -252,6 +252,7 @@ struct mhd_ctx {
   int precision = MHD_FP64;
   int rk = 2;  // Runge-Kutta stages
   int rs = 0;  // Riemann solver (MHD_RS_*)
+  int fz = 0;  // every box: one cell along z, more along y (no z march)
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -318,6 +319,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.var_m = c->var_m;
   sc.rk = c->rk;
   sc.rs = c->rs;
+  sc.fz = c->fz;
   sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
@@ -718,6 +720,9 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->flags = cfg->flags;
   c->rk = cfg->rk_stages == 3 ? 3 : 2;
   c->rs = cfg->riemann;
+  c->fz = 1;
+  for (int b = 0; b < cfg->nboxes; b++)
+    if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";

@@ -2,9 +2,10 @@
 //
 // Every stage (two, or three for SSP-RK3) runs: the x sweep (stage 1 also
 // reduces the CFL rate of the start-of-step state, and the per-box dt
-// follows), the y and z
-// marches (the z march applies the RK stage combine to the cells), the
-// corner-EMF kernel and the face update (RK stage combine of the faces).
+// follows), the y and z marches (the z march applies the RK stage combine
+// to the cells; with one cell along z in every box the y march does, and
+// no z march runs), the corner-EMF kernel and the face update (RK stage
+// combine of the faces).
 // Included by the two translation units that instantiate the kernels: the
 // FP64 one (no FMA contraction, results reproducible bit for bit) and the
 // FP32 one of the mixed path (contraction allowed).
@@ -25,6 +26,8 @@ struct StepCtx {
   int var_x, var_m;    // launch variants of the x sweep and the marches
   int rk;              // Runge-Kutta stages: 2 or 3
   int rs;              // Riemann solver: 0 HLLD (HLL fallback), 1 HLL
+  int fz;              // every box has one cell along z and more along y:
+                       // the y march completes each stage, no z march
   int xcd;             // XCD-grouped tile order
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
@@ -47,29 +50,29 @@ inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
 // SIMD and no prefetch; 8, 9, 10 = variants 2, 6, 7 with the z march's
 // swept state kept in an LDS ring for the RK combine (the y march has no
 // combine and runs 2, 6, 7)
-template <typename real, int D, int RS>
+template <typename real, int D, int RS, int FZ = 0>
 inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
   if (D == 1 && var >= 8) var = var == 8 ? 2 : var == 9 ? 6 : 7;
   switch (var) {
-    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
     case 8:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1, RS>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
       break;
     case 9:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1, RS>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
       break;
     case 10:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1, RS>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
       break;
-    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0, RS>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
@@ -121,18 +124,27 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     }
     L.ntiles = sc.total[kYS];
     mark(MHD_K_SWEEP_Y, true);
-    if (sc.rs)
-      launch_march<real, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
-    else
-      launch_march<real, 1, 0>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    if (sc.fz) {
+      if (sc.rs)
+        launch_march<real, 1, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+      else
+        launch_march<real, 1, 0, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    } else {
+      if (sc.rs)
+        launch_march<real, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+      else
+        launch_march<real, 1, 0>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+    }
     mark(MHD_K_SWEEP_Y, false);
-    L.ntiles = sc.total[kZS];
-    mark(MHD_K_SWEEP_Z, true);
-    if (sc.rs)
-      launch_march<real, 2, 1>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
-    else
-      launch_march<real, 2, 0>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
-    mark(MHD_K_SWEEP_Z, false);
+    if (!sc.fz) {
+      L.ntiles = sc.total[kZS];
+      mark(MHD_K_SWEEP_Z, true);
+      if (sc.rs)
+        launch_march<real, 2, 1>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+      else
+        launch_march<real, 2, 0>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+      mark(MHD_K_SWEEP_Z, false);
+    }
     L.ntiles = sc.total[kCTE];
     mark(MHD_K_CT_EDGE, true);
     hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);

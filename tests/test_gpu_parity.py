@@ -286,6 +286,26 @@ def test_ensemble_of_uneven_boxes():
             assert_fp64_parity(g, o, f"ensemble box {i}")
 
 
+@pytest.mark.parametrize("rk,solver", [(2, "hlld"), (3, "hll")])
+def test_ensemble_of_2d_boxes(rk, solver):
+    """Every box with one cell along z and more along y: the y march
+    completes each stage (RK combine and the z-face data, one or two z faces
+    per cell) and no z march runs; bit for bit with the oracle, including a
+    box with one cell along x and outflow z faces."""
+    boxes, states = [], []
+    for n, seed, bc in [((40, 24, 1), 11, (0, 0, 0)), ((17, 33, 1), 12, (1, 1, 1)),
+                        ((1, 30, 1), 13, (0, 1, 1))]:
+        w = W.random_smooth(n=n, seed=seed, bc=bc)
+        boxes += w.boxes
+        states += w.states
+    wl = W.Workload("mix2d", boxes, states, 3)
+    for flags in (0, mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT):
+        res = gpu_run(wl, 3, flags=flags, rk=rk, solver=solver)
+        for i, g in enumerate(res):
+            o = oracle_run(boxes[i], states[i], 3, rk=rk, solver=solver)
+            assert_fp64_parity(g, o, f"2d ensemble box {i}")
+
+
 def test_dt_query_and_t_stop():
     wl = W.random_smooth(n=(20, 16, 12), seed=8)
     spec, st = wl.boxes[0], wl.states[0]
