@@ -68,6 +68,7 @@ struct orc_box {
   int active[3];
   int rk;               /* Runge-Kutta stages: 2 (SSP-RK2) or 3 (SSP-RK3) */
   int solver;           /* Riemann solver: ORC_HLLD (HLL fallback) or ORC_HLL */
+  int rec;              /* reconstruction: ORC_REC_PRIM or ORC_REC_CHAR */
   double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
@@ -145,6 +146,155 @@ void orc_plm_face(double qm2, double qm1, double q0, double qp1, double *ql,
   double d0 = orc_minmod(q0 - qm1, qp1 - q0);
   *ql = qm1 + 0.5 * dm1;
   *qr = q0 - 0.5 * d0;
+}
+
+/* Eigen-decomposition of the primitive-variable ideal-MHD system along one
+ * axis, w = (rho, v_n, v_t1, v_t2, p, B_t1, B_t2), B_n = bn: the seven
+ * waves in the order u-c_f, u-c_a, u-c_s, u, u+c_s, u+c_a, u+c_f; R[v][k]
+ * = component v of right eigenvector k, L[k][v] = component v of left
+ * eigenvector k, L = R^-1.  Normalisation of Roe & Balsara (1996):
+ * alpha_f^2 = (a^2 - c_s^2)/(c_f^2 - c_s^2), alpha_s^2 = (c_f^2 - a^2)/
+ * (c_f^2 - c_s^2) (alpha_f = 1, alpha_s = 0 where c_f = c_s), beta = B_t/|B_t|
+ * (both 1/sqrt 2 where B_t = 0), S = sign(B_n) (+1 for B_n = 0).
+ * c_f^2 - c_s^2 is the square root of the discriminant, written as
+ * (a^2 - b_n^2)^2 + b_t^2 (2 (a^2 + b_n^2) + b_t^2) so that it is a sum of
+ * non-negative terms; c_s^2 = a^2 b_n^2 / c_f^2 (the product of the roots).
+ * Vectors derived from the linearised equations (the components of each
+ * wave follow from the continuity, normal momentum, pressure and induction
+ * equations; the left rows follow from the identities c_f^2 + c_s^2 =
+ * a^2 + b^2 and c_f^2 c_s^2 = a^2 b_n^2). */
+void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
+                    double R[7][7], double L[7][7]) {
+  double rho = w[0], u = w[1], p = w[4], by = w[5], bz = w[6];
+  double ir = 1.0 / rho;
+  double sr = sqrt(rho);
+  double a2 = gamma * p * ir;
+  double a = sqrt(a2);
+  double bn2 = bn * bn * ir;
+  double bt2 = (by * by + bz * bz) * ir;
+  double dd = a2 - bn2;
+  double disc = dd * dd + bt2 * (2.0 * (a2 + bn2) + bt2);
+  double sq = sqrt(disc);
+  double cf2 = 0.5 * (a2 + bn2 + bt2 + sq);
+  double cs2 = a2 * bn2 / cf2;
+  double cf = sqrt(cf2), cs = sqrt(cs2), ca = sqrt(bn2);
+  /* a^2 - c_s^2 = (sq + dd - b_t^2)/2 and c_f^2 - a^2 = (sq - dd + b_t^2)/2
+   * with sq = c_f^2 - c_s^2, dd = a^2 - b_n^2.  Of sq + dd and sq - dd the
+   * one that cancels is formed from their product, (sq + dd)(sq - dd) =
+   * b_t^2 (2 (a^2 + b_n^2) + b_t^2), so alpha_s keeps its accuracy for a
+   * small transverse field (alpha_s ~ |B_t| when a > c_A). */
+  double af, as;
+  if (sq > 0.0) {
+    double g = bt2 * (2.0 * (a2 + bn2) + bt2);
+    double sp, sm;
+    if (dd > 0.0) {
+      sp = sq + dd;
+      sm = g / sp;
+    } else {
+      sm = sq - dd;
+      sp = g / sm;
+    }
+    double af2 = 0.5 * (sp - bt2) / sq;
+    double as2 = 0.5 * (sm + bt2) / sq;
+    af2 = af2 < 0.0 ? 0.0 : (af2 > 1.0 ? 1.0 : af2);
+    as2 = as2 < 0.0 ? 0.0 : (as2 > 1.0 ? 1.0 : as2);
+    af = sqrt(af2);
+    as = sqrt(as2);
+  } else {
+    af = 1.0;
+    as = 0.0;
+  }
+  double bt = sqrt(by * by + bz * bz);
+  double bey, bez;
+  if (bt > 0.0) {
+    bey = by / bt;
+    bez = bz / bt;
+  } else {
+    bey = 1.0 / sqrt(2.0);
+    bez = bey;
+  }
+  double sg = bn < 0.0 ? -1.0 : 1.0;
+  double qf = sg * af * cf, qs = sg * as * cs;  /* S alpha c */
+  double Af = af * a * sr, As = as * a * sr;    /* alpha a sqrt(rho) */
+  double N = 0.5 / a2;
+  int v, k;
+  for (v = 0; v < 7; v++)
+    for (k = 0; k < 7; k++) R[v][k] = L[k][v] = 0.0;
+  lam[0] = u - cf;
+  lam[1] = u - ca;
+  lam[2] = u - cs;
+  lam[3] = u;
+  lam[4] = u + cs;
+  lam[5] = u + ca;
+  lam[6] = u + cf;
+  /* fast, u -/+ c_f */
+  R[0][0] = rho * af;  R[1][0] = -af * cf;  R[2][0] = qs * bey;  R[3][0] = qs * bez;
+  R[4][0] = rho * af * a2;  R[5][0] = As * bey;  R[6][0] = As * bez;
+  R[0][6] = rho * af;  R[1][6] = af * cf;  R[2][6] = -qs * bey;  R[3][6] = -qs * bez;
+  R[4][6] = rho * af * a2;  R[5][6] = As * bey;  R[6][6] = As * bez;
+  /* Alfven, u -/+ c_a */
+  R[2][1] = -bez;  R[3][1] = bey;  R[5][1] = -sg * sr * bez;  R[6][1] = sg * sr * bey;
+  R[2][5] = -bez;  R[3][5] = bey;  R[5][5] = sg * sr * bez;  R[6][5] = -sg * sr * bey;
+  /* slow, u -/+ c_s */
+  R[0][2] = rho * as;  R[1][2] = -as * cs;  R[2][2] = -qf * bey;  R[3][2] = -qf * bez;
+  R[4][2] = rho * as * a2;  R[5][2] = -Af * bey;  R[6][2] = -Af * bez;
+  R[0][4] = rho * as;  R[1][4] = as * cs;  R[2][4] = qf * bey;  R[3][4] = qf * bez;
+  R[4][4] = rho * as * a2;  R[5][4] = -Af * bey;  R[6][4] = -Af * bez;
+  /* entropy, u */
+  R[0][3] = 1.0;
+  /* left rows */
+  L[0][1] = -N * af * cf;  L[0][2] = N * qs * bey;  L[0][3] = N * qs * bez;
+  L[0][4] = N * af * ir;  L[0][5] = N * As * bey * ir;  L[0][6] = N * As * bez * ir;
+  L[6][1] = N * af * cf;  L[6][2] = -N * qs * bey;  L[6][3] = -N * qs * bez;
+  L[6][4] = N * af * ir;  L[6][5] = N * As * bey * ir;  L[6][6] = N * As * bez * ir;
+  L[1][2] = -0.5 * bez;  L[1][3] = 0.5 * bey;
+  L[1][5] = -0.5 * sg * bez / sr;  L[1][6] = 0.5 * sg * bey / sr;
+  L[5][2] = -0.5 * bez;  L[5][3] = 0.5 * bey;
+  L[5][5] = 0.5 * sg * bez / sr;  L[5][6] = -0.5 * sg * bey / sr;
+  L[2][1] = -N * as * cs;  L[2][2] = -N * qf * bey;  L[2][3] = -N * qf * bez;
+  L[2][4] = N * as * ir;  L[2][5] = -N * Af * bey * ir;  L[2][6] = -N * Af * bez * ir;
+  L[4][1] = N * as * cs;  L[4][2] = N * qf * bey;  L[4][3] = N * qf * bez;
+  L[4][4] = N * as * ir;  L[4][5] = -N * Af * bey * ir;  L[4][6] = -N * Af * bez * ir;
+  L[3][0] = 1.0;  L[3][4] = -1.0 / a2;
+}
+
+/* Limited slope of cell 0 from its neighbours qm, qp (seven face-frame
+ * primitives each).  rec = ORC_REC_PRIM: minmod of the two one-sided
+ * differences per variable.  ORC_REC_CHAR: the differences are projected on
+ * the left eigenvectors of the cell's own state (B_n = bn, its
+ * cell-centred normal field), limited by minmod per characteristic field and
+ * projected back with the right eigenvectors; where that slope would make
+ * the density or pressure at either face of the cell non-positive, the cell
+ * takes the primitive slope instead. */
+void orc_slope(const double qm[7], const double q0[7], const double qp[7], double bn,
+               double gamma, int rec, double d[7]) {
+  double dm[7], dp[7];
+  int v, k;
+  for (v = 0; v < 7; v++) {
+    dm[v] = q0[v] - qm[v];
+    dp[v] = qp[v] - q0[v];
+  }
+  if (rec == ORC_REC_CHAR) {
+    double lam[7], R[7][7], L[7][7], ch[7];
+    orc_prim_eigen(q0, bn, gamma, lam, R, L);
+    for (k = 0; k < 7; k++) {
+      double cm = 0.0, cp = 0.0;
+      for (v = 0; v < 7; v++) {
+        cm = cm + L[k][v] * dm[v];
+        cp = cp + L[k][v] * dp[v];
+      }
+      ch[k] = orc_minmod(cm, cp);
+    }
+    for (v = 0; v < 7; v++) {
+      double s = 0.0;
+      for (k = 0; k < 7; k++) s = s + R[v][k] * ch[k];
+      d[v] = s;
+    }
+    if (q0[0] + 0.5 * d[0] > 0.0 && q0[0] - 0.5 * d[0] > 0.0 &&
+        q0[4] + 0.5 * d[4] > 0.0 && q0[4] - 0.5 * d[4] > 0.0)
+      return;
+  }
+  for (v = 0; v < 7; v++) d[v] = orc_minmod(dm[v], dp[v]);
 }
 
 /* fast magnetosonic speed along the normal of (bn, bt1, bt2) */
@@ -499,6 +649,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->active[d] = n[d] > 1;
     b->rk = 2;
     b->solver = ORC_HLLD;
+    b->rec = ORC_REC_PRIM;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
     b->idx[d] = 1.0 / b->dx[d];
   }
@@ -742,9 +893,23 @@ static void sweep(orc_box *b, int d) {
           cs[s] = IXp(b, p2);
         }
         double wl[7], wr[7];
-        for (int v = 0; v < 7; v++) {
-          double *q = b->W[slot[v]];
-          orc_plm_face(q[cs[0]], q[cs[1]], q[cs[2]], q[cs[3]], &wl[v], &wr[v]);
+        if (b->rec == ORC_REC_PRIM) {
+          for (int v = 0; v < 7; v++) {
+            double *q = b->W[slot[v]];
+            orc_plm_face(q[cs[0]], q[cs[1]], q[cs[2]], q[cs[3]], &wl[v], &wr[v]);
+          }
+        } else {
+          /* slopes of the two cells next to the face, each limited in the
+           * characteristic fields of its own state */
+          double qs[4][7], s1[7], s2[7];
+          for (int m = 0; m < 4; m++)
+            for (int v = 0; v < 7; v++) qs[m][v] = b->W[slot[v]][cs[m]];
+          orc_slope(qs[0], qs[1], qs[2], b->W[5 + d][cs[1]], b->gamma, b->rec, s1);
+          orc_slope(qs[1], qs[2], qs[3], b->W[5 + d][cs[2]], b->gamma, b->rec, s2);
+          for (int v = 0; v < 7; v++) {
+            wl[v] = qs[1][v] + 0.5 * s1[v];
+            wr[v] = qs[2][v] - 0.5 * s2[v];
+          }
         }
         double bn = b->B[d][fidx];
         double f[7], fm;
@@ -944,6 +1109,12 @@ void orc_step_fixed_dt(orc_box *b, double dt) {
 int orc_set_rk(orc_box *b, int stages) {
   if (stages != 2 && stages != 3) return -1;
   b->rk = stages;
+  return 0;
+}
+
+int orc_set_recon(orc_box *b, int rec) {
+  if (rec != ORC_REC_PRIM && rec != ORC_REC_CHAR) return -1;
+  b->rec = rec;
   return 0;
 }
 

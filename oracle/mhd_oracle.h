@@ -55,6 +55,17 @@ int orc_set_rk(orc_box *b, int stages);
 #define ORC_HLLD 0
 #define ORC_HLL 1
 int orc_set_solver(orc_box *b, int solver);
+/* Variables the PLM slopes are limited in: ORC_REC_PRIM (the default,
+ * primitive variables) or ORC_REC_CHAR (characteristic fields of each
+ * cell's state, see orc_slope); -1 otherwise. */
+#define ORC_REC_PRIM 0
+#define ORC_REC_CHAR 1
+int orc_set_recon(orc_box *b, int rec);
+/* Point functions of the characteristic reconstruction (pinned by tests). */
+void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
+                    double R[7][7], double L[7][7]);
+void orc_slope(const double qm[7], const double q0[7], const double qp[7], double bn,
+               double gamma, int rec, double d[7]);
 /* One step with a caller-given dt (used for sampled parity on sub-boxes). */
 void orc_step_fixed_dt(orc_box *b, double dt);
 /* CFL time step of the current state (no t_stop clamp). */

@@ -20,6 +20,8 @@ _dp = C.POINTER(C.c_double)
 
 # Riemann solvers of the scheme (values of ORC_HLLD / ORC_HLL)
 SOLVERS = {"hlld": 0, "hll": 1}
+# reconstructions (values of ORC_REC_PRIM / ORC_REC_CHAR)
+RECONS = {"prim": 0, "char": 1}
 
 
 def _lib():
@@ -46,6 +48,10 @@ def _lib():
         lib.orc_set_rk.restype = C.c_int
         lib.orc_set_solver.argtypes = [C.c_void_p, C.c_int]
         lib.orc_set_solver.restype = C.c_int
+        lib.orc_set_recon.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_recon.restype = C.c_int
+        lib.orc_prim_eigen.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, _dp]
+        lib.orc_slope.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int, _dp]
         lib.orc_dt.argtypes = [C.c_void_p]
         lib.orc_dt.restype = C.c_double
         lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
@@ -85,7 +91,8 @@ def _vec(x, n):
 class OracleBox:
     """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
 
-    def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2, solver: str = "hlld"):
+    def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2, solver: str = "hlld",
+                 recon: str = "prim"):
         lib = _lib()
         self.spec = spec
         self.n = tuple(int(v) for v in spec.n)
@@ -102,6 +109,9 @@ class OracleBox:
         if solver not in SOLVERS or lib.orc_set_solver(self._h, SOLVERS[solver]) != 0:
             self.close()
             raise ValueError("oracle: solver must be 'hlld' or 'hll'")
+        if recon not in RECONS or lib.orc_set_recon(self._h, RECONS[recon]) != 0:
+            self.close()
+            raise ValueError("oracle: recon must be 'prim' or 'char'")
 
     def close(self):
         if self._h:
@@ -196,6 +206,25 @@ def plm_face(qm2, qm1, q0, qp1):
     return ql.value, qr.value
 
 
+def prim_eigen(w, bn, gamma):
+    """Wave speeds (u-c_f, u-c_a, u-c_s, u, u+c_s, u+c_a, u+c_f), right
+    eigenvectors R (columns) and left eigenvectors L (rows) of the
+    primitive-variable system along one axis."""
+    w = _vec(w, 7)
+    lam = np.empty(7)
+    R = np.empty((7, 7))
+    L = np.empty((7, 7))
+    _lib().orc_prim_eigen(_ptr(w), bn, gamma, _ptr(lam), _ptr(R), _ptr(L))
+    return lam, R, L
+
+
+def slope(qm, q0, qp, bn, gamma, recon="prim"):
+    qm, q0, qp = _vec(qm, 7), _vec(q0, 7), _vec(qp, 7)
+    d = np.empty(7)
+    _lib().orc_slope(_ptr(qm), _ptr(q0), _ptr(qp), bn, gamma, RECONS[recon], _ptr(d))
+    return d
+
+
 def phys_flux(w, bn, gamma):
     w = _vec(w, 7)
     f = np.empty(7)
@@ -233,5 +262,5 @@ def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0):
 
 __all__ = [
     "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
-    "hll", "ct_mass_flux", "ct_corner",
+    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "SOLVERS", "RECONS",
 ]

@@ -53,6 +53,14 @@ MUTATIONS = [
      "test_oracle_scheme.py::test_uniform_dt_closed_form"),
     ("periodic_ghost_off_by_one", "while (i < 0) i += n;", "while (i < 0) i += n - 1;",
      "test_oracle_scheme.py::test_conservation_divb_mean_field"),
+    ("char_switch_ignored", "  if (rec == ORC_REC_CHAR) {", "  if (0) {",
+     "test_oracle_point.py::test_char_slope_limits_each_wave_separately"),
+    ("char_left_fast_sign", "L[0][1] = -N * af * cf;", "L[0][1] = N * af * cf;",
+     "test_oracle_point.py::test_prim_eigenvectors_solve_the_jacobian"),
+    ("char_alfven_field_sign", "R[5][1] = -sg * sr * bez;", "R[5][1] = sg * sr * bez;",
+     "test_oracle_point.py::test_prim_eigenvectors_solve_the_jacobian"),
+    ("char_alpha_slow", "double as2 = 0.5 * (sm + bt2) / sq;", "double as2 = 0.5 * (sm - bt2) / sq;",
+     "test_oracle_point.py::test_prim_eigenvectors_solve_the_jacobian"),
     ("hll_switch_ignored", "if (b->solver == ORC_HLL) {", "if (0) {",
      "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
     ("hll_upwind_term_sign", "f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;",

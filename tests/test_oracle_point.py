@@ -336,3 +336,116 @@ def test_ct_upwind_selection():
     # zero flux: averages -> half weight
     e = O.ct_corner(*faces, ec, 0.0, 0.0, 0.0, 0.0)
     assert e == pytest.approx(-0.25)
+
+
+# ---------------------------------------------------------------- characteristic reconstruction
+
+def prim_jacobian(w, bn, gamma):
+    """Coefficient matrix A of the primitive-variable ideal-MHD equations
+    along x, dW/dt + A dW/dx = 0, W = (rho, u, v, w, p, B_y, B_z), B_x = bn,
+    written out from continuity, momentum, pressure and induction."""
+    rho, u, v, ww, p, by, bz = w
+    A = np.zeros((7, 7))
+    A[0, 0], A[0, 1] = u, rho
+    A[1, 1], A[1, 4], A[1, 5], A[1, 6] = u, 1 / rho, by / rho, bz / rho
+    A[2, 2], A[2, 5] = u, -bn / rho
+    A[3, 3], A[3, 6] = u, -bn / rho
+    A[4, 1], A[4, 4] = gamma * p, u
+    A[5, 1], A[5, 2], A[5, 5] = by, -bn, u
+    A[6, 1], A[6, 3], A[6, 6] = bz, -bn, u
+    return A
+
+
+def eigen_states():
+    rng = np.random.default_rng(17)
+    out = [(rand_state(rng)[[0, 1, 2, 3, 4, 5, 6]], rng.uniform(-2, 2)) for _ in range(300)]
+    rho, p = 1.2, 0.7
+    a = math.sqrt(G * p / rho)
+    out += [
+        (np.array([rho, 0.1, 0.2, -0.3, p, 0.0, 0.0]), 0.9),        # B along the normal
+        (np.array([rho, 0.1, 0.2, -0.3, p, 0.5, -0.4]), 0.0),       # B_n = 0
+        (np.array([rho, 0.1, 0.2, -0.3, p, 0.0, 0.0]), 0.0),        # no field
+        (np.array([rho, 0.1, 0.2, -0.3, p, 0.0, 0.0]), a * math.sqrt(rho)),   # c_A = a, B_t = 0
+        (np.array([rho, 0.1, 0.2, -0.3, p, 1e-9, 2e-9]), 0.8),      # B_t nearly 0
+        (np.array([rho, 0.1, 0.2, -0.3, p, 0.3, 0.4]), -1.1),       # B_n < 0
+    ]
+    return out
+
+
+def test_prim_eigenvectors_solve_the_jacobian():
+    """A R_k = lambda_k R_k for every wave, L R = I, and the wave speeds equal
+    the eigenvalues of A (numpy) and the fast speed of the flux code."""
+    for w, bn in eigen_states():
+        lam, R, L = O.prim_eigen(w, bn, G)
+        A = prim_jacobian(w, bn, G)
+        scale = np.max(np.abs(A)) * max(1.0, np.max(np.abs(R)))
+        assert np.max(np.abs(A @ R - R * lam)) <= 1e-12 * scale, (w, bn)
+        assert np.max(np.abs(L @ R - np.eye(7))) <= 1e-12, (w, bn)
+        ev = np.sort(np.linalg.eigvals(A).real)
+        assert np.allclose(np.sort(lam), ev, rtol=0, atol=1e-7 * (1 + np.max(np.abs(ev)))), (w, bn)
+        cf = O.fast_speed(w[0], w[4], bn, w[5], w[6], G)
+        assert lam[6] - w[1] == pytest.approx(cf, rel=1e-13)
+        assert np.all(np.diff(lam) >= -1e-12 * (1 + abs(w[1])))
+
+
+def test_char_slope_exact_on_linear_data():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        q0 = rand_state(rng)
+        dq = 0.01 * rng.uniform(-1, 1, 7)
+        bn = rng.uniform(-1, 1)
+        for rec in ("prim", "char"):
+            d = O.slope(q0 - dq, q0, q0 + dq, bn, G, rec)
+            assert np.allclose(d, dq, rtol=0, atol=1e-13), rec
+
+
+def test_char_slope_limits_each_wave_separately():
+    """Differences made of right eigenvectors: each characteristic field is
+    limited on its own (minmod of its two amplitudes), so a field whose
+    amplitude changes sign drops out while the others keep the smaller
+    amplitude; the primitive slope mixes them instead."""
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        q0 = rand_state(rng)
+        bn = rng.uniform(-1, 1)
+        lam, R, L = O.prim_eigen(q0, bn, G)
+        k, j = rng.choice(7, size=2, replace=False)
+        am, ap = rng.uniform(0.1, 1.0, 2) * 1e-3
+        gm, gp = rng.uniform(0.1, 1.0, 2) * 1e-3
+        dm = am * R[:, k] + gm * R[:, j]
+        dp = -ap * R[:, k] + gp * R[:, j]
+        d = O.slope(q0 - dm, q0, q0 + dp, bn, G, "char")
+        want = min(gm, gp) * R[:, j]
+        assert np.allclose(d, want, rtol=0, atol=1e-12 * (1 + np.max(np.abs(R)))), (k, j)
+
+
+def test_char_slope_mirror_antisymmetric():
+    """Reversing the stencil negates the slope exactly (both reconstructions)."""
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        qm, q0, qp = rand_state(rng), rand_state(rng), rand_state(rng)
+        bn = rng.uniform(-1, 1)
+        for rec in ("prim", "char"):
+            a = O.slope(qm, q0, qp, bn, G, rec)
+            b = O.slope(qp, q0, qm, bn, G, rec)
+            assert np.array_equal(a, -b) or np.array_equal(a + b, np.zeros(7)), rec
+
+
+def test_char_slope_falls_back_where_faces_lose_positivity():
+    """A slope that would make a face density non-positive is replaced by the
+    primitive minmod slope."""
+    q0 = np.array([0.1, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0])
+    bn = 0.0
+    lam, R, L = O.prim_eigen(q0, bn, G)
+    # a strong fast wave on both sides: rho changes by 0.3 per cell
+    amp = 0.3 / R[0, 6]
+    dm = amp * R[:, 6]
+    dm[0] = 0.05         # primitive density difference small on one side
+    dp = amp * R[:, 6]
+    d = O.slope(q0 - dm, q0, q0 + dp, bn, G, "char")
+    prim = O.slope(q0 - dm, q0, q0 + dp, bn, G, "prim")
+    lam_, R_, L_ = O.prim_eigen(q0, bn, G)
+    ch = [O.minmod(float(L_[k] @ dm), float(L_[k] @ dp)) for k in range(7)]
+    raw = R_ @ np.array(ch)
+    assert not (q0[0] - 0.5 * abs(raw[0]) > 0)   # the characteristic slope is rejected
+    assert np.array_equal(d, prim)

@@ -14,8 +14,8 @@ import oracle as O
 from paper_2606_12753_amd import workloads as W
 
 
-def make(wl, i=0, pfloor=1e-10, rk=2, solver="hlld"):
-    b = O.OracleBox(wl.boxes[i], pfloor=pfloor, rk=rk, solver=solver)
+def make(wl, i=0, pfloor=1e-10, rk=2, solver="hlld", recon="prim"):
+    b = O.OracleBox(wl.boxes[i], pfloor=pfloor, rk=rk, solver=solver, recon=recon)
     st = wl.states[i]
     b.set_state(st.cons, st.bface, st.t)
     return b
@@ -28,12 +28,12 @@ def rel_l1(a, b):
 
 # ---------------------------------------------------------------- invariants
 
-@pytest.mark.parametrize("solver", ["hlld", "hll"])
+@pytest.mark.parametrize("solver,recon", [("hlld", "prim"), ("hll", "prim"), ("hlld", "char")])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0), (1, 1, 1)])
 @pytest.mark.parametrize("n", [(6, 5, 4), (8, 6, 1)])
-def test_uniform_state_bitwise(bc, n, solver):
+def test_uniform_state_bitwise(bc, n, solver, recon):
     wl = W.uniform(n=n, bc=bc)
-    b = make(wl, solver=solver)
+    b = make(wl, solver=solver, recon=recon)
     b.step(4)
     cons, bf, t = b.get_state()
     for c, c0 in zip(cons, wl.states[0].cons):
@@ -107,11 +107,12 @@ def test_uniform_dt_closed_form():
     assert b.dt() == pytest.approx(0.3 / max(rates), rel=4e-16 * 8)
 
 
-@pytest.mark.parametrize("seed,rk,solver", [(1, 2, "hlld"), (2, 2, "hlld"), (3, 3, "hlld"),
-                                           (4, 2, "hll"), (5, 3, "hll")])
-def test_conservation_divb_mean_field(seed, rk, solver):
+@pytest.mark.parametrize("seed,rk,solver,recon", [
+    (1, 2, "hlld", "prim"), (2, 2, "hlld", "prim"), (3, 3, "hlld", "prim"),
+    (4, 2, "hll", "prim"), (5, 3, "hll", "prim"), (6, 2, "hlld", "char"), (7, 3, "hll", "char")])
+def test_conservation_divb_mean_field(seed, rk, solver, recon):
     wl = W.random_smooth(n=(12, 10, 8), seed=seed)
-    b = make(wl, rk=rk, solver=solver)
+    b = make(wl, rk=rk, solver=solver, recon=recon)
     st0 = wl.states[0]
     d0 = b.divb_max()
     b.step(6)
@@ -180,14 +181,15 @@ def _permute_state(spec, st):
     return spec2, cons2, bface2
 
 
-def test_axis_permutation_symmetry():
+@pytest.mark.parametrize("recon", ["prim", "char"])
+def test_axis_permutation_symmetry(recon):
     wl = W.random_smooth(n=(10, 8, 6), seed=9)
     spec, st = wl.boxes[0], wl.states[0]
-    a = make(wl)
+    a = make(wl, recon=recon)
     a.step(4)
     ca, ba, _ = a.get_state()
     spec2, cons2, bface2 = _permute_state(spec, st)
-    b = O.OracleBox(spec2)
+    b = O.OracleBox(spec2, recon=recon)
     b.set_state(cons2, bface2)
     b.step(4)
     cb, bb, _ = b.get_state()
@@ -251,8 +253,8 @@ def _run_to(b, t_end, max_steps=5000):
     raise AssertionError("time step collapsed before t_end")
 
 
-def _cp_error(wl):
-    b = make(wl)
+def _cp_error(wl, recon="prim"):
+    b = make(wl, recon=recon)
     _run_to(b, wl.meta["t_end"])
     cons, bf, _ = b.get_state()
     st = wl.states[0]
@@ -278,8 +280,9 @@ def test_cp_alfven_second_order_1d():
     assert orders[2] >= 1.8, orders
 
 
-def test_cp_alfven_linear_amplitude():
-    errs = [_cp_error(W.cp_alfven(n, axis=1, amp=1e-6)) for n in (32, 64, 128)]
+@pytest.mark.parametrize("recon", ["prim", "char"])
+def test_cp_alfven_linear_amplitude(recon):
+    errs = [_cp_error(W.cp_alfven(n, axis=1, amp=1e-6), recon) for n in (32, 64, 128)]
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert orders[1] > 1.7, orders
 
@@ -453,3 +456,29 @@ def test_riemann_2d_diagonal_mirror():
         assert np.max(np.abs(T(cons[qa]) - cons[qb][0])) <= 1e-12 * max(scale[qa], 1e-300), (qa, qb)
     assert np.max(np.abs(bf[0][0].T - bf[1][0])) <= 1e-12
     assert b.counters() == {"floor": 0, "hll": 0, "bad": 0}
+
+
+def test_sod_char_reconstruction_converges():
+    """Characteristic limiting on the Sod tube (B = 0, where the fields are
+    the acoustic waves and the entropy wave): the density converges to the
+    exact solution with an error close to that of primitive limiting."""
+    gamma = 1.4
+    errs = {"prim": [], "char": []}
+    for n in (100, 200, 400):
+        spec = W.BoxSpec((n, 1, 1), bc=(W.OUTFLOW, 0, 0), gamma=gamma, cfl=0.4)
+        x = W.centres(spec, 0)
+        left = (x < 0.5).reshape(1, 1, n)
+        rho = np.where(left, 1.0, 0.125)
+        p = np.where(left, 1.0, 0.1)
+        bface = [np.zeros(s) for s in W.face_shapes(spec)]
+        st = W.conserved(spec, rho, 0.0, 0.0, 0.0, p, bface)
+        exact = _sod_exact(x, 0.2, gamma, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+        for recon in errs:
+            b = O.OracleBox(spec, recon=recon)
+            b.set_state(st.cons, st.bface)
+            _run_to(b, 0.2)
+            cons, _, _ = b.get_state()
+            errs[recon].append(float(np.mean(np.abs(cons[0].ravel() - exact))))
+    e = errs["char"]
+    assert e[2] < e[1] < e[0] and math.log2(e[0] / e[2]) / 2 > 0.6, errs
+    assert all(0.7 < c / p < 1.3 for c, p in zip(errs["char"], errs["prim"])), errs
