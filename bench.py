@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--accuracy", action="store_true")
+    ap.add_argument("--options", action="store_true",
+                    help="the scheme options (RK3, HLL, characteristic slopes) on the benchmark input")
     ap.add_argument("--paper-workload", action="store_true",
                     help="the paper's 3D Orszag-Tang and 2D Riemann cases instead")
     ap.add_argument("--paper-case", choices=["orszag_tang_3d", "riemann_2d"], default=None,
@@ -169,7 +171,7 @@ def kind_of(name):
     return None
 
 
-def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld"):
+def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld", recon="prim"):
     """Per repeat: set the initial state, `warmup` untimed steps (the first
     repeat's include the autotuner's trials), then `steps` timed steps.
     Returns the median time, every repeat's time, the final state of box 0
@@ -178,7 +180,7 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld")
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
     sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk,
-                  solver=solver)
+                  solver=solver, recon=recon)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     times = []
@@ -546,15 +548,15 @@ PAPER_RIEMANN2D_INVOCATION_MS = {"Reconstruct, A100 OpenACC": 1.24,
                                  "HLL, A100 OpenACC": 1.63, "HLL, A100 OpenMP": 9.84}
 
 
-def kernel_times_of(wl, precision, steps, variant, rk, solver):
-    """kernel_times for a given integrator and Riemann solver."""
+def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim"):
+    """kernel_times for a given integrator, Riemann solver and reconstruction."""
     import torch
     from paper_2606_12753_amd import mhd
     os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
     try:
         stream = torch.cuda.Stream()
         sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
-                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver)
+                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver, recon=recon)
         for b, st in enumerate(wl.states):
             sim.set_state(b, st.cons, st.bface, 0.0)
         sim.step(1)
@@ -602,6 +604,43 @@ def paper_workload(a, flags):
         out.update(compare(wl.boxes[0], res["fp64"]["state"], res["mixed"]["state"]))
         print(json.dumps(out), flush=True)
         del wl, res
+
+
+def options_bench(a, flags):
+    """Cost of the scheme options on the benchmark input (blast, n^3): the
+    default (primitive slopes, HLLD, SSP-RK2) against SSP-RK3, HLL at every
+    face and characteristic slopes, FP64 and mixed; median of three repeats
+    of a.steps steps, per-launch kernel times, and the x sweep's algorithmic
+    HBM rate (its bytes do not depend on the options)."""
+    from paper_2606_12753_amd import mhd, workloads
+    print(f"# options: building blast {a.n}^3 input", file=sys.stderr, flush=True)
+    wl = workloads.blast_3d(n=a.n)
+    cells = wl.cells
+    opts = [("default", dict(rk=2, solver="hlld", recon="prim")),
+            ("rk3", dict(rk=3, solver="hlld", recon="prim")),
+            ("hll", dict(rk=2, solver="hll", recon="prim")),
+            ("char", dict(rk=2, solver="hlld", recon="char"))]
+    out = {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+CT, CFL 0.3", "cells": cells,
+           "steps": a.steps, "options": {}}
+    for name, kw in opts:
+        row = {}
+        for prec, key in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
+            print(f"# options: {name} {key}", file=sys.stderr, flush=True)
+            r = run_gpu(wl, prec, a.steps, a.warmup, flags, repeats=3, **kw)
+            r["sim"].close()
+            kt = kernel_times_of(wl, prec, min(a.steps, 10), r["variant"], kw["rk"], kw["solver"],
+                                 kw["recon"])
+            table = BYTES_FP64 if prec == mhd.MHD_FP64 else BYTES_MIXED
+            xbytes = 0.5 * (table["sweep_x"][0] + table["sweep_x"][1]) * cells
+            row[key] = {"Mcell_updates_per_s": round(cells * a.steps / (r["ms"] * 1e-3) / 1e6, 1),
+                        "ms_per_step": round(r["ms"] / a.steps, 4), "variant": r["variant"],
+                        "kernels_ms_per_launch": kt,
+                        "sweep_x_hbm_frac": round(xbytes / (kt["sweep_x"] * 1e-3) / 1e9
+                                                  / HBM_PEAK_GBS, 4)}
+        row["speedup_mixed"] = round(row["mixed"]["Mcell_updates_per_s"]
+                                     / row["fp64"]["Mcell_updates_per_s"], 3)
+        out["options"][name] = row
+    print(json.dumps(out), flush=True)
 
 
 def accuracy(flags):
@@ -662,6 +701,9 @@ def main():
         return
     if a.paper_workload:
         paper_workload(a, flags)
+        return
+    if a.options:
+        options_bench(a, flags)
         return
     print(f"# building blast {a.n}^3 input", file=sys.stderr, flush=True)
     wl = workloads.blast_3d(n=a.n)

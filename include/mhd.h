@@ -59,6 +59,16 @@ extern "C" {
 #define MHD_RS_HLL 1  /* HLL (Harten, Lax & van Leer 1983) with the same
                          outer wave speeds */
 
+/* variables the PLM slopes are limited in (minmod in both) */
+#define MHD_REC_PRIM 0 /* primitive variables */
+#define MHD_REC_CHAR 1 /* characteristic fields of each cell's own state
+                          (eigenvectors of the primitive-variable system,
+                          Roe & Balsara 1996 normalisation); a cell whose
+                          slope would give a non-positive face density or
+                          pressure takes the primitive slope.  The paper
+                          names both ("primitive (or characteristic)",
+                          its section 2.2.3). */
+
 /* where caller arrays live */
 #define MHD_HOST 0
 #define MHD_DEVICE 1
@@ -112,6 +122,7 @@ typedef struct {
                               third-order scheme; one more state copy in the
                               workspace) */
   int32_t riemann;         /* MHD_RS_HLLD (0) or MHD_RS_HLL */
+  int32_t recon;           /* MHD_REC_PRIM (0) or MHD_REC_CHAR */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -171,7 +182,8 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
  * cells in LDS for the RK combine instead of reading it again), [2] march
  * segment length (cells),
  * [3] persistent grid (0/1).
- * The variants differ only in scheduling: FP64 results are identical. */
+ * The variants differ only in scheduling: FP64 results are identical.  With
+ * MHD_REC_CHAR the sweeps run one variant ([0] and [1] are then ignored). */
 int mhd_tuning(mhd_ctx *ctx, int32_t variant[4]);
 
 /* Frees the context and every buffer the library allocated (a caller

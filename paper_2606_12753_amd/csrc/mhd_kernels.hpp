@@ -339,6 +339,131 @@ __device__ __forceinline__ void plm(real qm2, real qm1, real q0, real qp1, real&
   qr = q0 - (real)0.5 * d0;
 }
 
+// Limited slope of a cell in the characteristic fields of its own state
+// (face-frame primitives q0, normal field bn; neighbours qm, qp): the two
+// one-sided differences are projected on the left eigenvectors of the
+// primitive-variable MHD system, limited by minmod per field and projected
+// back with the right eigenvectors (Roe & Balsara 1996 normalisation, waves
+// u-c_f, u-c_a, u-c_s, u, u+c_s, u+c_a, u+c_f).  Where the slope would make
+// the density or pressure at a face of the cell non-positive, the primitive
+// minmod slope is used.  The eigenvector entries are formed in a fixed
+// order and the projections are dense sums in index order, so FP64 results
+// are reproducible bit for bit.
+template <typename real>
+__device__ __forceinline__ St7<real> char_slope(const St7<real>& qm, const St7<real>& q0,
+                                                const St7<real>& qp, real bn, real gamma) {
+  real dm[7], dp[7];
+#pragma unroll
+  for (int v = 0; v < 7; v++) {
+    dm[v] = q0.v[v] - qm.v[v];
+    dp[v] = qp.v[v] - q0.v[v];
+  }
+  const real rho = q0.v[0], p = q0.v[4], by = q0.v[5], bz = q0.v[6];
+  const real ir = rcp(rho);
+  const real sr = sq(rho);
+  const real a2 = gamma * p * ir;
+  const real a = sq(a2);
+  const real bn2 = bn * bn * ir;
+  const real bt2 = (by * by + bz * bz) * ir;
+  const real dd = a2 - bn2;
+  const real disc = dd * dd + bt2 * ((real)2 * (a2 + bn2) + bt2);
+  const real sqd = sq(disc);
+  const real cf2 = (real)0.5 * (a2 + bn2 + bt2 + sqd);
+  const real cs2 = quot(a2 * bn2, cf2);
+  const real cf = sq(cf2), cs = sq(cs2);
+  real af, as;
+  if (sqd > (real)0) {
+    // a^2 - c_s^2 and c_f^2 - a^2 without cancellation (the factor that
+    // cancels is formed from the product of the two)
+    const real g = bt2 * ((real)2 * (a2 + bn2) + bt2);
+    real sp, sm;
+    if (dd > (real)0) {
+      sp = sqd + dd;
+      sm = quot(g, sp);
+    } else {
+      sm = sqd - dd;
+      sp = quot(g, sm);
+    }
+    real af2 = quot((real)0.5 * (sp - bt2), sqd);
+    real as2 = quot((real)0.5 * (sm + bt2), sqd);
+    af2 = af2 < (real)0 ? (real)0 : (af2 > (real)1 ? (real)1 : af2);
+    as2 = as2 < (real)0 ? (real)0 : (as2 > (real)1 ? (real)1 : as2);
+    af = sq(af2);
+    as = sq(as2);
+  } else {
+    af = (real)1;
+    as = (real)0;
+  }
+  const real bt = sq(by * by + bz * bz);
+  real bey, bez;
+  if (bt > (real)0) {
+    bey = quot(by, bt);
+    bez = quot(bz, bt);
+  } else {
+    bey = rcp(sq((real)2));
+    bez = bey;
+  }
+  const real sg = bn < (real)0 ? (real)-1 : (real)1;
+  const real qf = sg * af * cf, qs = sg * as * cs;
+  const real Af = af * a * sr, As = as * a * sr;
+  const real N = quot((real)0.5, a2);
+  real L[7][7], R[7][7];
+#pragma unroll
+  for (int v = 0; v < 7; v++)
+#pragma unroll
+    for (int k = 0; k < 7; k++) L[v][k] = R[v][k] = (real)0;
+  L[0][1] = -N * af * cf;  L[0][2] = N * qs * bey;  L[0][3] = N * qs * bez;
+  L[0][4] = N * af * ir;  L[0][5] = N * As * bey * ir;  L[0][6] = N * As * bez * ir;
+  L[6][1] = N * af * cf;  L[6][2] = -N * qs * bey;  L[6][3] = -N * qs * bez;
+  L[6][4] = N * af * ir;  L[6][5] = N * As * bey * ir;  L[6][6] = N * As * bez * ir;
+  L[1][2] = (real)-0.5 * bez;  L[1][3] = (real)0.5 * bey;
+  L[1][5] = quot((real)-0.5 * sg * bez, sr);  L[1][6] = quot((real)0.5 * sg * bey, sr);
+  L[5][2] = (real)-0.5 * bez;  L[5][3] = (real)0.5 * bey;
+  L[5][5] = quot((real)0.5 * sg * bez, sr);  L[5][6] = quot((real)-0.5 * sg * bey, sr);
+  L[2][1] = -N * as * cs;  L[2][2] = -N * qf * bey;  L[2][3] = -N * qf * bez;
+  L[2][4] = N * as * ir;  L[2][5] = -N * Af * bey * ir;  L[2][6] = -N * Af * bez * ir;
+  L[4][1] = N * as * cs;  L[4][2] = N * qf * bey;  L[4][3] = N * qf * bez;
+  L[4][4] = N * as * ir;  L[4][5] = -N * Af * bey * ir;  L[4][6] = -N * Af * bez * ir;
+  L[3][0] = (real)1;  L[3][4] = quot((real)-1, a2);
+  real ch[7];
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    real cm = (real)0, cp = (real)0;
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      cm = cm + L[k][v] * dm[v];
+      cp = cp + L[k][v] * dp[v];
+    }
+    ch[k] = minmod(cm, cp);
+  }
+  R[0][0] = rho * af;  R[1][0] = -af * cf;  R[2][0] = qs * bey;  R[3][0] = qs * bez;
+  R[4][0] = rho * af * a2;  R[5][0] = As * bey;  R[6][0] = As * bez;
+  R[0][6] = rho * af;  R[1][6] = af * cf;  R[2][6] = -qs * bey;  R[3][6] = -qs * bez;
+  R[4][6] = rho * af * a2;  R[5][6] = As * bey;  R[6][6] = As * bez;
+  R[2][1] = -bez;  R[3][1] = bey;  R[5][1] = -sg * sr * bez;  R[6][1] = sg * sr * bey;
+  R[2][5] = -bez;  R[3][5] = bey;  R[5][5] = sg * sr * bez;  R[6][5] = -sg * sr * bey;
+  R[0][2] = rho * as;  R[1][2] = -as * cs;  R[2][2] = -qf * bey;  R[3][2] = -qf * bez;
+  R[4][2] = rho * as * a2;  R[5][2] = -Af * bey;  R[6][2] = -Af * bez;
+  R[0][4] = rho * as;  R[1][4] = as * cs;  R[2][4] = qf * bey;  R[3][4] = qf * bez;
+  R[4][4] = rho * as * a2;  R[5][4] = -Af * bey;  R[6][4] = -Af * bez;
+  R[0][3] = (real)1;
+  St7<real> d;
+#pragma unroll
+  for (int v = 0; v < 7; v++) {
+    real s = (real)0;
+#pragma unroll
+    for (int k = 0; k < 7; k++) s = s + R[v][k] * ch[k];
+    d.v[v] = s;
+  }
+  const bool ok = q0.v[0] + (real)0.5 * d.v[0] > (real)0 && q0.v[0] - (real)0.5 * d.v[0] > (real)0 &&
+                  q0.v[4] + (real)0.5 * d.v[4] > (real)0 && q0.v[4] - (real)0.5 * d.v[4] > (real)0;
+  if (!ok) {
+#pragma unroll
+    for (int v = 0; v < 7; v++) d.v[v] = minmod(dm[v], dp[v]);
+  }
+  return d;
+}
+
 // square of the fast magnetosonic speed along n
 template <typename real>
 __device__ __forceinline__ real fast_speed_sq(real rho, real p, real bn, real bt1, real bt2,
@@ -716,10 +841,10 @@ __device__ __forceinline__ void x_row(const XTile& x, int p, int& j, int& k) {
   }
 }
 
-// Staging slot s: piece p, cell index i in the row, and whether the tile
-// owns the cell (the cell's index is one of the piece's faces).
-__device__ __forceinline__ void x_slot(const XTile& x, int s, int& p, int& i, int& own) {
-  int c, w;
+// Staging slot s: piece p, cell index i in the row, offset c of the slot in
+// its piece and the piece's face count w; the tile owns the cell when its
+// index is one of the piece's faces (2 <= c < w + 2).
+__device__ __forceinline__ void x_slot(const XTile& x, int s, int& p, int& i, int& c, int& w) {
   if (s < x.W0 + 3) {
     p = 0;
     c = s;
@@ -732,7 +857,6 @@ __device__ __forceinline__ void x_slot(const XTile& x, int s, int& p, int& i, in
     w = min(x.nf, x.nF - x.W0 - (p - 1) * x.nf);
     i = c - 2;
   }
-  own = c >= 2 && c < w + 2;
 }
 
 // Face t of the tile: piece p, face f in the row, and the slot o of the
@@ -756,11 +880,13 @@ __device__ __forceinline__ void x_face(const XTile& x, int t, int& p, int& f, in
 // (stage 1, the state at the start of the step).
 // WPE: minimum resident wavefronts per SIMD the register allocation must
 // allow (1 = unconstrained); one of the tunable launch variants.  RS: the
-// Riemann solver (see riemann).
-template <typename real, int WPE, int RS>
+// Riemann solver (see riemann).  REC = 1: slopes limited in characteristic
+// fields (char_slope), computed once per staged cell into LDS rows 8-14
+// after the staging pass (row 7 holds the cell's normal field).
+template <typename real, int WPE, int RS, int REC>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_x(
     Launch L) {
-  __shared__ real sw[7][kLdsCells];
+  __shared__ real sw[REC ? 15 : 7][kLdsCells];
   const int s = L.stage;
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
     const int tile = tile_of(L, v);
@@ -775,8 +901,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       const int npieces = 1 + (x.nF - x.W0 + x.nf - 1) / x.nf;
       const int ncell = x.nF + 3 * npieces;
       for (int sidx = threadIdx.x; sidx < ncell; sidx += kTPB) {
-        int p, i, own, j, k;
-        x_slot(x, sidx, p, i, own);
+        int p, i, c, wd, j, k;
+        x_slot(x, sidx, p, i, c, wd);
+        const bool own = c >= 2 && c < wd + 2;
         x_row(x, p, j, k);
         const int im = map_cell(i, nx, b.per[0]);
         PrimD w;
@@ -788,6 +915,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         sw[4][sidx] = (real)w.p;
         sw[5][sidx] = (real)w.by;
         sw[6][sidx] = (real)w.bz;
+        if constexpr (REC) sw[7][sidx] = (real)w.bx;
         if (own && i >= 0 && i < nx) {
           const int c = cidx(b, i, j, k);
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
@@ -801,17 +929,46 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         }
       }
       __syncthreads();
+      if constexpr (REC) {
+        // slope of every cell next to a face of the tile (offsets 1..w+1
+        // of its piece), from its two neighbours in the same piece
+        for (int sidx = threadIdx.x; sidx < ncell; sidx += kTPB) {
+          int p, i, c, wd;
+          x_slot(x, sidx, p, i, c, wd);
+          if (c >= 1 && c <= wd + 1) {
+            St7<real> qm, q0, qp;
+#pragma unroll
+            for (int v = 0; v < 7; v++) {
+              qm.v[v] = sw[v][sidx - 1];
+              q0.v[v] = sw[v][sidx];
+              qp.v[v] = sw[v][sidx + 1];
+            }
+            const St7<real> d = char_slope(qm, q0, qp, sw[7][sidx], (real)b.gamma);
+#pragma unroll
+            for (int v = 0; v < 7; v++) sw[8 + v][sidx] = d.v[v];
+          }
+        }
+        __syncthreads();
+      }
       for (int t = threadIdx.x; t < x.nF; t += kTPB) {
         int p, f, o, j, k;
         x_face(x, t, p, f, o);
         x_row(x, p, j, k);
-        St7<real> q[4];
-#pragma unroll
-        for (int m = 0; m < 4; m++)
-#pragma unroll
-          for (int v = 0; v < 7; v++) q[m].v[v] = sw[v][o + m];
         St7<real> wl, wr;
-        plm_face(q[0], q[1], q[2], q[3], wl, wr);
+        if constexpr (REC) {
+#pragma unroll
+          for (int v = 0; v < 7; v++) {
+            wl.v[v] = sw[v][o + 1] + (real)0.5 * sw[8 + v][o + 1];
+            wr.v[v] = sw[v][o + 2] - (real)0.5 * sw[8 + v][o + 2];
+          }
+        } else {
+          St7<real> q[4];
+#pragma unroll
+          for (int m = 0; m < 4; m++)
+#pragma unroll
+            for (int v = 0; v < 7; v++) q[m].v[v] = sw[v][o + m];
+          plm_face(q[0], q[1], q[2], q[3], wl, wr);
+        }
         const int fi = fidx(b, 0, f, j, k);
         const real bn = (real)ld<double>(b.B[s][0], fi);
         real F[7], fm;
@@ -890,20 +1047,51 @@ __device__ __forceinline__ double rk_combine(int kind, double uold, double usw, 
 // LW = 0 keeps it in registers; LW = 1 keeps it in a per-lane LDS column
 // (three slots of seven values, no sharing between lanes, so no barrier):
 // fewer registers live across the Riemann solve.
-template <typename real, int LW>
+// REC = 1 (registers only): slopes limited in characteristic fields; the
+// window also keeps the normal field of its newer cell, whose slope the next
+// face computes.
+template <typename real, int LW, int REC>
 struct Window;
 
 template <typename real>
-struct Window<real, 0> {
+struct Window<real, 0, 1> {
   St7<real> q1, q2, dm1;
-  __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d) {
+  real bn2;
+  __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d,
+                                       real bnb) {
+    q1 = a;
+    q2 = b;
+    dm1 = d;
+    bn2 = bnb;
+  }
+  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, real bn3, real gamma,
+                                                 St7<real>& wl, St7<real>& wr) {
+    const St7<real> d0 = char_slope(q1, q2, q3, bn2, gamma);
+#pragma unroll
+    for (int v = 0; v < 7; v++) {
+      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
+      wr.v[v] = q2.v[v] - (real)0.5 * d0.v[v];
+    }
+    dm1 = d0;
+    q1 = q2;
+    q2 = q3;
+    bn2 = bn3;
+  }
+};
+
+template <typename real>
+struct Window<real, 0, 0> {
+  St7<real> q1, q2, dm1;
+  __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d,
+                                       real) {
     q1 = a;
     q2 = b;
     dm1 = d;
   }
   // PLM states of the face between the window's cells given the next cell
   // q3; then slides the window by one cell
-  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, St7<real>& wl, St7<real>& wr) {
+  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, real, real, St7<real>& wl,
+                                                 St7<real>& wr) {
 #pragma unroll
     for (int v = 0; v < 7; v++) {
       const real d0 = minmod(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
@@ -917,10 +1105,11 @@ struct Window<real, 0> {
 };
 
 template <typename real>
-struct Window<real, 1> {
+struct Window<real, 1, 0> {
   real (*lds)[kTPB];  // [21][kTPB]: slots 0-6 and 7-13 cells, 14-20 slope
   int t, a;           // lane, offset of the slot holding cell f-1
-  __device__ __forceinline__ void init(const St7<real>& q1, const St7<real>& q2, const St7<real>& d) {
+  __device__ __forceinline__ void init(const St7<real>& q1, const St7<real>& q2, const St7<real>& d,
+                                       real) {
     a = 0;
 #pragma unroll
     for (int v = 0; v < 7; v++) {
@@ -929,7 +1118,8 @@ struct Window<real, 1> {
       lds[14 + v][t] = d.v[v];
     }
   }
-  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, St7<real>& wl, St7<real>& wr) {
+  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, real, real, St7<real>& wl,
+                                                 St7<real>& wr) {
     const int bo = 7 - a;
 #pragma unroll
     for (int v = 0; v < 7; v++) {
@@ -951,7 +1141,7 @@ struct Window<real, 1> {
 // the state the RK combine reads (U^n in stage 1, U* in stage 2), three
 // faces after the sweep loaded it, when it has usually left L2; the ring
 // saves that second fetch.
-template <typename real, int D, int PF, int LW, int CU, int RS, int FZ>
+template <typename real, int D, int PF, int LW, int CU, int RS, int FZ, int REC>
 __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, int i, int tr,
                                              int j0, int j1, real (*lds)[kTPB],
                                              double (*ring)[kTPB]) {
@@ -965,7 +1155,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     const int am = map_cell(a, n, per);
     return D == 1 ? addr_of(b, i, am, tr) : addr_of(b, i, tr, am);
   };
-  Window<real, LW> win;
+  Window<real, LW, REC> win;
+  const real gam = (real)b.gamma;
+  // cell-centred normal field of a primitive state (characteristic slopes)
+  auto bnorm = [&](const PrimD& w) { return (real)(D == 1 ? w.by : w.bz); };
   if constexpr (LW) {
     win.lds = lds;
     win.t = threadIdx.x;
@@ -976,18 +1169,24 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     const St7<real> q0 = rotate<real>(w, D);
     raw_to_prim(b, load_raw(b, s, addr_at(j0 - 1)), w);
     const St7<real> q1 = rotate<real>(w, D);
+    const real bn1 = bnorm(w);
     const Raw r2 = load_raw(b, s, addr_at(j0));
     raw_to_prim(b, r2, w);
     const St7<real> q2 = rotate<real>(w, D);
+    const real bn2 = bnorm(w);
     if constexpr (kRing) {
       const int slot = j0 % 3;
 #pragma unroll
       for (int q = 0; q < kNQ; q++) ring[slot * kNQ + q][lane] = r2.u[q];
     }
     St7<real> dm1;
+    if constexpr (REC) {
+      dm1 = char_slope(q0, q1, q2, bn1, gam);
+    } else {
 #pragma unroll
-    for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
-    win.init(q1, q2, dm1);
+      for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
+    }
+    win.init(q1, q2, dm1, bn2);
   }
   Raw next = load_raw(b, s, addr_at(j0 + 1));
   real fprev[kNQ];
@@ -1043,7 +1242,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     };
     if (PF && f > j0) load_update_inputs();
     St7<real> wl, wr;
-    win.face_and_slide(q3, wl, wr);
+    win.face_and_slide(q3, bnorm(w), gam, wl, wr);
     // face index f along D is in [0, n]; periodic face n is face 0
     const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
     const real bn = (real)ld<double>(b.B[s][D], fi);
@@ -1142,8 +1341,9 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int com
 // (latency hidden, more registers live across the solve); RS: the Riemann
 // solver (see riemann); FZ (y march only, every box with one cell along z
 // and more than one along y): the y march completes the stage, RK combine
-// and z-face data included, and no z march runs.
-template <typename real, int D, int WPE, int PF, int LW, int CU, int RS, int FZ>
+// and z-face data included, and no z march runs.  REC = 1: characteristic
+// slopes (register window only).
+template <typename real, int D, int WPE, int PF, int LW, int CU, int RS, int FZ, int REC>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
@@ -1168,7 +1368,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW, CU, RS, FZ>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
+      march_column<real, D, PF, LW, CU, RS, FZ, REC>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
     } else {
       inactive_column<real, D>(b, L.stage, L.dst, L.comb, i, tr);
     }

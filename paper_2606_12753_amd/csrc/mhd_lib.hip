@@ -140,6 +140,10 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     err = "config: riemann must be MHD_RS_HLLD or MHD_RS_HLL";
     return MHD_E_INVAL;
   }
+  if (cfg->recon != MHD_REC_PRIM && cfg->recon != MHD_REC_CHAR) {
+    err = "config: recon must be MHD_REC_PRIM or MHD_REC_CHAR";
+    return MHD_E_INVAL;
+  }
   for (int b = 0; b < cfg->nboxes; b++) {
     int rc = validate_box(cfg->boxes[b], err);
     if (rc) {
@@ -253,6 +257,7 @@ struct mhd_ctx {
   int rk = 2;  // Runge-Kutta stages
   int rs = 0;  // Riemann solver (MHD_RS_*)
   int fz = 0;  // every box: one cell along z, more along y (no z march)
+  int rec = 0; // reconstruction (MHD_REC_*)
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -320,6 +325,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.rk = c->rk;
   sc.rs = c->rs;
   sc.fz = c->fz;
+  sc.rec = c->rec;
   sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
@@ -720,6 +726,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->flags = cfg->flags;
   c->rk = cfg->rk_stages == 3 ? 3 : 2;
   c->rs = cfg->riemann;
+  c->rec = cfg->recon;
   c->fz = 1;
   for (int b = 0; b < cfg->nboxes; b++)
     if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;

@@ -26,6 +26,7 @@ struct StepCtx {
   int var_x, var_m;    // launch variants of the x sweep and the marches
   int rk;              // Runge-Kutta stages: 2 or 3
   int rs;              // Riemann solver: 0 HLLD (HLL fallback), 1 HLL
+  int rec;             // slopes limited in 0 primitive, 1 characteristic variables
   int fz;              // every box has one cell along z and more along y:
                        // the y march completes each stage, no z march
   int xcd;             // XCD-grouped tile order
@@ -34,12 +35,17 @@ struct StepCtx {
   int* ev_kind;        // timing: kernel kind of each pair
 };
 
-template <typename real, int RS>
+template <typename real, int RS, int REC>
 inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
+  if constexpr (REC) {
+    // characteristic slopes: one variant (unconstrained registers)
+    hipLaunchKernelGGL((k_sweep_x<real, 1, RS, 1>), g, dim3(kTPB), 0, st, L);
+    return;
+  }
   switch (wpe) {
-    case 3: hipLaunchKernelGGL((k_sweep_x<real, 3, RS>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_x<real, 4, RS>), g, dim3(kTPB), 0, st, L); break;
-    default: hipLaunchKernelGGL((k_sweep_x<real, 1, RS>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_x<real, 3, RS, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_x<real, 4, RS, 0>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_x<real, 1, RS, 0>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
@@ -50,35 +56,40 @@ inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
 // SIMD and no prefetch; 8, 9, 10 = variants 2, 6, 7 with the z march's
 // swept state kept in an LDS ring for the RK combine (the y march has no
 // combine and runs 2, 6, 7)
-template <typename real, int D, int RS, int FZ = 0>
+template <typename real, int D, int RS, int FZ, int REC>
 inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
+  if constexpr (REC) {
+    // characteristic slopes: one variant (register window, no prefetch)
+    hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ, 1>), g, dim3(kTPB), 0, st, L);
+    return;
+  }
   if (D == 1 && var >= 8) var = var == 8 ? 2 : var == 9 ? 6 : 7;
   switch (var) {
-    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
-    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
-    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
-    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
-    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
-    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    case 2: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 3: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 0, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 4: hipLaunchKernelGGL((k_sweep_march<real, D, 4, 0, 0, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 5: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 1, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 6: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
+    case 7: hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
     case 8:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 1, RS, FZ, 0>), g, dim3(kTPB), 0, st, L);
       break;
     case 9:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 1, 1, RS, FZ, 0>), g, dim3(kTPB), 0, st, L);
       break;
     case 10:
       if constexpr (D == 2)
-        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1, RS, FZ>), g, dim3(kTPB), 0, st, L);
+        hipLaunchKernelGGL((k_sweep_march<real, D, 3, 0, 1, 1, RS, FZ, 0>), g, dim3(kTPB), 0, st, L);
       break;
-    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0, RS, FZ>), g, dim3(kTPB), 0, st, L); break;
+    default: hipLaunchKernelGGL((k_sweep_march<real, D, 1, 1, 0, 0, RS, FZ, 0>), g, dim3(kTPB), 0, st, L); break;
   }
 }
 
 // Enqueues one step on sc.stream; returns the number of timed launches.
-template <typename real>
-inline int enqueue_step_kernels(const StepCtx& sc) {
+template <typename real, int REC>
+inline int enqueue_step_rec(const StepCtx& sc) {
   Launch L = sc.L;
   L.xcd = sc.xcd;
   auto grid = [&](int kind) {
@@ -112,9 +123,9 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     L.ntiles = sc.total[kXS];
     mark(MHD_K_SWEEP_X, true);
     if (sc.rs)
-      launch_x<real, 1>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+      launch_x<real, 1, REC>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
     else
-      launch_x<real, 0>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+      launch_x<real, 0, REC>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
     mark(MHD_K_SWEEP_X, false);
     L.lam = 0;
     if (s == 0) {
@@ -126,23 +137,23 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     mark(MHD_K_SWEEP_Y, true);
     if (sc.fz) {
       if (sc.rs)
-        launch_march<real, 1, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 1, 1, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
       else
-        launch_march<real, 1, 0, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 0, 1, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
     } else {
       if (sc.rs)
-        launch_march<real, 1, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 1, 0, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
       else
-        launch_march<real, 1, 0>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 0, 0, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
     }
     mark(MHD_K_SWEEP_Y, false);
     if (!sc.fz) {
       L.ntiles = sc.total[kZS];
       mark(MHD_K_SWEEP_Z, true);
       if (sc.rs)
-        launch_march<real, 2, 1>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+        launch_march<real, 2, 1, 0, REC>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
       else
-        launch_march<real, 2, 0>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+        launch_march<real, 2, 0, 0, REC>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
       mark(MHD_K_SWEEP_Z, false);
     }
     L.ntiles = sc.total[kCTE];
@@ -155,6 +166,11 @@ inline int enqueue_step_kernels(const StepCtx& sc) {
     mark(MHD_K_CT_FACE, false);
   }
   return slot;
+}
+
+template <typename real>
+inline int enqueue_step_kernels(const StepCtx& sc) {
+  return sc.rec ? enqueue_step_rec<real, 1>(sc) : enqueue_step_rec<real, 0>(sc);
 }
 
 }  // namespace mhd

@@ -39,11 +39,12 @@ def rel_l1(a, b):
 
 
 def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2,
-            solver="hlld"):
+            solver="hlld", recon="prim"):
     idx = range(len(wl.boxes)) if boxes is None else boxes
     specs = [wl.boxes[i] for i in idx]
     out = []
-    with mhd.Sim(specs, precision=precision, flags=flags, rk=rk, solver=solver) as sim:
+    with mhd.Sim(specs, precision=precision, flags=flags, rk=rk, solver=solver,
+                 recon=recon) as sim:
         for k, i in enumerate(idx):
             st = wl.states[i]
             sim.set_state(k, st.cons, st.bface, st.t)
@@ -54,8 +55,8 @@ def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None,
     return out
 
 
-def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld"):
-    b = O.OracleBox(spec, rk=rk, solver=solver)
+def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim"):
+    b = O.OracleBox(spec, rk=rk, solver=solver, recon=recon)
     b.set_state(st.cons, st.bface, st.t)
     b.step(nsteps, t_stop)
     cons, bface, t = b.get_state()
@@ -201,6 +202,57 @@ def test_riemann_2d_hll_fp64_and_mixed():
     for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
         assert rel_l1(a, b) <= TOLMIX, name
     assert divb_norm(spec, m[1])[0] <= 1e-12
+
+
+@pytest.mark.parametrize("rk,solver,flags", [(2, "hlld", 0), (3, "hlld", mhd.MHD_F_GRAPH),
+                                             (2, "hll", mhd.MHD_F_PERSISTENT)])
+@pytest.mark.parametrize("n,bc", [((30, 26, 22), (1, 0, 0)), ((17, 9, 1), (0, 1, 0)),
+                                  ((5, 40, 33), (1, 1, 1)), ((1, 1, 48), (0, 0, 1))])
+def test_char_reconstruction_fp64(n, bc, rk, solver, flags):
+    """Slopes limited in characteristic fields (MHD_REC_CHAR): bit for bit
+    with the oracle in 3D, 2D (fused y march) and 1D boxes."""
+    wl = W.random_smooth(n=n, seed=sum(n) + 3 * rk, bc=bc)
+    g = gpu_run(wl, 4, flags=flags, rk=rk, solver=solver, recon="char")[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=rk, solver=solver, recon="char")
+    assert_fp64_parity(g, o, f"char {n} {bc} rk{rk} {solver}")
+
+
+def test_char_reconstruction_shocks_and_mixed():
+    """Characteristic slopes through shocks (Orszag-Tang 2D, 60 steps, and
+    the 2D Riemann problem with HLL, 40 steps) bit for bit with the oracle,
+    the positivity fallback included; the mixed path within its bar."""
+    for wl, steps, kw in ((W.orszag_tang_2d(n=64), 60, {}),
+                          (W.riemann_2d(n=80), 40, {"rk": 3, "solver": "hll"})):
+        spec = wl.boxes[0]
+        o = oracle_run(spec, wl.states[0], steps, recon="char", **kw)
+        g = gpu_run(wl, steps, flags=mhd.MHD_F_GRAPH, recon="char", **kw)[0]
+        assert_fp64_parity(g, o, f"char {wl.name}")
+        m = gpu_run(wl, steps, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, recon="char",
+                    **kw)[0]
+        mp, mb = pressure_bmag(spec, m[0], m[1])
+        op, ob = pressure_bmag(spec, o[0], o[1])
+        for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+            assert rel_l1(a, b) <= TOLMIX, (wl.name, name)
+        assert divb_norm(spec, m[1])[0] <= 1e-12
+
+
+def test_char_blast_256_full_size_sampled():
+    """The benchmark workload at full size with characteristic slopes, graph
+    replay and autotuning: one step, dt over the whole grid and sampled cells
+    against the oracle (neighbourhoods of radius 8)."""
+    wl = W.blast_3d(n=256)
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE, recon="char") as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        dt_gpu, _ = sim.dt(0)
+        sim.step(1)
+        cons, bface, t = sim.get_state(0)
+    ob = O.OracleBox(spec, recon="char")
+    ob.set_state(st.cons, st.bface)
+    assert dt_gpu == ob.dt()
+    del ob
+    centres = [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25), (128, 154, 131)]
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, recon="char")
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
@@ -450,12 +502,12 @@ def _sub_box(spec, st, centre, r):
     return sub, cons, bface, tuple(off)
 
 
-def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2, solver="hlld"):
+def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2, solver="hlld", recon="prim"):
     """One oracle step with the GPU's dt on the neighbourhood of each sampled
     cell; compares the cell's conserved state and its three lower faces."""
     for c in centres:
         sub, sc, sb, o = _sub_box(spec, st, c, r)
-        ob = O.OracleBox(sub, rk=rk, solver=solver)
+        ob = O.OracleBox(sub, rk=rk, solver=solver, recon=recon)
         ob.set_state(sc, sb)
         ob.step_fixed_dt(dt)
         oc, obf, _ = ob.get_state()
