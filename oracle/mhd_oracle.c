@@ -69,6 +69,7 @@ struct orc_box {
   int rk;               /* Runge-Kutta stages: 2 (SSP-RK2) or 3 (SSP-RK3) */
   int solver;           /* Riemann solver: ORC_HLLD (HLL fallback) or ORC_HLL */
   int rec;              /* reconstruction: ORC_REC_PRIM or ORC_REC_CHAR */
+  int emf;              /* corner EMF: ORC_EMF_CONTACT, ORC_EMF_E0, ORC_EMF_ARITH */
   double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
@@ -598,6 +599,18 @@ double orc_ct_corner(double fa1, double fa0, double fb1, double fb0,
          0.25 * (dam - dap);
 }
 
+/* Corner EMF of the chosen kind: ORC_EMF_CONTACT as orc_ct_corner;
+ * ORC_EMF_E0, Gardiner & Stone's E0 average, the same formula with both
+ * sides of every derivative averaged (no upwinding); ORC_EMF_ARITH, the
+ * mean of the four face EMFs (Balsara & Spicer 1999). */
+double orc_ct_corner_kind(int kind, double fa1, double fa0, double fb1, double fb0,
+                          const double ec[4], double ma1, double ma0, double mb1,
+                          double mb0) {
+  if (kind == ORC_EMF_ARITH) return 0.25 * (fa1 + fa0 + fb1 + fb0);
+  if (kind == ORC_EMF_E0) return orc_ct_corner(fa1, fa0, fb1, fb0, ec, 0.0, 0.0, 0.0, 0.0);
+  return orc_ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0);
+}
+
 /* ------------------------------------------------------------------ */
 /* box                                                                 */
 /* ------------------------------------------------------------------ */
@@ -650,6 +663,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->rk = 2;
     b->solver = ORC_HLLD;
     b->rec = ORC_REC_PRIM;
+    b->emf = ORC_EMF_CONTACT;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
     b->idx[d] = 1.0 / b->dx[d];
   }
@@ -974,9 +988,8 @@ static void corner_emfs(orc_box *b, int c) {
         ec[1] = b->Ec[c][ia0]; /* (ia, ib-1)   */
         ec[2] = b->Ec[c][ib0]; /* (ia-1, ib)   */
         ec[3] = b->Ec[c][i11]; /* (ia, ib)     */
-        b->ED[c][i11] = orc_ct_corner(fa1, fa0, fb1, fb0, ec, b->FM[a][i11],
-                                      b->FM[a][ia0], b->FM[bb][i11],
-                                      b->FM[bb][ib0]);
+        b->ED[c][i11] = orc_ct_corner_kind(b->emf, fa1, fa0, fb1, fb0, ec, b->FM[a][i11],
+                                           b->FM[a][ia0], b->FM[bb][i11], b->FM[bb][ib0]);
       }
 }
 
@@ -1109,6 +1122,12 @@ void orc_step_fixed_dt(orc_box *b, double dt) {
 int orc_set_rk(orc_box *b, int stages) {
   if (stages != 2 && stages != 3) return -1;
   b->rk = stages;
+  return 0;
+}
+
+int orc_set_emf(orc_box *b, int emf) {
+  if (emf != ORC_EMF_CONTACT && emf != ORC_EMF_E0 && emf != ORC_EMF_ARITH) return -1;
+  b->emf = emf;
   return 0;
 }
 

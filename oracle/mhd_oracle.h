@@ -61,6 +61,17 @@ int orc_set_solver(orc_box *b, int solver);
 #define ORC_REC_PRIM 0
 #define ORC_REC_CHAR 1
 int orc_set_recon(orc_box *b, int rec);
+/* Corner EMF of the constrained transport: ORC_EMF_CONTACT (the default,
+ * contact-upwinded average, see orc_ct_corner), ORC_EMF_E0 (the same
+ * average with both sides of every derivative averaged) or ORC_EMF_ARITH
+ * (mean of the four face EMFs); -1 otherwise. */
+#define ORC_EMF_CONTACT 0
+#define ORC_EMF_E0 1
+#define ORC_EMF_ARITH 2
+int orc_set_emf(orc_box *b, int emf);
+double orc_ct_corner_kind(int kind, double fa1, double fa0, double fb1, double fb0,
+                          const double ec[4], double ma1, double ma0, double mb1,
+                          double mb0);
 /* Point functions of the characteristic reconstruction (pinned by tests). */
 void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
                     double R[7][7], double L[7][7]);

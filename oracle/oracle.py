@@ -22,6 +22,8 @@ _dp = C.POINTER(C.c_double)
 SOLVERS = {"hlld": 0, "hll": 1}
 # reconstructions (values of ORC_REC_PRIM / ORC_REC_CHAR)
 RECONS = {"prim": 0, "char": 1}
+# corner EMFs (values of ORC_EMF_CONTACT / ORC_EMF_E0 / ORC_EMF_ARITH)
+EMFS = {"contact": 0, "e0": 1, "arith": 2}
 
 
 def _lib():
@@ -50,6 +52,10 @@ def _lib():
         lib.orc_set_solver.restype = C.c_int
         lib.orc_set_recon.argtypes = [C.c_void_p, C.c_int]
         lib.orc_set_recon.restype = C.c_int
+        lib.orc_set_emf.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_emf.restype = C.c_int
+        lib.orc_ct_corner_kind.argtypes = [C.c_int] + [C.c_double] * 4 + [_dp] + [C.c_double] * 4
+        lib.orc_ct_corner_kind.restype = C.c_double
         lib.orc_prim_eigen.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, _dp]
         lib.orc_slope.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int, _dp]
         lib.orc_dt.argtypes = [C.c_void_p]
@@ -92,7 +98,7 @@ class OracleBox:
     """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
 
     def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2, solver: str = "hlld",
-                 recon: str = "prim"):
+                 recon: str = "prim", emf: str = "contact"):
         lib = _lib()
         self.spec = spec
         self.n = tuple(int(v) for v in spec.n)
@@ -112,6 +118,9 @@ class OracleBox:
         if recon not in RECONS or lib.orc_set_recon(self._h, RECONS[recon]) != 0:
             self.close()
             raise ValueError("oracle: recon must be 'prim' or 'char'")
+        if emf not in EMFS or lib.orc_set_emf(self._h, EMFS[emf]) != 0:
+            self.close()
+            raise ValueError("oracle: emf must be 'contact', 'e0' or 'arith'")
 
     def close(self):
         if self._h:
@@ -255,12 +264,13 @@ def ct_mass_flux(wl, wr, bn, gamma):
     return _lib().orc_ct_mass_flux(_ptr(wl), _ptr(wr), bn, gamma)
 
 
-def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0):
+def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0, kind="contact"):
     ec = _vec(ec, 4)
-    return _lib().orc_ct_corner(fa1, fa0, fb1, fb0, _ptr(ec), ma1, ma0, mb1, mb0)
+    return _lib().orc_ct_corner_kind(EMFS[kind], fa1, fa0, fb1, fb0, _ptr(ec), ma1, ma0, mb1,
+                                     mb0)
 
 
 __all__ = [
     "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
-    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "SOLVERS", "RECONS",
+    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "SOLVERS", "RECONS", "EMFS",
 ]

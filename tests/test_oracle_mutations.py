@@ -61,6 +61,12 @@ MUTATIONS = [
      "test_oracle_point.py::test_prim_eigenvectors_solve_the_jacobian"),
     ("char_alpha_slow", "double as2 = 0.5 * (sm + bt2) / sq;", "double as2 = 0.5 * (sm - bt2) / sq;",
      "test_oracle_point.py::test_prim_eigenvectors_solve_the_jacobian"),
+    ("emf_e0_upwinds", "if (kind == ORC_EMF_E0) return orc_ct_corner(fa1, fa0, fb1, fb0, ec, 0.0, 0.0, 0.0, 0.0);",
+     "if (kind == ORC_EMF_E0) return orc_ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0);",
+     "test_oracle_point.py::test_ct_corner_kinds"),
+    ("emf_arith_drops_face", "if (kind == ORC_EMF_ARITH) return 0.25 * (fa1 + fa0 + fb1 + fb0);",
+     "if (kind == ORC_EMF_ARITH) return 0.25 * (fa1 + fa0 + fb1 + fb1);",
+     "test_oracle_point.py::test_ct_corner_kinds"),
     ("hll_switch_ignored", "if (b->solver == ORC_HLL) {", "if (0) {",
      "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
     ("hll_upwind_term_sign", "f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;",

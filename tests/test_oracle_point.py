@@ -323,6 +323,33 @@ def test_ct_plane_parallel_reduction():
         assert e == pytest.approx(F, abs=1e-14 * (1 + abs(F) + abs(ec_lo) + abs(ec_hi)))
 
 
+def test_ct_corner_kinds():
+    """E0 (Gardiner & Stone): the contact formula with every derivative
+    averaged, so independent of the mass fluxes and equal to the contact
+    average where they vanish; it still reduces to the face EMF for a
+    grid-aligned plane-parallel flow.  The arithmetic mean (Balsara &
+    Spicer) ignores the cell EMFs and does not reduce: for variation along
+    a it gives F/2 + (E_c(ia-1) + E_c(ia))/4."""
+    rng = np.random.default_rng(43)
+    for _ in range(200):
+        f = rng.normal(size=4)
+        ec = rng.normal(size=4)
+        m = rng.normal(size=4)
+        e0 = O.ct_corner(*f, ec, *m, kind="e0")
+        assert e0 == O.ct_corner(*f, ec, 0.0, 0.0, 0.0, 0.0, kind="contact")
+        assert e0 == O.ct_corner(*f, ec, *rng.normal(size=4), kind="e0")
+        ar = O.ct_corner(*f, ec, *m, kind="arith")
+        assert ar == pytest.approx(0.25 * sum(f), abs=1e-15 * (1 + np.sum(np.abs(f))))
+        assert ar == O.ct_corner(*f, rng.normal(size=4), *rng.normal(size=4), kind="arith")
+        F = rng.normal()
+        ec_lo, ec_hi = rng.normal(size=2)
+        ec2 = np.array([ec_lo, ec_hi, ec_lo, ec_hi])
+        tol = 1e-14 * (1 + abs(F) + abs(ec_lo) + abs(ec_hi))
+        assert O.ct_corner(F, F, ec_hi, ec_lo, ec2, *m, kind="e0") == pytest.approx(F, abs=tol)
+        ar = O.ct_corner(F, F, ec_hi, ec_lo, ec2, *m, kind="arith")
+        assert ar == pytest.approx(0.5 * F + 0.25 * (ec_lo + ec_hi), abs=tol)
+
+
 def test_ct_upwind_selection():
     """With all transverse derivatives on one side zero and the other side
     non-zero, the sign of the mass flux picks which side contributes."""
