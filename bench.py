@@ -171,7 +171,8 @@ def kind_of(name):
     return None
 
 
-def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld", recon="prim"):
+def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld", recon="prim",
+            emf="contact"):
     """Per repeat: set the initial state, `warmup` untimed steps (the first
     repeat's include the autotuner's trials), then `steps` timed steps.
     Returns the median time, every repeat's time, the final state of box 0
@@ -180,7 +181,7 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld",
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
     sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk,
-                  solver=solver, recon=recon)
+                  solver=solver, recon=recon, emf=emf)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     times = []
@@ -548,7 +549,7 @@ PAPER_RIEMANN2D_INVOCATION_MS = {"Reconstruct, A100 OpenACC": 1.24,
                                  "HLL, A100 OpenACC": 1.63, "HLL, A100 OpenMP": 9.84}
 
 
-def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim"):
+def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim", emf="contact"):
     """kernel_times for a given integrator, Riemann solver and reconstruction."""
     import torch
     from paper_2606_12753_amd import mhd
@@ -556,7 +557,7 @@ def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim"):
     try:
         stream = torch.cuda.Stream()
         sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
-                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver, recon=recon)
+                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver, recon=recon, emf=emf)
         for b, st in enumerate(wl.states):
             sim.set_state(b, st.cons, st.bface, 0.0)
         sim.step(1)
@@ -608,18 +609,21 @@ def paper_workload(a, flags):
 
 def options_bench(a, flags):
     """Cost of the scheme options on the benchmark input (blast, n^3): the
-    default (primitive slopes, HLLD, SSP-RK2) against SSP-RK3, HLL at every
-    face and characteristic slopes, FP64 and mixed; median of three repeats
+    default (primitive slopes, HLLD, SSP-RK2, contact-upwinded corner EMFs)
+    against SSP-RK3, HLL at every face, characteristic slopes and the E0 and
+    arithmetic corner EMFs, FP64 and mixed; median of three repeats
     of a.steps steps, per-launch kernel times, and the x sweep's algorithmic
     HBM rate (its bytes do not depend on the options)."""
     from paper_2606_12753_amd import mhd, workloads
     print(f"# options: building blast {a.n}^3 input", file=sys.stderr, flush=True)
     wl = workloads.blast_3d(n=a.n)
     cells = wl.cells
-    opts = [("default", dict(rk=2, solver="hlld", recon="prim")),
-            ("rk3", dict(rk=3, solver="hlld", recon="prim")),
-            ("hll", dict(rk=2, solver="hll", recon="prim")),
-            ("char", dict(rk=2, solver="hlld", recon="char"))]
+    opts = [("default", dict(rk=2, solver="hlld", recon="prim", emf="contact")),
+            ("rk3", dict(rk=3, solver="hlld", recon="prim", emf="contact")),
+            ("hll", dict(rk=2, solver="hll", recon="prim", emf="contact")),
+            ("char", dict(rk=2, solver="hlld", recon="char", emf="contact")),
+            ("emf_e0", dict(rk=2, solver="hlld", recon="prim", emf="e0")),
+            ("emf_arith", dict(rk=2, solver="hlld", recon="prim", emf="arith"))]
     out = {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+CT, CFL 0.3", "cells": cells,
            "steps": a.steps, "options": {}}
     for name, kw in opts:
@@ -629,7 +633,7 @@ def options_bench(a, flags):
             r = run_gpu(wl, prec, a.steps, a.warmup, flags, repeats=3, **kw)
             r["sim"].close()
             kt = kernel_times_of(wl, prec, min(a.steps, 10), r["variant"], kw["rk"], kw["solver"],
-                                 kw["recon"])
+                                 kw["recon"], kw["emf"])
             table = BYTES_FP64 if prec == mhd.MHD_FP64 else BYTES_MIXED
             xbytes = 0.5 * (table["sweep_x"][0] + table["sweep_x"][1]) * cells
             row[key] = {"Mcell_updates_per_s": round(cells * a.steps / (r["ms"] * 1e-3) / 1e6, 1),

@@ -69,6 +69,15 @@ extern "C" {
                           names both ("primitive (or characteristic)",
                           its section 2.2.3). */
 
+/* corner EMF of the constrained transport */
+#define MHD_EMF_CONTACT 0 /* contact-upwinded average (Gardiner & Stone
+                             2005): face-to-corner derivatives taken on the
+                             upwind side of the face's mass flux */
+#define MHD_EMF_E0 1      /* their E0 average: each derivative the mean of
+                             its two sides */
+#define MHD_EMF_ARITH 2   /* mean of the four face EMFs (Balsara & Spicer
+                             1999) */
+
 /* where caller arrays live */
 #define MHD_HOST 0
 #define MHD_DEVICE 1
@@ -123,6 +132,7 @@ typedef struct {
                               workspace) */
   int32_t riemann;         /* MHD_RS_HLLD (0) or MHD_RS_HLL */
   int32_t recon;           /* MHD_REC_PRIM (0) or MHD_REC_CHAR */
+  int32_t ct_emf;          /* MHD_EMF_CONTACT (0), MHD_EMF_E0 or MHD_EMF_ARITH */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;

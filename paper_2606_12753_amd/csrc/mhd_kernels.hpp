@@ -77,6 +77,8 @@ struct Box {
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
   int xft;            // x sweep: faces per tile
+  int emf;            // corner EMF: 0 contact-upwinded, 1 E0 (derivatives
+                      // averaged), 2 mean of the four face EMFs
   int ysl, yseg;      // y march: cells per segment, segments
   int zsl, zseg;      // z march
   int ntile[6];       // tiles per kernel kind
@@ -1384,7 +1386,11 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 }
 
 // Corner EMFs: for every corner position one lane computes the EMF along
-// each axis c whose range contains it (contact-upwinded average).
+// each axis c whose range contains it: the contact-upwinded average of
+// Gardiner & Stone (2005) (b.emf = 0), their E0 average with every
+// face-to-corner derivative taken as the mean of its two sides (1), or the
+// mean of the four face EMFs (2, Balsara & Spicer 1999; no cell EMF or mass
+// flux is read).
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -1423,26 +1429,34 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
       const int fb1i = fidx(b, bb, q[0], q[1], q[2]);
       q[a] = m0[a];
       const int fb0i = fidx(b, bb, q[0], q[1], q[2]);
-      // cells (ia-1, ib-1), (ia, ib-1), (ia-1, ib), (ia, ib)
-      real ec[4];
-      q[a] = m0[a]; q[bb] = m0[bb]; ec[0] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = m1[a]; q[bb] = m0[bb]; ec[1] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = m0[a]; q[bb] = m1[bb]; ec[2] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-      q[a] = m1[a]; q[bb] = m1[bb]; ec[3] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
       const real fa1 = ld<real>(b.EF[a][1], fa1i);
       const real fa0 = ld<real>(b.EF[a][1], fa0i);
       const real fb1 = ld<real>(b.EF[bb][0], fb1i);
       const real fb0 = ld<real>(b.EF[bb][0], fb0i);
-      const real m_a1 = ld<real>(b.MF[a], fa1i);
-      const real m_a0 = ld<real>(b.MF[a], fa0i);
-      const real m_b1 = ld<real>(b.MF[bb], fb1i);
-      const real m_b0 = ld<real>(b.MF[bb], fb0i);
-      const real dbp = upwind(m_a1, ec[2] - fb0, ec[3] - fb1);
-      const real dbm = upwind(m_a0, fb0 - ec[0], fb1 - ec[1]);
-      const real dap = upwind(m_b1, ec[1] - fa0, ec[3] - fa1);
-      const real dam = upwind(m_b0, fa0 - ec[0], fa1 - ec[2]);
-      const real e = (real)0.25 * (fa1 + fa0 + fb1 + fb0) + (real)0.25 * (dbm - dbp) +
-                     (real)0.25 * (dam - dap);
+      real e;
+      if (b.emf == 2) {
+        e = (real)0.25 * (fa1 + fa0 + fb1 + fb0);
+      } else {
+        // cells (ia-1, ib-1), (ia, ib-1), (ia-1, ib), (ia, ib)
+        real ec[4];
+        q[a] = m0[a]; q[bb] = m0[bb]; ec[0] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+        q[a] = m1[a]; q[bb] = m0[bb]; ec[1] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+        q[a] = m0[a]; q[bb] = m1[bb]; ec[2] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+        q[a] = m1[a]; q[bb] = m1[bb]; ec[3] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
+        real m_a1 = (real)0, m_a0 = (real)0, m_b1 = (real)0, m_b0 = (real)0;
+        if (b.emf == 0) {
+          m_a1 = ld<real>(b.MF[a], fa1i);
+          m_a0 = ld<real>(b.MF[a], fa0i);
+          m_b1 = ld<real>(b.MF[bb], fb1i);
+          m_b0 = ld<real>(b.MF[bb], fb0i);
+        }
+        const real dbp = upwind(m_a1, ec[2] - fb0, ec[3] - fb1);
+        const real dbm = upwind(m_a0, fb0 - ec[0], fb1 - ec[1]);
+        const real dap = upwind(m_b1, ec[1] - fa0, ec[3] - fa1);
+        const real dam = upwind(m_b0, fa0 - ec[0], fa1 - ec[2]);
+        e = (real)0.25 * (fa1 + fa0 + fb1 + fb0) + (real)0.25 * (dbm - dbp) +
+            (real)0.25 * (dam - dap);
+      }
       st<real>(b.ED[c], eidx(b, c, pos[0], pos[1], pos[2]), e);
     }
   }

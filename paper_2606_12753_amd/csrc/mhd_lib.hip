@@ -144,6 +144,11 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     err = "config: recon must be MHD_REC_PRIM or MHD_REC_CHAR";
     return MHD_E_INVAL;
   }
+  if (cfg->ct_emf != MHD_EMF_CONTACT && cfg->ct_emf != MHD_EMF_E0 &&
+      cfg->ct_emf != MHD_EMF_ARITH) {
+    err = "config: ct_emf must be MHD_EMF_CONTACT, MHD_EMF_E0 or MHD_EMF_ARITH";
+    return MHD_E_INVAL;
+  }
   for (int b = 0; b < cfg->nboxes; b++) {
     int rc = validate_box(cfg->boxes[b], err);
     if (rc) {
@@ -570,6 +575,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xft = t.xft;
+    b.emf = cfg->ct_emf;
     b.ysl = t.ysl;
     b.yseg = t.yseg;
     b.zsl = t.zsl;

@@ -39,12 +39,12 @@ def rel_l1(a, b):
 
 
 def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2,
-            solver="hlld", recon="prim"):
+            solver="hlld", recon="prim", emf="contact"):
     idx = range(len(wl.boxes)) if boxes is None else boxes
     specs = [wl.boxes[i] for i in idx]
     out = []
     with mhd.Sim(specs, precision=precision, flags=flags, rk=rk, solver=solver,
-                 recon=recon) as sim:
+                 recon=recon, emf=emf) as sim:
         for k, i in enumerate(idx):
             st = wl.states[i]
             sim.set_state(k, st.cons, st.bface, st.t)
@@ -55,8 +55,8 @@ def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None,
     return out
 
 
-def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim"):
-    b = O.OracleBox(spec, rk=rk, solver=solver, recon=recon)
+def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim", emf="contact"):
+    b = O.OracleBox(spec, rk=rk, solver=solver, recon=recon, emf=emf)
     b.set_state(st.cons, st.bface, st.t)
     b.step(nsteps, t_stop)
     cons, bface, t = b.get_state()
@@ -215,6 +215,34 @@ def test_char_reconstruction_fp64(n, bc, rk, solver, flags):
     g = gpu_run(wl, 4, flags=flags, rk=rk, solver=solver, recon="char")[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=rk, solver=solver, recon="char")
     assert_fp64_parity(g, o, f"char {n} {bc} rk{rk} {solver}")
+
+
+@pytest.mark.parametrize("emf", ["e0", "arith"])
+@pytest.mark.parametrize("n,bc,recon", [((30, 26, 22), (1, 0, 0), "prim"),
+                                        ((24, 20, 1), (0, 1, 0), "char"),
+                                        ((9, 1, 40), (1, 0, 1), "prim")])
+def test_corner_emf_kinds_fp64(n, bc, recon, emf):
+    """E0 and arithmetic corner EMFs: bit for bit with the oracle (3D, 2D
+    with the fused y march, and a box with one inactive axis)."""
+    wl = W.random_smooth(n=n, seed=sum(n) + len(emf), bc=bc)
+    g = gpu_run(wl, 4, flags=mhd.MHD_F_GRAPH, recon=recon, emf=emf)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4, recon=recon, emf=emf)
+    assert_fp64_parity(g, o, f"emf {emf} {n} {bc}")
+
+
+def test_corner_emf_kinds_orszag_tang_and_mixed():
+    wl = W.orszag_tang_2d(n=64)
+    spec = wl.boxes[0]
+    for emf in ("e0", "arith"):
+        o = oracle_run(spec, wl.states[0], 40, emf=emf)
+        g = gpu_run(wl, 40, flags=mhd.MHD_F_GRAPH, emf=emf)[0]
+        assert_fp64_parity(g, o, f"OT2D {emf}")
+        m = gpu_run(wl, 40, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, emf=emf)[0]
+        mp, mb = pressure_bmag(spec, m[0], m[1])
+        op, ob = pressure_bmag(spec, o[0], o[1])
+        for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+            assert rel_l1(a, b) <= TOLMIX, (emf, name)
+        assert divb_norm(spec, m[1])[0] <= 1e-12
 
 
 def test_char_reconstruction_shocks_and_mixed():
