@@ -70,6 +70,7 @@ struct orc_box {
   int solver;           /* Riemann solver: ORC_HLLD (HLL fallback) or ORC_HLL */
   int rec;              /* reconstruction: ORC_REC_PRIM or ORC_REC_CHAR */
   int emf;              /* corner EMF: ORC_EMF_CONTACT, ORC_EMF_E0, ORC_EMF_ARITH */
+  int lim;              /* slope limiter: ORC_LIM_MINMOD, ORC_LIM_MC, ORC_LIM_VANLEER */
   double dx[3], idx[3]; /* cell size and its reciprocal */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
@@ -107,6 +108,36 @@ double orc_minmod(double a, double b) {
   if (a > 0.0 && b > 0.0) return a < b ? a : b;
   if (a < 0.0 && b < 0.0) return a > b ? a : b;
   return 0.0;
+}
+
+/* Monotonised central limiter (van Leer 1977): the central difference
+ * (a + b)/2, bounded by twice each one-sided difference; 0 at an extremum. */
+double orc_mc(double a, double b) {
+  if (a > 0.0 && b > 0.0) {
+    double c = 0.5 * (a + b);
+    double m = 2.0 * a < 2.0 * b ? 2.0 * a : 2.0 * b;
+    return c < m ? c : m;
+  }
+  if (a < 0.0 && b < 0.0) {
+    double c = 0.5 * (a + b);
+    double m = 2.0 * a > 2.0 * b ? 2.0 * a : 2.0 * b;
+    return c > m ? c : m;
+  }
+  return 0.0;
+}
+
+/* van Leer's harmonic limiter (van Leer 1974): 2ab/(a + b) where a and b
+ * have the same sign, else 0. */
+double orc_vanleer(double a, double b) {
+  if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return 2.0 * a * b / (a + b);
+  return 0.0;
+}
+
+/* limited slope from the two one-sided differences */
+double orc_limit(int lim, double a, double b) {
+  if (lim == ORC_LIM_MC) return orc_mc(a, b);
+  if (lim == ORC_LIM_VANLEER) return orc_vanleer(a, b);
+  return orc_minmod(a, b);
 }
 
 int orc_cons_to_prim(const double u[5], const double bc[3], double gamma,
@@ -260,15 +291,15 @@ void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
 }
 
 /* Limited slope of cell 0 from its neighbours qm, qp (seven face-frame
- * primitives each).  rec = ORC_REC_PRIM: minmod of the two one-sided
- * differences per variable.  ORC_REC_CHAR: the differences are projected on
- * the left eigenvectors of the cell's own state (B_n = bn, its
- * cell-centred normal field), limited by minmod per characteristic field and
- * projected back with the right eigenvectors; where that slope would make
- * the density or pressure at either face of the cell non-positive, the cell
- * takes the primitive slope instead. */
+ * primitives each), with limiter lim (orc_limit).  rec = ORC_REC_PRIM: the
+ * limiter on the two one-sided differences per variable.  ORC_REC_CHAR: the
+ * differences are projected on the left eigenvectors of the cell's own
+ * state (B_n = bn, its cell-centred normal field), limited per
+ * characteristic field and projected back with the right eigenvectors;
+ * where that slope would make the density or pressure at either face of the
+ * cell non-positive, the cell takes the primitive slope instead. */
 void orc_slope(const double qm[7], const double q0[7], const double qp[7], double bn,
-               double gamma, int rec, double d[7]) {
+               double gamma, int rec, int lim, double d[7]) {
   double dm[7], dp[7];
   int v, k;
   for (v = 0; v < 7; v++) {
@@ -284,7 +315,7 @@ void orc_slope(const double qm[7], const double q0[7], const double qp[7], doubl
         cm = cm + L[k][v] * dm[v];
         cp = cp + L[k][v] * dp[v];
       }
-      ch[k] = orc_minmod(cm, cp);
+      ch[k] = orc_limit(lim, cm, cp);
     }
     for (v = 0; v < 7; v++) {
       double s = 0.0;
@@ -295,7 +326,7 @@ void orc_slope(const double qm[7], const double q0[7], const double qp[7], doubl
         q0[4] + 0.5 * d[4] > 0.0 && q0[4] - 0.5 * d[4] > 0.0)
       return;
   }
-  for (v = 0; v < 7; v++) d[v] = orc_minmod(dm[v], dp[v]);
+  for (v = 0; v < 7; v++) d[v] = orc_limit(lim, dm[v], dp[v]);
 }
 
 /* fast magnetosonic speed along the normal of (bn, bt1, bt2) */
@@ -664,6 +695,7 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->solver = ORC_HLLD;
     b->rec = ORC_REC_PRIM;
     b->emf = ORC_EMF_CONTACT;
+    b->lim = ORC_LIM_MINMOD;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
     b->idx[d] = 1.0 / b->dx[d];
   }
@@ -907,19 +939,19 @@ static void sweep(orc_box *b, int d) {
           cs[s] = IXp(b, p2);
         }
         double wl[7], wr[7];
-        if (b->rec == ORC_REC_PRIM) {
+        if (b->rec == ORC_REC_PRIM && b->lim == ORC_LIM_MINMOD) {
           for (int v = 0; v < 7; v++) {
             double *q = b->W[slot[v]];
             orc_plm_face(q[cs[0]], q[cs[1]], q[cs[2]], q[cs[3]], &wl[v], &wr[v]);
           }
         } else {
-          /* slopes of the two cells next to the face, each limited in the
-           * characteristic fields of its own state */
+          /* slopes of the two cells next to the face (in the characteristic
+           * fields of each cell's own state for ORC_REC_CHAR) */
           double qs[4][7], s1[7], s2[7];
           for (int m = 0; m < 4; m++)
             for (int v = 0; v < 7; v++) qs[m][v] = b->W[slot[v]][cs[m]];
-          orc_slope(qs[0], qs[1], qs[2], b->W[5 + d][cs[1]], b->gamma, b->rec, s1);
-          orc_slope(qs[1], qs[2], qs[3], b->W[5 + d][cs[2]], b->gamma, b->rec, s2);
+          orc_slope(qs[0], qs[1], qs[2], b->W[5 + d][cs[1]], b->gamma, b->rec, b->lim, s1);
+          orc_slope(qs[1], qs[2], qs[3], b->W[5 + d][cs[2]], b->gamma, b->rec, b->lim, s2);
           for (int v = 0; v < 7; v++) {
             wl[v] = qs[1][v] + 0.5 * s1[v];
             wr[v] = qs[2][v] - 0.5 * s2[v];
@@ -1122,6 +1154,12 @@ void orc_step_fixed_dt(orc_box *b, double dt) {
 int orc_set_rk(orc_box *b, int stages) {
   if (stages != 2 && stages != 3) return -1;
   b->rk = stages;
+  return 0;
+}
+
+int orc_set_limiter(orc_box *b, int lim) {
+  if (lim != ORC_LIM_MINMOD && lim != ORC_LIM_MC && lim != ORC_LIM_VANLEER) return -1;
+  b->lim = lim;
   return 0;
 }
 

@@ -76,7 +76,15 @@ double orc_ct_corner_kind(int kind, double fa1, double fa0, double fb1, double f
 void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
                     double R[7][7], double L[7][7]);
 void orc_slope(const double qm[7], const double q0[7], const double qp[7], double bn,
-               double gamma, int rec, double d[7]);
+               double gamma, int rec, int lim, double d[7]);
+/* Slope limiter of the PLM reconstruction: ORC_LIM_MINMOD (the default),
+ * ORC_LIM_MC (monotonised central) or ORC_LIM_VANLEER (harmonic); -1
+ * otherwise.  orc_limit is the limiter as a point function. */
+#define ORC_LIM_MINMOD 0
+#define ORC_LIM_MC 1
+#define ORC_LIM_VANLEER 2
+int orc_set_limiter(orc_box *b, int lim);
+double orc_limit(int lim, double a, double b);
 /* One step with a caller-given dt (used for sampled parity on sub-boxes). */
 void orc_step_fixed_dt(orc_box *b, double dt);
 /* CFL time step of the current state (no t_stop clamp). */

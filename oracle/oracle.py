@@ -24,6 +24,8 @@ SOLVERS = {"hlld": 0, "hll": 1}
 RECONS = {"prim": 0, "char": 1}
 # corner EMFs (values of ORC_EMF_CONTACT / ORC_EMF_E0 / ORC_EMF_ARITH)
 EMFS = {"contact": 0, "e0": 1, "arith": 2}
+# slope limiters (values of ORC_LIM_MINMOD / ORC_LIM_MC / ORC_LIM_VANLEER)
+LIMITERS = {"minmod": 0, "mc": 1, "vanleer": 2}
 
 
 def _lib():
@@ -57,7 +59,11 @@ def _lib():
         lib.orc_ct_corner_kind.argtypes = [C.c_int] + [C.c_double] * 4 + [_dp] + [C.c_double] * 4
         lib.orc_ct_corner_kind.restype = C.c_double
         lib.orc_prim_eigen.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, _dp]
-        lib.orc_slope.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int, _dp]
+        lib.orc_slope.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp]
+        lib.orc_set_limiter.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_limiter.restype = C.c_int
+        lib.orc_limit.argtypes = [C.c_int, C.c_double, C.c_double]
+        lib.orc_limit.restype = C.c_double
         lib.orc_dt.argtypes = [C.c_void_p]
         lib.orc_dt.restype = C.c_double
         lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
@@ -98,7 +104,7 @@ class OracleBox:
     """One box of the oracle.  ``spec`` needs n, lo, hi, bc, gamma, cfl."""
 
     def __init__(self, spec, pfloor: float = 1e-10, rk: int = 2, solver: str = "hlld",
-                 recon: str = "prim", emf: str = "contact"):
+                 recon: str = "prim", emf: str = "contact", limiter: str = "minmod"):
         lib = _lib()
         self.spec = spec
         self.n = tuple(int(v) for v in spec.n)
@@ -121,6 +127,9 @@ class OracleBox:
         if emf not in EMFS or lib.orc_set_emf(self._h, EMFS[emf]) != 0:
             self.close()
             raise ValueError("oracle: emf must be 'contact', 'e0' or 'arith'")
+        if limiter not in LIMITERS or lib.orc_set_limiter(self._h, LIMITERS[limiter]) != 0:
+            self.close()
+            raise ValueError("oracle: limiter must be 'minmod', 'mc' or 'vanleer'")
 
     def close(self):
         if self._h:
@@ -227,11 +236,16 @@ def prim_eigen(w, bn, gamma):
     return lam, R, L
 
 
-def slope(qm, q0, qp, bn, gamma, recon="prim"):
+def slope(qm, q0, qp, bn, gamma, recon="prim", limiter="minmod"):
     qm, q0, qp = _vec(qm, 7), _vec(q0, 7), _vec(qp, 7)
     d = np.empty(7)
-    _lib().orc_slope(_ptr(qm), _ptr(q0), _ptr(qp), bn, gamma, RECONS[recon], _ptr(d))
+    _lib().orc_slope(_ptr(qm), _ptr(q0), _ptr(qp), bn, gamma, RECONS[recon], LIMITERS[limiter],
+                     _ptr(d))
     return d
+
+
+def limit(a, b, limiter="minmod"):
+    return _lib().orc_limit(LIMITERS[limiter], a, b)
 
 
 def phys_flux(w, bn, gamma):
@@ -272,5 +286,5 @@ def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0, kind="contact"):
 
 __all__ = [
     "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
-    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "SOLVERS", "RECONS", "EMFS",
+    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "limit", "SOLVERS", "RECONS", "EMFS", "LIMITERS",
 ]

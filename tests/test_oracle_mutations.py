@@ -67,6 +67,14 @@ MUTATIONS = [
     ("emf_arith_drops_face", "if (kind == ORC_EMF_ARITH) return 0.25 * (fa1 + fa0 + fb1 + fb0);",
      "if (kind == ORC_EMF_ARITH) return 0.25 * (fa1 + fa0 + fb1 + fb1);",
      "test_oracle_point.py::test_ct_corner_kinds"),
+    ("mc_bound_one_sided", "double m = 2.0 * a < 2.0 * b ? 2.0 * a : 2.0 * b;",
+     "double m = 2.0 * a < 2.0 * b ? a : b;",
+     "test_oracle_point.py::test_limiters_match_their_flux_limiter_functions"),
+    ("vanleer_arithmetic_mean", "return 2.0 * a * b / (a + b);", "return 0.5 * (a + b);",
+     "test_oracle_point.py::test_limiters_match_their_flux_limiter_functions"),
+    ("limiter_switch_ignored", "if (b->rec == ORC_REC_PRIM && b->lim == ORC_LIM_MINMOD) {",
+     "if (b->rec == ORC_REC_PRIM) {",
+     "test_oracle_scheme.py::test_limiters_sod_order_and_sharpness"),
     ("hll_switch_ignored", "if (b->solver == ORC_HLL) {", "if (0) {",
      "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
     ("hll_upwind_term_sign", "f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;",

@@ -476,3 +476,41 @@ def test_char_slope_falls_back_where_faces_lose_positivity():
     raw = R_ @ np.array(ch)
     assert not (q0[0] - 0.5 * abs(raw[0]) > 0)   # the characteristic slope is rejected
     assert np.array_equal(d, prim)
+
+
+# ---------------------------------------------------------------- slope limiters
+
+def test_limiters_match_their_flux_limiter_functions():
+    """In Sweby's form slope = phi(r) b with r = a/b: minmod phi = max(0,
+    min(r, 1)); monotonised central phi = max(0, min(2r, (1 + r)/2, 2));
+    van Leer phi = (r + |r|)/(1 + |r|).  All three lie in the TVD region
+    0 <= phi <= min(2r, 2) and have phi(1) = 1."""
+    rng = np.random.default_rng(61)
+    phis = {
+        "minmod": lambda r: max(0.0, min(r, 1.0)),
+        "mc": lambda r: max(0.0, min(2 * r, 0.5 * (1 + r), 2.0)),
+        "vanleer": lambda r: (r + abs(r)) / (1 + abs(r)),
+    }
+    for _ in range(2000):
+        b = rng.choice([-1, 1]) * 10 ** rng.uniform(-3, 3)
+        r = rng.uniform(-3, 5)
+        a = r * b
+        for name, phi in phis.items():
+            s = O.limit(a, b, name)
+            assert s == pytest.approx(phi(r) * b, rel=1e-13, abs=1e-300), (name, r)
+            ph = s / b
+            assert -1e-15 <= ph <= min(2 * max(r, 0), 2) + 1e-12, (name, r)
+    for name in phis:
+        for d in (1e-3, -2.5, 7.0):
+            assert O.limit(d, d, name) == pytest.approx(d, rel=1e-15)
+
+
+def test_limiters_symmetric_and_odd():
+    rng = np.random.default_rng(62)
+    for _ in range(1000):
+        a, b = rng.normal(size=2) * 10 ** rng.uniform(-3, 3, 2)
+        for name in ("minmod", "mc", "vanleer"):
+            s = O.limit(a, b, name)
+            assert s == O.limit(b, a, name)
+            assert -s == O.limit(-a, -b, name)
+            assert (s == 0.0) == (a * b <= 0.0)
