@@ -103,7 +103,7 @@ def parse():
 
 
 SOURCES = ["csrc/mhd_kernels.hpp", "csrc/mhd_step.hpp", "csrc/mhd_lib.hip", "csrc/mhd_fp32.hip",
-           "build.py"]
+           "csrc/mhd_opt64.hip", "csrc/mhd_opt32.hip", "build.py"]
 TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_blast_256.md")
 KINDS = ["sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 COPY_BYTES = 1 << 30  # calibration copy of the counter pass
@@ -172,7 +172,7 @@ def kind_of(name):
 
 
 def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld", recon="prim",
-            emf="contact"):
+            emf="contact", limiter="minmod"):
     """Per repeat: set the initial state, `warmup` untimed steps (the first
     repeat's include the autotuner's trials), then `steps` timed steps.
     Returns the median time, every repeat's time, the final state of box 0
@@ -181,7 +181,7 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld",
     from paper_2606_12753_amd import mhd
     stream = torch.cuda.Stream()
     sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream, flags=flags, rk=rk,
-                  solver=solver, recon=recon, emf=emf)
+                  solver=solver, recon=recon, emf=emf, limiter=limiter)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     times = []
@@ -549,7 +549,8 @@ PAPER_RIEMANN2D_INVOCATION_MS = {"Reconstruct, A100 OpenACC": 1.24,
                                  "HLL, A100 OpenACC": 1.63, "HLL, A100 OpenMP": 9.84}
 
 
-def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim", emf="contact"):
+def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim", emf="contact",
+                    limiter="minmod"):
     """kernel_times for a given integrator, Riemann solver and reconstruction."""
     import torch
     from paper_2606_12753_amd import mhd
@@ -557,7 +558,8 @@ def kernel_times_of(wl, precision, steps, variant, rk, solver, recon="prim", emf
     try:
         stream = torch.cuda.Stream()
         sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
-                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver, recon=recon, emf=emf)
+                      flags=mhd.MHD_F_TIMING, rk=rk, solver=solver, recon=recon, emf=emf,
+                      limiter=limiter)
         for b, st in enumerate(wl.states):
             sim.set_state(b, st.cons, st.bface, 0.0)
         sim.step(1)
@@ -610,8 +612,8 @@ def paper_workload(a, flags):
 def options_bench(a, flags):
     """Cost of the scheme options on the benchmark input (blast, n^3): the
     default (primitive slopes, HLLD, SSP-RK2, contact-upwinded corner EMFs)
-    against SSP-RK3, HLL at every face, characteristic slopes and the E0 and
-    arithmetic corner EMFs, FP64 and mixed; median of three repeats
+    against SSP-RK3, HLL at every face, characteristic slopes, the E0 and
+    arithmetic corner EMFs and the MC and van Leer limiters, FP64 and mixed; median of three repeats
     of a.steps steps, per-launch kernel times, and the x sweep's algorithmic
     HBM rate (its bytes do not depend on the options)."""
     from paper_2606_12753_amd import mhd, workloads
@@ -623,7 +625,10 @@ def options_bench(a, flags):
             ("hll", dict(rk=2, solver="hll", recon="prim", emf="contact")),
             ("char", dict(rk=2, solver="hlld", recon="char", emf="contact")),
             ("emf_e0", dict(rk=2, solver="hlld", recon="prim", emf="e0")),
-            ("emf_arith", dict(rk=2, solver="hlld", recon="prim", emf="arith"))]
+            ("emf_arith", dict(rk=2, solver="hlld", recon="prim", emf="arith")),
+            ("limiter_mc", dict(rk=2, solver="hlld", recon="prim", emf="contact", limiter="mc")),
+            ("limiter_vanleer", dict(rk=2, solver="hlld", recon="prim", emf="contact",
+                                     limiter="vanleer"))]
     out = {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+CT, CFL 0.3", "cells": cells,
            "steps": a.steps, "options": {}}
     for name, kw in opts:
@@ -633,7 +638,7 @@ def options_bench(a, flags):
             r = run_gpu(wl, prec, a.steps, a.warmup, flags, repeats=3, **kw)
             r["sim"].close()
             kt = kernel_times_of(wl, prec, min(a.steps, 10), r["variant"], kw["rk"], kw["solver"],
-                                 kw["recon"], kw["emf"])
+                                 kw["recon"], kw["emf"], kw.get("limiter", "minmod"))
             table = BYTES_FP64 if prec == mhd.MHD_FP64 else BYTES_MIXED
             xbytes = 0.5 * (table["sweep_x"][0] + table["sweep_x"][1]) * cells
             row[key] = {"Mcell_updates_per_s": round(cells * a.steps / (r["ms"] * 1e-3) / 1e6, 1),

@@ -59,7 +59,8 @@ extern "C" {
 #define MHD_RS_HLL 1  /* HLL (Harten, Lax & van Leer 1983) with the same
                          outer wave speeds */
 
-/* variables the PLM slopes are limited in (minmod in both) */
+/* variables the PLM slopes are limited in (with the limiter of
+ * mhd_config.limiter) */
 #define MHD_REC_PRIM 0 /* primitive variables */
 #define MHD_REC_CHAR 1 /* characteristic fields of each cell's own state
                           (eigenvectors of the primitive-variable system,
@@ -68,6 +69,11 @@ extern "C" {
                           pressure takes the primitive slope.  The paper
                           names both ("primitive (or characteristic)",
                           its section 2.2.3). */
+
+/* slope limiter of the PLM reconstruction (in either variable set) */
+#define MHD_LIM_MINMOD 0  /* minmod */
+#define MHD_LIM_MC 1      /* monotonised central (van Leer 1977) */
+#define MHD_LIM_VANLEER 2 /* van Leer's harmonic mean (van Leer 1974) */
 
 /* corner EMF of the constrained transport */
 #define MHD_EMF_CONTACT 0 /* contact-upwinded average (Gardiner & Stone
@@ -133,6 +139,7 @@ typedef struct {
   int32_t riemann;         /* MHD_RS_HLLD (0) or MHD_RS_HLL */
   int32_t recon;           /* MHD_REC_PRIM (0) or MHD_REC_CHAR */
   int32_t ct_emf;          /* MHD_EMF_CONTACT (0), MHD_EMF_E0 or MHD_EMF_ARITH */
+  int32_t limiter;         /* MHD_LIM_MINMOD (0), MHD_LIM_MC or MHD_LIM_VANLEER */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -193,7 +200,8 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
  * segment length (cells),
  * [3] persistent grid (0/1).
  * The variants differ only in scheduling: FP64 results are identical.  With
- * MHD_REC_CHAR the sweeps run one variant ([0] and [1] are then ignored). */
+ * MHD_REC_CHAR or a limiter other than minmod the sweeps run one variant
+ * ([0] and [1] are then ignored). */
 int mhd_tuning(mhd_ctx *ctx, int32_t variant[4]);
 
 /* Frees the context and every buffer the library allocated (a caller

@@ -20,6 +20,8 @@ LIB = os.path.join(HERE, "libmhd355.so")
 UNITS = [
     (os.path.join(CSRC, "mhd_lib.hip"), ["-ffp-contract=off"]),
     (os.path.join(CSRC, "mhd_fp32.hip"), ["-ffp-contract=fast"]),
+    (os.path.join(CSRC, "mhd_opt64.hip"), ["-ffp-contract=off"]),
+    (os.path.join(CSRC, "mhd_opt32.hip"), ["-ffp-contract=fast"]),
 ]
 SOURCES = [u[0] for u in UNITS]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("mhd_kernels.hpp", "mhd_step.hpp")] + \
@@ -34,14 +36,18 @@ FLAGS = [
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    objs = []
+    # the translation units compile concurrently
+    objs, procs = [], []
     for src, fl in UNITS:
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
         cmd = [HIPCC] + FLAGS + fl + list(extra or []) + ["-c", "-o", obj, src]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, pr in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

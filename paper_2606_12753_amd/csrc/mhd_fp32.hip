@@ -6,4 +6,4 @@
 // its instruction stream.
 #include "mhd_step.hpp"
 
-int mhd_enqueue_fp32(const mhd::StepCtx& sc) { return mhd::enqueue_step_kernels<float>(sc); }
+int mhd_enqueue_fp32(const mhd::StepCtx& sc) { return mhd::enqueue_step_sl<float, 0>(sc); }

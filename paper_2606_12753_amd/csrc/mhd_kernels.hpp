@@ -331,12 +331,32 @@ __device__ __forceinline__ real minmod(real a, real b) {
   return vmax(vmin(a, b), vmin(vmax(a, b), (real)0));
 }
 
+// Slope limiter on the two one-sided differences a (left) and b (right):
+// LIM 0 minmod, 1 monotonised central (the central difference bounded by
+// twice each one-sided one; van Leer 1977), 2 van Leer's harmonic mean
+// 2ab/(a + b) (van Leer 1974); zero where a and b differ in sign.
+template <int LIM, typename real>
+__device__ __forceinline__ real limit(real a, real b) {
+  if constexpr (LIM == 0) {
+    return minmod(a, b);
+  } else if constexpr (LIM == 1) {
+    const real c = (real)0.5 * (a + b);
+    if (a > (real)0 && b > (real)0) return vmin(c, vmin((real)2 * a, (real)2 * b));
+    if (a < (real)0 && b < (real)0) return vmax(c, vmax((real)2 * a, (real)2 * b));
+    return (real)0;
+  } else {
+    if ((a > (real)0 && b > (real)0) || (a < (real)0 && b < (real)0))
+      return quot((real)2 * a * b, a + b);
+    return (real)0;
+  }
+}
+
 // PLM interface values between cells c-1 and c from q(c-2), q(c-1), q(c),
 // q(c+1)
-template <typename real>
+template <typename real, int LIM = 0>
 __device__ __forceinline__ void plm(real qm2, real qm1, real q0, real qp1, real& ql, real& qr) {
-  real dm1 = minmod(qm1 - qm2, q0 - qm1);
-  real d0 = minmod(q0 - qm1, qp1 - q0);
+  real dm1 = limit<LIM>(qm1 - qm2, q0 - qm1);
+  real d0 = limit<LIM>(q0 - qm1, qp1 - q0);
   ql = qm1 + (real)0.5 * dm1;
   qr = q0 - (real)0.5 * d0;
 }
@@ -351,7 +371,7 @@ __device__ __forceinline__ void plm(real qm2, real qm1, real q0, real qp1, real&
 // minmod slope is used.  The eigenvector entries are formed in a fixed
 // order and the projections are dense sums in index order, so FP64 results
 // are reproducible bit for bit.
-template <typename real>
+template <int LIM, typename real>
 __device__ __forceinline__ St7<real> char_slope(const St7<real>& qm, const St7<real>& q0,
                                                 const St7<real>& qp, real bn, real gamma) {
   real dm[7], dp[7];
@@ -436,7 +456,7 @@ __device__ __forceinline__ St7<real> char_slope(const St7<real>& qm, const St7<r
       cm = cm + L[k][v] * dm[v];
       cp = cp + L[k][v] * dp[v];
     }
-    ch[k] = minmod(cm, cp);
+    ch[k] = limit<LIM>(cm, cp);
   }
   R[0][0] = rho * af;  R[1][0] = -af * cf;  R[2][0] = qs * bey;  R[3][0] = qs * bez;
   R[4][0] = rho * af * a2;  R[5][0] = As * bey;  R[6][0] = As * bez;
@@ -461,7 +481,7 @@ __device__ __forceinline__ St7<real> char_slope(const St7<real>& qm, const St7<r
                   q0.v[4] + (real)0.5 * d.v[4] > (real)0 && q0.v[4] - (real)0.5 * d.v[4] > (real)0;
   if (!ok) {
 #pragma unroll
-    for (int v = 0; v < 7; v++) d.v[v] = minmod(dm[v], dp[v]);
+    for (int v = 0; v < 7; v++) d.v[v] = limit<LIM>(dm[v], dp[v]);
   }
   return d;
 }
@@ -740,12 +760,12 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
 }
 
 // PLM on the seven face-frame variables of a four-cell stencil
-template <typename real>
+template <int LIM, typename real>
 __device__ __forceinline__ void plm_face(const St7<real>& q0, const St7<real>& q1,
                                          const St7<real>& q2, const St7<real>& q3,
                                          St7<real>& wl, St7<real>& wr) {
 #pragma unroll
-  for (int v = 0; v < 7; v++) plm(q0.v[v], q1.v[v], q2.v[v], q3.v[v], wl.v[v], wr.v[v]);
+  for (int v = 0; v < 7; v++) plm<real, LIM>(q0.v[v], q1.v[v], q2.v[v], q3.v[v], wl.v[v], wr.v[v]);
 }
 
 __device__ __forceinline__ void count(unsigned long long* c, int fl) {
@@ -882,12 +902,14 @@ __device__ __forceinline__ void x_face(const XTile& x, int t, int& p, int& f, in
 // (stage 1, the state at the start of the step).
 // WPE: minimum resident wavefronts per SIMD the register allocation must
 // allow (1 = unconstrained); one of the tunable launch variants.  RS: the
-// Riemann solver (see riemann).  REC = 1: slopes limited in characteristic
+// Riemann solver (see riemann).  SL: slope kind, REC = SL & 1 and limiter
+// LIM = SL >> 1 (see limit); REC = 1: slopes limited in characteristic
 // fields (char_slope), computed once per staged cell into LDS rows 8-14
 // after the staging pass (row 7 holds the cell's normal field).
-template <typename real, int WPE, int RS, int REC>
+template <typename real, int WPE, int RS, int SL>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_x(
     Launch L) {
+  constexpr int REC = SL & 1, LIM = SL >> 1;
   __shared__ real sw[REC ? 15 : 7][kLdsCells];
   const int s = L.stage;
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -945,7 +967,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
               q0.v[v] = sw[v][sidx];
               qp.v[v] = sw[v][sidx + 1];
             }
-            const St7<real> d = char_slope(qm, q0, qp, sw[7][sidx], (real)b.gamma);
+            const St7<real> d = char_slope<LIM>(qm, q0, qp, sw[7][sidx], (real)b.gamma);
 #pragma unroll
             for (int v = 0; v < 7; v++) sw[8 + v][sidx] = d.v[v];
           }
@@ -969,7 +991,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
           for (int m = 0; m < 4; m++)
 #pragma unroll
             for (int v = 0; v < 7; v++) q[m].v[v] = sw[v][o + m];
-          plm_face(q[0], q[1], q[2], q[3], wl, wr);
+          plm_face<LIM>(q[0], q[1], q[2], q[3], wl, wr);
         }
         const int fi = fidx(b, 0, f, j, k);
         const real bn = (real)ld<double>(b.B[s][0], fi);
@@ -1049,14 +1071,16 @@ __device__ __forceinline__ double rk_combine(int kind, double uold, double usw, 
 // LW = 0 keeps it in registers; LW = 1 keeps it in a per-lane LDS column
 // (three slots of seven values, no sharing between lanes, so no barrier):
 // fewer registers live across the Riemann solve.
-// REC = 1 (registers only): slopes limited in characteristic fields; the
-// window also keeps the normal field of its newer cell, whose slope the next
-// face computes.
-template <typename real, int LW, int REC>
+// Register window (LW = 0) for any slope kind SL (REC = SL & 1, LIM =
+// SL >> 1): with REC = 1 the slopes are limited in characteristic fields
+// and the window also keeps the normal field of its newer cell, whose
+// slope the next face computes.  The LDS window (LW = 1) serves SL = 0.
+template <typename real, int LW, int SL>
 struct Window;
 
-template <typename real>
-struct Window<real, 0, 1> {
+template <typename real, int SL>
+struct Window<real, 0, SL> {
+  static constexpr int REC = SL & 1, LIM = SL >> 1;
   St7<real> q1, q2, dm1;
   real bn2;
   __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d,
@@ -1066,40 +1090,27 @@ struct Window<real, 0, 1> {
     dm1 = d;
     bn2 = bnb;
   }
+  // PLM states of the face between the window's cells given the next cell
+  // q3 (normal field bn3); then slides the window by one cell
   __device__ __forceinline__ void face_and_slide(const St7<real>& q3, real bn3, real gamma,
                                                  St7<real>& wl, St7<real>& wr) {
-    const St7<real> d0 = char_slope(q1, q2, q3, bn2, gamma);
+    if constexpr (REC) {
+      const St7<real> d0 = char_slope<LIM>(q1, q2, q3, bn2, gamma);
 #pragma unroll
-    for (int v = 0; v < 7; v++) {
-      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
-      wr.v[v] = q2.v[v] - (real)0.5 * d0.v[v];
-    }
-    dm1 = d0;
-    q1 = q2;
-    q2 = q3;
-    bn2 = bn3;
-  }
-};
-
-template <typename real>
-struct Window<real, 0, 0> {
-  St7<real> q1, q2, dm1;
-  __device__ __forceinline__ void init(const St7<real>& a, const St7<real>& b, const St7<real>& d,
-                                       real) {
-    q1 = a;
-    q2 = b;
-    dm1 = d;
-  }
-  // PLM states of the face between the window's cells given the next cell
-  // q3; then slides the window by one cell
-  __device__ __forceinline__ void face_and_slide(const St7<real>& q3, real, real, St7<real>& wl,
-                                                 St7<real>& wr) {
+      for (int v = 0; v < 7; v++) {
+        wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
+        wr.v[v] = q2.v[v] - (real)0.5 * d0.v[v];
+      }
+      dm1 = d0;
+      bn2 = bn3;
+    } else {
 #pragma unroll
-    for (int v = 0; v < 7; v++) {
-      const real d0 = minmod(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
-      wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
-      wr.v[v] = q2.v[v] - (real)0.5 * d0;
-      dm1.v[v] = d0;
+      for (int v = 0; v < 7; v++) {
+        const real d0 = limit<LIM>(q2.v[v] - q1.v[v], q3.v[v] - q2.v[v]);
+        wl.v[v] = q1.v[v] + (real)0.5 * dm1.v[v];
+        wr.v[v] = q2.v[v] - (real)0.5 * d0;
+        dm1.v[v] = d0;
+      }
     }
     q1 = q2;
     q2 = q3;
@@ -1143,7 +1154,7 @@ struct Window<real, 1, 0> {
 // the state the RK combine reads (U^n in stage 1, U* in stage 2), three
 // faces after the sweep loaded it, when it has usually left L2; the ring
 // saves that second fetch.
-template <typename real, int D, int PF, int LW, int CU, int RS, int FZ, int REC>
+template <typename real, int D, int PF, int LW, int CU, int RS, int FZ, int SL>
 __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, int i, int tr,
                                              int j0, int j1, real (*lds)[kTPB],
                                              double (*ring)[kTPB]) {
@@ -1157,7 +1168,8 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     const int am = map_cell(a, n, per);
     return D == 1 ? addr_of(b, i, am, tr) : addr_of(b, i, tr, am);
   };
-  Window<real, LW, REC> win;
+  constexpr int REC = SL & 1, LIM = SL >> 1;
+  Window<real, LW, SL> win;
   const real gam = (real)b.gamma;
   // cell-centred normal field of a primitive state (characteristic slopes)
   auto bnorm = [&](const PrimD& w) { return (real)(D == 1 ? w.by : w.bz); };
@@ -1183,10 +1195,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     }
     St7<real> dm1;
     if constexpr (REC) {
-      dm1 = char_slope(q0, q1, q2, bn1, gam);
+      dm1 = char_slope<LIM>(q0, q1, q2, bn1, gam);
     } else {
 #pragma unroll
-      for (int v = 0; v < 7; v++) dm1.v[v] = minmod(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
+      for (int v = 0; v < 7; v++) dm1.v[v] = limit<LIM>(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
     }
     win.init(q1, q2, dm1, bn2);
   }
@@ -1343,9 +1355,9 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int com
 // (latency hidden, more registers live across the solve); RS: the Riemann
 // solver (see riemann); FZ (y march only, every box with one cell along z
 // and more than one along y): the y march completes the stage, RK combine
-// and z-face data included, and no z march runs.  REC = 1: characteristic
-// slopes (register window only).
-template <typename real, int D, int WPE, int PF, int LW, int CU, int RS, int FZ, int REC>
+// and z-face data included, and no z march runs.  SL: slope kind (see
+// Window); kinds other than 0 use the register window.
+template <typename real, int D, int WPE, int PF, int LW, int CU, int RS, int FZ, int SL>
 __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_sweep_march(
     Launch L) {
   __shared__ real lds[LW ? 21 : 1][kTPB];
@@ -1370,7 +1382,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (b.act[D]) {
       const int j0 = seg * sl;
       const int j1 = min(j0 + sl, b.n[D]);
-      march_column<real, D, PF, LW, CU, RS, FZ, REC>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
+      march_column<real, D, PF, LW, CU, RS, FZ, SL>(b, L.stage, L.dst, L.comb, i, tr, j0, j1, lds, ring);
     } else {
       inactive_column<real, D>(b, L.stage, L.dst, L.comb, i, tr);
     }

@@ -36,6 +36,8 @@ using mhd::kTPB;
 
 // defined in mhd_fp32.hip (FP32 kernels of the mixed path)
 int mhd_enqueue_fp32(const mhd::StepCtx& sc);
+int mhd_enqueue_opt64(const mhd::StepCtx& sc);
+int mhd_enqueue_opt32(const mhd::StepCtx& sc);
 
 namespace {
 
@@ -142,6 +144,11 @@ int validate_config(const mhd_config* cfg, std::string& err) {
   }
   if (cfg->recon != MHD_REC_PRIM && cfg->recon != MHD_REC_CHAR) {
     err = "config: recon must be MHD_REC_PRIM or MHD_REC_CHAR";
+    return MHD_E_INVAL;
+  }
+  if (cfg->limiter != MHD_LIM_MINMOD && cfg->limiter != MHD_LIM_MC &&
+      cfg->limiter != MHD_LIM_VANLEER) {
+    err = "config: limiter must be MHD_LIM_MINMOD, MHD_LIM_MC or MHD_LIM_VANLEER";
     return MHD_E_INVAL;
   }
   if (cfg->ct_emf != MHD_EMF_CONTACT && cfg->ct_emf != MHD_EMF_E0 &&
@@ -262,7 +269,7 @@ struct mhd_ctx {
   int rk = 2;  // Runge-Kutta stages
   int rs = 0;  // Riemann solver (MHD_RS_*)
   int fz = 0;  // every box: one cell along z, more along y (no z march)
-  int rec = 0; // reconstruction (MHD_REC_*)
+  int sl = 0;  // slope kind: recon + 2 * limiter (MHD_REC_*, MHD_LIM_*)
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -330,14 +337,15 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.rk = c->rk;
   sc.rs = c->rs;
   sc.fz = c->fz;
-  sc.rec = c->rec;
+  sc.sl = c->sl;
   sc.xcd = c->var_xcd;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
   sc.ev = timing ? c->ev.data() : nullptr;
   sc.ev_kind = timing ? c->ev_kind.data() : nullptr;
-  const int slots = c->precision == MHD_FP64 ? mhd::enqueue_step_kernels<double>(sc)
-                                             : mhd_enqueue_fp32(sc);
+  const bool fp64 = c->precision == MHD_FP64;
+  const int slots = sc.sl == 0 ? (fp64 ? mhd::enqueue_step_sl<double, 0>(sc) : mhd_enqueue_fp32(sc))
+                               : (fp64 ? mhd_enqueue_opt64(sc) : mhd_enqueue_opt32(sc));
   HIPCHK(c, hipGetLastError());
   if (timing) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -732,7 +740,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->flags = cfg->flags;
   c->rk = cfg->rk_stages == 3 ? 3 : 2;
   c->rs = cfg->riemann;
-  c->rec = cfg->recon;
+  c->sl = cfg->recon + 2 * cfg->limiter;
   c->fz = 1;
   for (int b = 0; b < cfg->nboxes; b++)
     if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;

@@ -26,7 +26,9 @@ struct StepCtx {
   int var_x, var_m;    // launch variants of the x sweep and the marches
   int rk;              // Runge-Kutta stages: 2 or 3
   int rs;              // Riemann solver: 0 HLLD (HLL fallback), 1 HLL
-  int rec;             // slopes limited in 0 primitive, 1 characteristic variables
+  int sl;              // slope kind: reconstruction (0 primitive, 1
+                       // characteristic variables) + 2 * limiter (0 minmod,
+                       // 1 monotonised central, 2 van Leer)
   int fz;              // every box has one cell along z and more along y:
                        // the y march completes each stage, no z march
   int xcd;             // XCD-grouped tile order
@@ -35,11 +37,11 @@ struct StepCtx {
   int* ev_kind;        // timing: kernel kind of each pair
 };
 
-template <typename real, int RS, int REC>
+template <typename real, int RS, int SL>
 inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
-  if constexpr (REC) {
-    // characteristic slopes: one variant (unconstrained registers)
-    hipLaunchKernelGGL((k_sweep_x<real, 1, RS, 1>), g, dim3(kTPB), 0, st, L);
+  if constexpr (SL != 0) {
+    // other slope kinds: one variant (unconstrained registers)
+    hipLaunchKernelGGL((k_sweep_x<real, 1, RS, SL>), g, dim3(kTPB), 0, st, L);
     return;
   }
   switch (wpe) {
@@ -56,11 +58,11 @@ inline void launch_x(int wpe, dim3 g, hipStream_t st, const Launch& L) {
 // SIMD and no prefetch; 8, 9, 10 = variants 2, 6, 7 with the z march's
 // swept state kept in an LDS ring for the RK combine (the y march has no
 // combine and runs 2, 6, 7)
-template <typename real, int D, int RS, int FZ, int REC>
+template <typename real, int D, int RS, int FZ, int SL>
 inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
-  if constexpr (REC) {
-    // characteristic slopes: one variant (register window, no prefetch)
-    hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ, 1>), g, dim3(kTPB), 0, st, L);
+  if constexpr (SL != 0) {
+    // other slope kinds: one variant (register window, no prefetch)
+    hipLaunchKernelGGL((k_sweep_march<real, D, 1, 0, 0, 0, RS, FZ, SL>), g, dim3(kTPB), 0, st, L);
     return;
   }
   if (D == 1 && var >= 8) var = var == 8 ? 2 : var == 9 ? 6 : 7;
@@ -87,9 +89,10 @@ inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
   }
 }
 
-// Enqueues one step on sc.stream; returns the number of timed launches.
-template <typename real, int REC>
-inline int enqueue_step_rec(const StepCtx& sc) {
+// Enqueues one step on sc.stream with slope kind SL (reconstruction
+// SL & 1, limiter SL >> 1); returns the number of timed launches.
+template <typename real, int SL>
+inline int enqueue_step_sl(const StepCtx& sc) {
   Launch L = sc.L;
   L.xcd = sc.xcd;
   auto grid = [&](int kind) {
@@ -123,9 +126,9 @@ inline int enqueue_step_rec(const StepCtx& sc) {
     L.ntiles = sc.total[kXS];
     mark(MHD_K_SWEEP_X, true);
     if (sc.rs)
-      launch_x<real, 1, REC>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+      launch_x<real, 1, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
     else
-      launch_x<real, 0, REC>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+      launch_x<real, 0, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
     mark(MHD_K_SWEEP_X, false);
     L.lam = 0;
     if (s == 0) {
@@ -137,23 +140,23 @@ inline int enqueue_step_rec(const StepCtx& sc) {
     mark(MHD_K_SWEEP_Y, true);
     if (sc.fz) {
       if (sc.rs)
-        launch_march<real, 1, 1, 1, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 1, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
       else
-        launch_march<real, 1, 0, 1, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 0, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
     } else {
       if (sc.rs)
-        launch_march<real, 1, 1, 0, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 1, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
       else
-        launch_march<real, 1, 0, 0, REC>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march<real, 1, 0, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
     }
     mark(MHD_K_SWEEP_Y, false);
     if (!sc.fz) {
       L.ntiles = sc.total[kZS];
       mark(MHD_K_SWEEP_Z, true);
       if (sc.rs)
-        launch_march<real, 2, 1, 0, REC>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+        launch_march<real, 2, 1, 0, SL>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
       else
-        launch_march<real, 2, 0, 0, REC>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
+        launch_march<real, 2, 0, 0, SL>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
       mark(MHD_K_SWEEP_Z, false);
     }
     L.ntiles = sc.total[kCTE];
@@ -168,9 +171,17 @@ inline int enqueue_step_rec(const StepCtx& sc) {
   return slot;
 }
 
+// slope kinds other than the default (primitive variables, minmod); their
+// kernels are instantiated in translation units of their own
 template <typename real>
-inline int enqueue_step_kernels(const StepCtx& sc) {
-  return sc.rec ? enqueue_step_rec<real, 1>(sc) : enqueue_step_rec<real, 0>(sc);
+inline int enqueue_step_options(const StepCtx& sc) {
+  switch (sc.sl) {
+    case 1: return enqueue_step_sl<real, 1>(sc);
+    case 2: return enqueue_step_sl<real, 2>(sc);
+    case 3: return enqueue_step_sl<real, 3>(sc);
+    case 4: return enqueue_step_sl<real, 4>(sc);
+    default: return enqueue_step_sl<real, 5>(sc);
+  }
 }
 
 }  // namespace mhd

@@ -46,6 +46,10 @@ MHD_EMF_CONTACT = 0
 MHD_EMF_E0 = 1
 MHD_EMF_ARITH = 2
 EMFS = {"contact": MHD_EMF_CONTACT, "e0": MHD_EMF_E0, "arith": MHD_EMF_ARITH}
+MHD_LIM_MINMOD = 0
+MHD_LIM_MC = 1
+MHD_LIM_VANLEER = 2
+LIMITERS = {"minmod": MHD_LIM_MINMOD, "mc": MHD_LIM_MC, "vanleer": MHD_LIM_VANLEER}
 KERNELS = ["lambda", "dt", "sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 
 EXPORTED = [
@@ -87,6 +91,7 @@ class mhd_config(C.Structure):
         ("riemann", C.c_int32),
         ("recon", C.c_int32),
         ("ct_emf", C.c_int32),
+        ("limiter", C.c_int32),
     ]
 
 
@@ -145,7 +150,8 @@ def _box_struct(spec) -> mhd_box:
 
 def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
                 stream=None, workspace=None, workspace_bytes: int = 0, flags: int = 0,
-                rk: int = 2, solver: str = "hlld", recon: str = "prim", emf: str = "contact"):
+                rk: int = 2, solver: str = "hlld", recon: str = "prim", emf: str = "contact",
+                limiter: str = "minmod"):
     arr = (mhd_box * len(boxes))(*[_box_struct(s) for s in boxes])
     cfg = mhd_config()
     cfg.nboxes = len(boxes)
@@ -160,14 +166,15 @@ def make_config(boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0
     cfg.riemann = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     cfg.recon = RECONS[recon] if isinstance(recon, str) else int(recon)
     cfg.ct_emf = EMFS[emf] if isinstance(emf, str) else int(emf)
+    cfg.limiter = LIMITERS[limiter] if isinstance(limiter, str) else int(limiter)
     return cfg, arr  # keep arr alive with cfg
 
 
 def mhd_workspace_bytes(boxes, precision=MHD_FP64, flags=0, rk=2, solver="hlld",
-                        recon="prim", emf="contact") -> int:
+                        recon="prim", emf="contact", limiter="minmod") -> int:
     lib = load()
     cfg, _keep = make_config(boxes, precision, flags=flags, rk=rk, solver=solver, recon=recon,
-                             emf=emf)
+                             emf=emf, limiter=limiter)
     out = C.c_uint64()
     rc = lib.mhd_workspace_bytes(C.byref(cfg), C.byref(out))
     if rc != MHD_OK:
@@ -184,7 +191,8 @@ class Sim:
 
     def __init__(self, boxes: Sequence, precision: int = MHD_FP64, p_floor: float = 0.0,
                  stream=None, workspace=None, flags: int = 0, rk: int = 2,
-                 solver: str = "hlld", recon: str = "prim", emf: str = "contact"):
+                 solver: str = "hlld", recon: str = "prim", emf: str = "contact",
+                 limiter: str = "minmod"):
         self._lib = load()
         self.boxes = list(boxes)
         self._h = None
@@ -193,7 +201,7 @@ class Sim:
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         self._workspace = workspace
         cfg, self._keep = make_config(self.boxes, precision, p_floor, stream, ws_ptr, ws_bytes,
-                                      flags, rk, solver, recon, emf)
+                                      flags, rk, solver, recon, emf, limiter)
         h = C.c_void_p()
         rc = self._lib.mhd_create(C.byref(cfg), C.byref(h))
         if rc != MHD_OK:

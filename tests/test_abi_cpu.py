@@ -46,11 +46,12 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mhd_box), offsetof(mhd_box, lo),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mhd_box), offsetof(mhd_box, lo),
          offsetof(mhd_box, bc_lo), offsetof(mhd_box, gamma), sizeof(mhd_config),
          offsetof(mhd_config, stream), offsetof(mhd_config, flags),
          offsetof(mhd_config, rk_stages), offsetof(mhd_config, riemann),
-         offsetof(mhd_config, recon), offsetof(mhd_config, ct_emf));
+         offsetof(mhd_config, recon), offsetof(mhd_config, ct_emf),
+         offsetof(mhd_config, limiter));
   return 0;
 }}''')
     exe = tmp_path / "layout"
@@ -62,7 +63,7 @@ int main(void) {{
            mhd.mhd_box.gamma.offset, C.sizeof(mhd.mhd_config), mhd.mhd_config.stream.offset,
            mhd.mhd_config.flags.offset, mhd.mhd_config.rk_stages.offset,
            mhd.mhd_config.riemann.offset, mhd.mhd_config.recon.offset,
-           mhd.mhd_config.ct_emf.offset]
+           mhd.mhd_config.ct_emf.offset, mhd.mhd_config.limiter.offset]
     assert vals == got
 
 
@@ -94,7 +95,7 @@ def test_validation_before_device(lib):
     with pytest.raises(mhd.MhdError) as ei:
         mhd.mhd_workspace_bytes([])
     assert ei.value.code == mhd.MHD_E_INVAL
-    for kw in ({"rk": 4}, {"solver": 2}, {"recon": 2}, {"emf": 3}):
+    for kw in ({"rk": 4}, {"solver": 2}, {"recon": 2}, {"emf": 3}, {"limiter": 3}):
         with pytest.raises(mhd.MhdError) as ei:
             mhd.mhd_workspace_bytes([good], **kw)
         assert ei.value.code == mhd.MHD_E_INVAL, kw

@@ -39,12 +39,12 @@ def rel_l1(a, b):
 
 
 def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2,
-            solver="hlld", recon="prim", emf="contact"):
+            solver="hlld", recon="prim", emf="contact", limiter="minmod"):
     idx = range(len(wl.boxes)) if boxes is None else boxes
     specs = [wl.boxes[i] for i in idx]
     out = []
     with mhd.Sim(specs, precision=precision, flags=flags, rk=rk, solver=solver,
-                 recon=recon, emf=emf) as sim:
+                 recon=recon, emf=emf, limiter=limiter) as sim:
         for k, i in enumerate(idx):
             st = wl.states[i]
             sim.set_state(k, st.cons, st.bface, st.t)
@@ -55,8 +55,9 @@ def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None,
     return out
 
 
-def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim", emf="contact"):
-    b = O.OracleBox(spec, rk=rk, solver=solver, recon=recon, emf=emf)
+def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim", emf="contact",
+               limiter="minmod"):
+    b = O.OracleBox(spec, rk=rk, solver=solver, recon=recon, emf=emf, limiter=limiter)
     b.set_state(st.cons, st.bface, st.t)
     b.step(nsteps, t_stop)
     cons, bface, t = b.get_state()
@@ -228,6 +229,36 @@ def test_corner_emf_kinds_fp64(n, bc, recon, emf):
     g = gpu_run(wl, 4, flags=mhd.MHD_F_GRAPH, recon=recon, emf=emf)[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, recon=recon, emf=emf)
     assert_fp64_parity(g, o, f"emf {emf} {n} {bc}")
+
+
+@pytest.mark.parametrize("limiter", ["mc", "vanleer"])
+@pytest.mark.parametrize("recon", ["prim", "char"])
+@pytest.mark.parametrize("n,bc", [((30, 26, 22), (1, 0, 0)), ((24, 20, 1), (0, 1, 0))])
+def test_limiters_fp64(n, bc, recon, limiter):
+    """MC and van Leer limiters, primitive and characteristic slopes: bit
+    for bit with the oracle (3D and 2D)."""
+    wl = W.random_smooth(n=n, seed=sum(n) + len(limiter), bc=bc)
+    g = gpu_run(wl, 4, flags=mhd.MHD_F_GRAPH, recon=recon, limiter=limiter)[0]
+    o = oracle_run(wl.boxes[0], wl.states[0], 4, recon=recon, limiter=limiter)
+    assert_fp64_parity(g, o, f"{limiter} {recon} {n}")
+
+
+def test_limiters_shocks_and_mixed():
+    """Through shocks (Orszag-Tang 2D, 50 steps) bit for bit; the mixed
+    path within its bar."""
+    wl = W.orszag_tang_2d(n=64)
+    spec = wl.boxes[0]
+    for limiter, recon in (("mc", "prim"), ("vanleer", "char")):
+        o = oracle_run(spec, wl.states[0], 50, recon=recon, limiter=limiter)
+        g = gpu_run(wl, 50, flags=mhd.MHD_F_GRAPH, recon=recon, limiter=limiter)[0]
+        assert_fp64_parity(g, o, f"OT2D {limiter} {recon}")
+        m = gpu_run(wl, 50, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, recon=recon,
+                    limiter=limiter)[0]
+        mp, mb = pressure_bmag(spec, m[0], m[1])
+        op, ob = pressure_bmag(spec, o[0], o[1])
+        for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+            assert rel_l1(a, b) <= TOLMIX, (limiter, name)
+        assert divb_norm(spec, m[1])[0] <= 1e-12
 
 
 def test_corner_emf_kinds_orszag_tang_and_mixed():
