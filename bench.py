@@ -133,11 +133,12 @@ def source_sha() -> str:
 
 def kernel_name(kind, real, variant):
     """Demangled name of the kernel a launch variant runs for a kernel kind
-    (x sweep: waves per SIMD; marches: waves per SIMD, prefetch, LDS window,
-    LDS ring of the z march)."""
+    on the benchmark input (x sweep: waves per SIMD; marches: waves per SIMD,
+    prefetch, LDS window, LDS ring of the z march; then HLLD, no fused y
+    march, primitive minmod slopes)."""
     x, m = variant[0], variant[1]
     if kind == "sweep_x":
-        return f"mhd::k_sweep_x<{real}, {x}>"
+        return f"mhd::k_sweep_x<{real}, {x}, 0, 0>"
     if kind in ("sweep_y", "sweep_z"):
         d = 1 if kind == "sweep_y" else 2
         if d == 1 and m >= 8:
@@ -145,7 +146,7 @@ def kernel_name(kind, real, variant):
         wpe, pf, lw, cu = {1: (1, 1, 0, 0), 2: (1, 0, 0, 0), 3: (3, 0, 0, 0), 4: (4, 0, 0, 0),
                            5: (1, 1, 1, 0), 6: (1, 0, 1, 0), 7: (3, 0, 1, 0), 8: (1, 0, 0, 1),
                            9: (1, 0, 1, 1), 10: (3, 0, 1, 1)}[m]
-        return f"mhd::k_sweep_march<{real}, {d}, {wpe}, {pf}, {lw}, {cu}>"
+        return f"mhd::k_sweep_march<{real}, {d}, {wpe}, {pf}, {lw}, {cu}, 0, 0, 0>"
     return f"mhd::k_{kind}<{real}>"
 
 
