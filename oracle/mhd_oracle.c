@@ -52,6 +52,9 @@
 #include "mhd_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -817,8 +820,10 @@ static void fill_cells_axis(orc_box *b, double *arr, int a) {
     lo[d] = -NG;
     hi[d] = b->n[d] + NG; /* exclusive; includes the extra face slot */
   }
-  int pos[3];
-  for (pos[2] = lo[2]; pos[2] < hi[2]; pos[2]++)
+#pragma omp parallel for schedule(static)
+  for (int k = lo[2]; k < hi[2]; k++) {
+    int pos[3];
+    pos[2] = k;
     for (pos[1] = lo[1]; pos[1] < hi[1]; pos[1]++)
       for (pos[0] = lo[0]; pos[0] < hi[0]; pos[0]++) {
         int p = pos[a];
@@ -827,6 +832,7 @@ static void fill_cells_axis(orc_box *b, double *arr, int a) {
         src[a] = ghost_src(b, a, p);
         arr[IXp(b, pos)] = arr[IXp(b, src)];
       }
+  }
 }
 
 /* Fill ghost faces of the normal field B_a along its own axis: periodic wrap
@@ -839,9 +845,11 @@ static void fill_faces_normal(orc_box *b, double *arr, int a) {
     hi[d] = b->n[d] + NG;
   }
   hi[a] = b->n[a] + NG + 1;
-  int pos[3];
   int n = b->n[a];
-  for (pos[2] = lo[2]; pos[2] < hi[2]; pos[2]++)
+#pragma omp parallel for schedule(static)
+  for (int k = lo[2]; k < hi[2]; k++) {
+    int pos[3];
+    pos[2] = k;
     for (pos[1] = lo[1]; pos[1] < hi[1]; pos[1]++)
       for (pos[0] = lo[0]; pos[0] < hi[0]; pos[0]++) {
         int p = pos[a];
@@ -857,15 +865,17 @@ static void fill_faces_normal(orc_box *b, double *arr, int a) {
           arr[IXp(b, pos)] = NAN;
         }
       }
+  }
 }
 
 /* Stage-start preparation: cell-centred field, ghost cells, primitives and
  * cell EMFs over the whole padded domain. */
 static void prepare(orc_box *b) {
-  int i, j, k, q, a, d;
-  for (k = 0; k < b->n[2]; k++)
-    for (j = 0; j < b->n[1]; j++)
-      for (i = 0; i < b->n[0]; i++) {
+  int q, a, d;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < b->n[2]; k++)
+    for (int j = 0; j < b->n[1]; j++)
+      for (int i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
         b->Bc[0][c] = 0.5 * (b->B[0][c] + b->B[0][IX(b, i + 1, j, k)]);
         b->Bc[1][c] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i, j + 1, k)]);
@@ -884,24 +894,28 @@ static void prepare(orc_box *b) {
   /* primitives and cell EMF everywhere (ghosts hold copies, so their
    * primitives equal those of their source cells); counters on interior
    * cells only */
-  for (k = -NG; k < b->n[2] + NG; k++)
-    for (j = -NG; j < b->n[1] + NG; j++)
-      for (i = -NG; i < b->n[0] + NG; i++) {
+  long long nfloor = 0, nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nfloor, nbad)
+  for (int k = -NG; k < b->n[2] + NG; k++)
+    for (int j = -NG; j < b->n[1] + NG; j++)
+      for (int i = -NG; i < b->n[0] + NG; i++) {
         size_t c = IX(b, i, j, k);
         double u[5], bcv[3], w[8];
-        for (q = 0; q < NQ; q++) u[q] = b->U[q][c];
-        for (d = 0; d < 3; d++) bcv[d] = b->Bc[d][c];
+        for (int m = 0; m < NQ; m++) u[m] = b->U[m][c];
+        for (int e = 0; e < 3; e++) bcv[e] = b->Bc[e][c];
         int fl = orc_cons_to_prim(u, bcv, b->gamma, b->pfloor, w);
         if (i >= 0 && i < b->n[0] && j >= 0 && j < b->n[1] && k >= 0 && k < b->n[2]) {
-          if (fl & 1) b->nfloor++;
-          if (fl & 2) b->nbad++;
+          if (fl & 1) nfloor++;
+          if (fl & 2) nbad++;
         }
-        for (q = 0; q < 8; q++) b->W[q][c] = w[q];
+        for (int m = 0; m < 8; m++) b->W[m][c] = w[m];
         /* E = -v x B */
         b->Ec[0][c] = w[3] * w[6] - w[2] * w[7];
         b->Ec[1][c] = w[1] * w[7] - w[3] * w[5];
         b->Ec[2][c] = w[2] * w[5] - w[1] * w[6];
       }
+  b->nfloor += nfloor;
+  b->nbad += nbad;
 }
 
 /* Face fluxes along direction d for faces 0..n_d and transverse cells
@@ -918,8 +932,11 @@ static void sweep(orc_box *b, int d) {
   }
   lo[d] = 0;
   hi[d] = b->n[d] + 1; /* faces 0..n_d */
-  int pos[3];
-  for (pos[2] = lo[2]; pos[2] < hi[2]; pos[2]++)
+  long long nhll = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nhll)
+  for (int k = lo[2]; k < hi[2]; k++) {
+    int pos[3];
+    pos[2] = k;
     for (pos[1] = lo[1]; pos[1] < hi[1]; pos[1]++)
       for (pos[0] = lo[0]; pos[0] < hi[0]; pos[0]++) {
         size_t fidx = IXp(b, pos);
@@ -972,15 +989,15 @@ static void sweep(orc_box *b, int d) {
         }
         /* count each distinct interior face once */
         int interior = 1;
-        for (a = 0; a < 3; a++) {
-          if (a == d) {
+        for (int e = 0; e < 3; e++) {
+          if (e == d) {
             int nf = b->bc[d] == ORC_BC_PERIODIC ? b->n[d] : b->n[d] + 1;
-            if (pos[a] >= nf) interior = 0;
-          } else if (pos[a] < 0 || pos[a] >= b->n[a]) {
+            if (pos[e] >= nf) interior = 0;
+          } else if (pos[e] < 0 || pos[e] >= b->n[e]) {
             interior = 0;
           }
         }
-        if (used_hll && interior) b->nhll++;
+        if (used_hll && interior) nhll++;
         b->FH[d][0][fidx] = f[0];
         b->FH[d][1 + d][fidx] = f[1];
         b->FH[d][1 + t1][fidx] = f[2];
@@ -991,17 +1008,21 @@ static void sweep(orc_box *b, int d) {
         b->EF[d][t2][fidx] = -f[5];
         b->FM[d][fidx] = fm;
       }
+  }
+  b->nhll += nhll;
 }
 
 /* corner EMFs along c at a-faces 0..n_a, b-faces 0..n_b, c cells 0..n_c-1 */
 static void corner_emfs(orc_box *b, int c) {
   int a = (c + 1) % 3, bb = (c + 2) % 3;
-  int pos[3];
   int lo[3] = {0, 0, 0}, hi[3];
   hi[a] = b->n[a] + 1;
   hi[bb] = b->n[bb] + 1;
   hi[c] = b->n[c];
-  for (pos[2] = lo[2]; pos[2] < hi[2]; pos[2]++)
+#pragma omp parallel for schedule(static)
+  for (int k = lo[2]; k < hi[2]; k++) {
+    int pos[3];
+    pos[2] = k;
     for (pos[1] = lo[1]; pos[1] < hi[1]; pos[1]++)
       for (pos[0] = lo[0]; pos[0] < hi[0]; pos[0]++) {
         int pa[3] = {pos[0], pos[1], pos[2]}; /* a-face (ia, ib-1) */
@@ -1023,35 +1044,39 @@ static void corner_emfs(orc_box *b, int c) {
         b->ED[c][i11] = orc_ct_corner_kind(b->emf, fa1, fa0, fb1, fb0, ec, b->FM[a][i11],
                                            b->FM[a][ia0], b->FM[bb][i11], b->FM[bb][ib0]);
       }
+  }
 }
 
 /* Stage operator: R (interior cells) and RB (faces). */
 static void stage_operator(orc_box *b) {
-  int i, j, k, q, d;
+  int d;
   prepare(b);
   for (d = 0; d < 3; d++) sweep(b, d);
-  for (k = 0; k < b->n[2]; k++)
-    for (j = 0; j < b->n[1]; j++)
-      for (i = 0; i < b->n[0]; i++) {
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < b->n[2]; k++)
+    for (int j = 0; j < b->n[1]; j++)
+      for (int i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
         size_t up[3] = {IX(b, i + 1, j, k), IX(b, i, j + 1, k), IX(b, i, j, k + 1)};
-        for (q = 0; q < NQ; q++) {
+        for (int m = 0; m < NQ; m++) {
           double r = 0.0;
-          for (d = 0; d < 3; d++) {
-            if (!b->active[d]) continue;
-            r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];
+          for (int e = 0; e < 3; e++) {
+            if (!b->active[e]) continue;
+            r = r - (b->FH[e][m][up[e]] - b->FH[e][m][c]) * b->idx[e];
           }
-          b->R[q][c] = r;
+          b->R[m][c] = r;
         }
       }
   for (d = 0; d < 3; d++) corner_emfs(b, d);
   /* face rate: dB_d/dt = -[(E_f(e+1/2)-E_f(e-1/2))/dx_e - (E_e(f+1/2)-E_e(f-1/2))/dx_f] */
   for (d = 0; d < 3; d++) {
     int e = (d + 1) % 3, f = (d + 2) % 3;
-    int pos[3];
     int hi[3] = {b->n[0], b->n[1], b->n[2]};
     hi[d] = b->n[d] + 1;
-    for (pos[2] = 0; pos[2] < hi[2]; pos[2]++)
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < hi[2]; k++) {
+      int pos[3];
+      pos[2] = k;
       for (pos[1] = 0; pos[1] < hi[1]; pos[1]++)
         for (pos[0] = 0; pos[0] < hi[0]; pos[0]++) {
           int pe[3] = {pos[0], pos[1], pos[2]};
@@ -1064,23 +1089,25 @@ static void stage_operator(orc_box *b) {
           if (b->active[f]) t2 = (b->ED[e][IXp(b, pf)] - b->ED[e][c0]) * b->idx[f];
           b->RB[d][c0] = -(t1 - t2);
         }
+    }
   }
 }
 
 double orc_dt(orc_box *b) {
-  int i, j, k, d, q;
   double lmax = 0.0;
-  for (k = 0; k < b->n[2]; k++)
-    for (j = 0; j < b->n[1]; j++)
-      for (i = 0; i < b->n[0]; i++) {
+  /* the maximum is independent of the order of the cells */
+#pragma omp parallel for schedule(static) reduction(max : lmax)
+  for (int k = 0; k < b->n[2]; k++)
+    for (int j = 0; j < b->n[1]; j++)
+      for (int i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
         double u[5], bcv[3], w[8];
-        for (q = 0; q < NQ; q++) u[q] = b->U[q][c];
+        for (int q = 0; q < NQ; q++) u[q] = b->U[q][c];
         bcv[0] = 0.5 * (b->B[0][c] + b->B[0][IX(b, i + 1, j, k)]);
         bcv[1] = 0.5 * (b->B[1][c] + b->B[1][IX(b, i, j + 1, k)]);
         bcv[2] = 0.5 * (b->B[2][c] + b->B[2][IX(b, i, j, k + 1)]);
         orc_cons_to_prim(u, bcv, b->gamma, b->pfloor, w);
-        for (d = 0; d < 3; d++) {
+        for (int d = 0; d < 3; d++) {
           if (!b->active[d]) continue;
           int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
           double cf = orc_fast_speed(w[0], w[4], w[5 + d], w[5 + t1], w[5 + t2], b->gamma);
@@ -1110,19 +1137,21 @@ static double combine(int kind, double u0, double u, double dtl) {
 }
 
 static void stage_update(orc_box *b, double dt, int kind) {
-  int i, j, k, q, d;
-  for (k = 0; k < b->n[2]; k++)
-    for (j = 0; j < b->n[1]; j++)
-      for (i = 0; i < b->n[0]; i++) {
+  int d;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < b->n[2]; k++)
+    for (int j = 0; j < b->n[1]; j++)
+      for (int i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
-        for (q = 0; q < NQ; q++)
+        for (int q = 0; q < NQ; q++)
           b->U[q][c] = combine(kind, b->U0[q][c], b->U[q][c], dt * b->R[q][c]);
       }
   for (d = 0; d < 3; d++) {
     int ex = b->n[0] + (d == 0), ey = b->n[1] + (d == 1), ez = b->n[2] + (d == 2);
-    for (k = 0; k < ez; k++)
-      for (j = 0; j < ey; j++)
-        for (i = 0; i < ex; i++) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < ez; k++)
+      for (int j = 0; j < ey; j++)
+        for (int i = 0; i < ex; i++) {
           size_t c = IX(b, i, j, k);
           b->B[d][c] = combine(kind, b->B0[d][c], b->B[d][c], dt * b->RB[d][c]);
         }
@@ -1155,6 +1184,16 @@ int orc_set_rk(orc_box *b, int stages) {
   if (stages != 2 && stages != 3) return -1;
   b->rk = stages;
   return 0;
+}
+
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 int orc_set_limiter(orc_box *b, int lim) {
@@ -1210,11 +1249,11 @@ void orc_rhs(orc_box *b, double *const R[5], double *const rB[3]) {
 }
 
 double orc_divb_max(const orc_box *b) {
-  int i, j, k;
   double m = 0.0;
-  for (k = 0; k < b->n[2]; k++)
-    for (j = 0; j < b->n[1]; j++)
-      for (i = 0; i < b->n[0]; i++) {
+#pragma omp parallel for schedule(static) reduction(max : m)
+  for (int k = 0; k < b->n[2]; k++)
+    for (int j = 0; j < b->n[1]; j++)
+      for (int i = 0; i < b->n[0]; i++) {
         size_t c = IX(b, i, j, k);
         double dv = (b->B[0][IX(b, i + 1, j, k)] - b->B[0][c]) / b->dx[0] +
                     (b->B[1][IX(b, i, j + 1, k)] - b->B[1][c]) / b->dx[1] +

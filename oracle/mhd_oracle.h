@@ -48,6 +48,12 @@ void orc_get_state(const orc_box *b, double *const cons[5],
  * SSP-RK3) with the CFL time step of each step's starting state (clamped to
  * t_stop - t when t_stop > 0). */
 void orc_step(orc_box *b, int nsteps, double t_stop);
+/* Threads of the cell and face loops (OpenMP; each output element is
+ * computed by one thread in the serial order of its own terms, counters are
+ * integer sums and the time step a maximum, so results are identical for any
+ * count).  n > 0 sets the count; returns the count in use (1 without
+ * OpenMP). */
+int orc_threads(int n);
 /* Integrator: 2 (SSP-RK2, the default) or 3 (SSP-RK3) stages; -1 otherwise. */
 int orc_set_rk(orc_box *b, int stages);
 /* Riemann solver of every face: ORC_HLLD (the default; HLL where the HLLD

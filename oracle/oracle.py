@@ -64,6 +64,8 @@ def _lib():
         lib.orc_set_limiter.restype = C.c_int
         lib.orc_limit.argtypes = [C.c_int, C.c_double, C.c_double]
         lib.orc_limit.restype = C.c_double
+        lib.orc_threads.argtypes = [C.c_int]
+        lib.orc_threads.restype = C.c_int
         lib.orc_dt.argtypes = [C.c_void_p]
         lib.orc_dt.restype = C.c_double
         lib.orc_rhs.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp)]
@@ -248,6 +250,52 @@ def limit(a, b, limiter="minmod"):
     return _lib().orc_limit(LIMITERS[limiter], a, b)
 
 
+def threads(n: int = 0) -> int:
+    """Sets the oracle's thread count (n > 0); returns the count in use."""
+    return _lib().orc_threads(int(n))
+
+
+_TAG = b"MHDSTAT1"
+
+
+def write_state(path, spec, cons, bface, t=0.0):
+    """One box in the command-line oracle's state file (boundary layout)."""
+    with open(path, "wb") as fh:
+        fh.write(_TAG)
+        fh.write(np.asarray(spec.n, dtype="<i4").tobytes())
+        fh.write(np.asarray(spec.lo, dtype="<f8").tobytes())
+        fh.write(np.asarray(spec.hi, dtype="<f8").tobytes())
+        fh.write(np.asarray(spec.bc, dtype="<i4").tobytes())
+        fh.write(np.asarray([spec.gamma, spec.cfl, t], dtype="<f8").tobytes())
+        for a in list(cons) + list(bface):
+            fh.write(np.ascontiguousarray(a, dtype="<f8").tobytes())
+
+
+def read_state(path):
+    """(n, lo, hi, bc, gamma, cfl, t, cons, bface) of a state file."""
+    with open(path, "rb") as fh:
+        raw = fh.read()
+    if raw[:8] != _TAG:
+        raise ValueError("not a state file")
+    o = 8
+    n = tuple(int(v) for v in np.frombuffer(raw, "<i4", 3, o)); o += 12
+    lo = tuple(np.frombuffer(raw, "<f8", 3, o)); o += 24
+    hi = tuple(np.frombuffer(raw, "<f8", 3, o)); o += 24
+    bc = tuple(int(v) for v in np.frombuffer(raw, "<i4", 3, o)); o += 12
+    gamma, cfl, t = np.frombuffer(raw, "<f8", 3, o); o += 24
+    nx, ny, nz = n
+    cons = []
+    for _ in range(5):
+        cons.append(np.frombuffer(raw, "<f8", nx * ny * nz, o).reshape(nz, ny, nx).copy())
+        o += 8 * nx * ny * nz
+    bface = []
+    for shp in ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)):
+        cnt = shp[0] * shp[1] * shp[2]
+        bface.append(np.frombuffer(raw, "<f8", cnt, o).reshape(shp).copy())
+        o += 8 * cnt
+    return n, lo, hi, bc, float(gamma), float(cfl), float(t), cons, bface
+
+
 def phys_flux(w, bn, gamma):
     w = _vec(w, 7)
     f = np.empty(7)
@@ -286,5 +334,6 @@ def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0, kind="contact"):
 
 __all__ = [
     "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
-    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "limit", "SOLVERS", "RECONS", "EMFS", "LIMITERS",
+    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "limit", "threads", "write_state", "read_state", "SOLVERS", "RECONS",
+    "EMFS", "LIMITERS",
 ]

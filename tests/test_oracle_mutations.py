@@ -45,8 +45,8 @@ MUTATIONS = [
     ("rk3_third_weights", "default: return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (u + dtl);",
      "default: return 0.5 * u0 + 0.5 * (u + dtl);",
      "test_oracle_scheme.py::test_rk_temporal_order"),
-    ("divergence_sign", "r = r - (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];",
-     "r = r + (b->FH[d][q][up[d]] - b->FH[d][q][c]) * b->idx[d];",
+    ("divergence_sign", "r = r - (b->FH[e][m][up[e]] - b->FH[e][m][c]) * b->idx[e];",
+     "r = r + (b->FH[e][m][up[e]] - b->FH[e][m][c]) * b->idx[e];",
      "test_oracle_scheme.py::test_sod_shock_tube_against_exact"),
     ("dt_ignores_velocity", "double l = (fabs(w[1 + d]) + cf) * b->idx[d];",
      "double l = cf * b->idx[d];",
