@@ -74,8 +74,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variant")
-    ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-n", type=int, default=256, help="cells per axis of the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="steps of the CPU sample")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads of the CPU oracle (the box's CPU share is 16)")
     ap.add_argument("--accuracy", action="store_true")
     ap.add_argument("--options", action="store_true",
                     help="the scheme options (RK3, HLL, characteristic slopes) on the benchmark input")
@@ -355,22 +357,27 @@ def compare(spec, st64, stmx):
             "max_divB_norm": {"fp64": n64, "mixed": nmx}}
 
 
-def cpu_baseline(n, steps):
+def cpu_baseline(n, steps, threads):
+    """The oracle as it is (FP64, OpenMP over its cell and face loops) on a
+    bounded sample of the benchmark input: `steps` steps of the blast recipe
+    on n^3 cells with `threads` host threads."""
     import oracle
     from paper_2606_12753_amd import workloads
     wl = workloads.blast_3d(n=n)
+    used = oracle.threads(threads)
     ob = oracle.OracleBox(wl.boxes[0])
     ob.set_state(wl.states[0].cons, wl.states[0].bface)
     t0 = time.perf_counter()
     ob.step(steps)
     el = time.perf_counter() - t0
+    ob.close()
     return {
         "value": round(wl.cells * steps / el / 1e6, 4),
         "unit": "Mcell-updates/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": f"blast recipe at {n}^3 (same seed and set-up, smaller grid), {steps} steps, "
-                  f"serial FP64 oracle, {el:.1f} s",
+        "sample": f"blast recipe at {n}^3 ({'the benchmark input' if n == 256 else 'same seed and set-up'}), "
+                  f"{steps} steps, FP64 oracle on {used} host threads, {el:.1f} s",
     }
 
 
@@ -753,7 +760,7 @@ def main():
     cpu = None
     if not a.no_cpu:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(a.cpu_n, a.cpu_steps)
+        cpu = cpu_baseline(a.cpu_n, a.cpu_steps, a.cpu_threads)
     line = {
         "metric": "Mcell-updates/s, FP64 vs mixed FP32 at stated L1 error; % HBM/FP64 roofline",
         "value": round(value, 2),

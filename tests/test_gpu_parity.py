@@ -605,6 +605,22 @@ def test_blast_256_full_size_sampled():
     _check_sampled(spec, st, cons, bface, dt_gpu, centres)
 
 
+def test_blast_256_full_size_full_state():
+    """The benchmark workload at full size (256^3) over 20 steps in the
+    benchmark's launch configuration (graph replay, autotuned variant):
+    every cell and face value, the time and the event counters equal the
+    threaded oracle's bit for bit."""
+    import os
+    wl = W.blast_3d(n=256)
+    spec, st = wl.boxes[0], wl.states[0]
+    g = gpu_run(wl, 20, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE)[0]
+    O.threads(min(16, os.cpu_count() or 1))
+    o = oracle_run(spec, st, 20)
+    assert_fp64_parity(g, o, "blast 256 x 20")
+    for a, b in zip(g[0] + g[1], o[0] + o[1]):
+        assert np.array_equal(a, b)
+
+
 def test_orszag_tang_352_rk3_full_size_sampled():
     """The paper's profiled case, 3D Orszag-Tang on 352^3 cells with SSP-RK3,
     at full size with graph replay and the autotuned launch variant: one step
