@@ -621,6 +621,33 @@ def test_blast_256_full_size_full_state():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["orszag_tang_3d", "riemann_2d", "kelvin_helmholtz", "ensemble"])
+def test_full_size_full_state(case):
+    """Full-size workloads over a few steps with graph replay and the
+    autotuned variant, every cell and face of every box bit for bit with
+    the threaded oracle: the paper's 352^3 Orszag-Tang case (SSP-RK3, 3
+    steps), its 3200^2 Riemann case (HLL, SSP-RK3, 4 steps), the
+    768 x 384 x 384 shear layer with outflow walls (2 steps) and the
+    96-box ensemble (2 steps, persistent grid)."""
+    import os
+    wl = {"orszag_tang_3d": lambda: W.orszag_tang_3d(n=352),
+          "riemann_2d": lambda: W.riemann_2d(n=3200),
+          "kelvin_helmholtz": W.kelvin_helmholtz,
+          "ensemble": W.ensemble}[case]()
+    steps = {"orszag_tang_3d": 3, "riemann_2d": 4}.get(case, 2)
+    kw = {k: v for k, v in wl.meta.items() if k in ("rk", "solver")}
+    flags = mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE
+    if case == "ensemble":
+        flags |= mhd.MHD_F_PERSISTENT
+    res = gpu_run(wl, steps, flags=flags, **kw)
+    O.threads(min(16, os.cpu_count() or 1))
+    for b, g in enumerate(res):
+        o = oracle_run(wl.boxes[b], wl.states[b], steps, **kw)
+        assert_fp64_parity(g, o, f"{case} box {b}")
+        for x, y in zip(g[0] + g[1], o[0] + o[1]):
+            assert np.array_equal(x, y), (case, b)
+
+
 def test_orszag_tang_352_rk3_full_size_sampled():
     """The paper's profiled case, 3D Orszag-Tang on 352^3 cells with SSP-RK3,
     at full size with graph replay and the autotuned launch variant: one step
