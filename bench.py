@@ -101,6 +101,8 @@ def parse():
                     help="write the kernel-trace summary from a rocprofv3 --kernel-trace "
                          "--stats run of this script")
     ap.add_argument("--trace-command", default="", help="command of the kernel-trace run")
+    ap.add_argument("--trace-out", default="kernel_trace_paper_cases.md",
+                    help="file under profiles/ for the summary of a run without a bench line")
     return ap.parse_args()
 
 
@@ -495,12 +497,17 @@ def summarize_trace(a):
     import csv
     tdir, log = a.summarize_trace
     bench = None
+    cases = []
     with open(log) as fh:
         for line in fh:
             if line.startswith('{"metric"'):
                 bench = json.loads(line)
+            elif line.startswith('{"workload"'):
+                cases.append(json.loads(line))
     if bench is None:
-        raise SystemExit(f"bench.py: no bench line in {log}")
+        if not cases:
+            raise SystemExit(f"bench.py: no bench or workload line in {log}")
+        return summarize_case_trace(a, tdir, cases)
     stats = []
     with open(os.path.join(tdir, "run_kernel_stats.csv"), newline="") as fh:
         for r in csv.DictReader(fh):
@@ -541,6 +548,34 @@ def summarize_trace(a):
         lines.append(f"| {key} | `{want}` | {grid} | {cnt} | {avg:.1f} | {bench_us:.1f} | "
                      f"{avg / bench_us:.3f} |")
     with open(TRACE_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_case_trace(a, tdir, cases):
+    """Kernel-trace summary of a --paper-workload (or --options) run: the
+    per-kernel statistics of rocprofv3 and the timed results of the run."""
+    import csv
+    stats = []
+    with open(os.path.join(tdir, "run_kernel_stats.csv"), newline="") as fh:
+        for r in csv.DictReader(fh):
+            stats.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                          float(r["Percentage"])))
+    lines = [f"# rocprofv3 kernel trace: {', '.join(c['workload'].split(',')[0] for c in cases)}",
+             "", "Command (from the repository root):", "", "```", a.trace_command, "```", "",
+             f"Kernel source hash {source_sha()}.", "",
+             "| workload | FP64 s / 10 steps (Mcell-updates/s) | mixed s / 10 steps (Mcell-updates/s) |",
+             "|---|---:|---:|"]
+    for c in cases:
+        if "fp64" in c and "s_10_steps" in c["fp64"]:
+            lines.append(f"| {c['workload']} | {c['fp64']['s_10_steps']} "
+                         f"({c['fp64']['Mcell_updates_per_s']}) | {c['mixed']['s_10_steps']} "
+                         f"({c['mixed']['Mcell_updates_per_s']}) |")
+    lines += ["", "| kernel | calls | avg us | % time |", "|---|---:|---:|---:|"]
+    for name, calls, avg, pct in stats[:24]:
+        lines.append(f"| `{name}` | {calls} | {avg:.1f} | {pct:.2f} |")
+    out = os.path.join(ROOT, "profiles", a.trace_out)
+    with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
