@@ -77,6 +77,8 @@ struct Box {
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
   int xft;            // x sweep: faces per tile
+  int ctx;            // corner-EMF kernel: tile width along x (kTPB / ctx
+                      // rows), 0 for flat order
   int emf;            // corner EMF: 0 contact-upwinded, 1 E0 (derivatives
                       // averaged), 2 mean of the four face EMFs
   int ysl, yseg;      // y march: cells per segment, segments
@@ -1397,6 +1399,31 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
   pos[1] = q - pos[2] * e1;
 }
 
+// Position of a lane in the corner-EMF kernel: tiles of ctx x (kTPB / ctx)
+// positions in one xy plane (x fastest, then y, then the plane), so that the
+// row below a lane's row, whose face values and cell EMFs the lane reads,
+// is mostly fetched by the same workgroup.  ctx = 0: flat order over all
+// positions.  Returns false for lanes past the edge.
+__device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
+  const int cx = b.ctx;
+  if (cx == 0) {
+    const int p = lt * kTPB + (int)threadIdx.x;
+    if (p >= b.nf[0] * b.nf[1] * b.nf[2]) return false;
+    unflatten(p, b.nf[0], b.nf[1], pos);
+    return true;
+  }
+  const int cy = kTPB / cx;
+  const int nbx = (b.nf[0] + cx - 1) / cx;
+  const int nby = (b.nf[1] + cy - 1) / cy;
+  const int bx = lt % nbx;
+  const int r = lt / nbx;
+  const int by = r % nby;
+  pos[0] = bx * cx + (int)threadIdx.x % cx;
+  pos[1] = by * cy + (int)threadIdx.x / cx;
+  pos[2] = r / nby;
+  return pos[0] < b.nf[0] && pos[1] < b.nf[1];
+}
+
 // Corner EMFs: for every corner position one lane computes the EMF along
 // each axis c whose range contains it: the contact-upwinded average of
 // Gardiner & Stone (2005) (b.emf = 0), their E0 average with every
@@ -1411,11 +1438,8 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
     const int bi = find_box(table(L.base) + kCTE * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
-    const int p = lt * kTPB + (int)threadIdx.x;
-    const int P = b.nf[0] * b.nf[1] * b.nf[2];
-    if (p >= P) continue;
     int pos[3];
-    unflatten(p, b.nf[0], b.nf[1], pos);
+    if (!ct_pos(b, lt, pos)) continue;
     // mapped cell indices of the positions and of the positions - 1
     int m1[3], m0[3];
 #pragma unroll

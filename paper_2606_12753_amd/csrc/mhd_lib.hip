@@ -168,11 +168,11 @@ int validate_config(const mhd_config* cfg, std::string& err) {
 
 // tiling of one box (the y/z march segment lengths are tunable)
 struct Tiling {
-  int xft, ysl, yseg, zsl, zseg;
+  int xft, ctx, ysl, yseg, zsl, zseg;
   int ntile[6];
 };
 
-Tiling tiling_of(const Geom& g, int ysl, int zsl) {
+Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64) {
   Tiling t;
   // x sweep: kTPB consecutive faces of the rows per tile when the pieces of
   // rows they touch fit the LDS, else whole rows
@@ -192,9 +192,41 @@ Tiling tiling_of(const Geom& g, int ysl, int zsl) {
   t.ntile[mhd::kXS] = (int)((nrows * nf + t.xft - 1) / t.xft);
   t.ntile[mhd::kYS] = (int)(((long long)g.n[0] * g.n[2] + kTPB - 1) / kTPB * t.yseg);
   t.ntile[mhd::kZS] = (int)(((long long)g.n[0] * g.n[1] + kTPB - 1) / kTPB * t.zseg);
+  // corner-EMF kernel: tiles of ctx x (kTPB / ctx) positions per xy plane,
+  // rows of 32 in FP64 and of 128 in the mixed path (measured best on rows
+  // of 256, 352 and 768 positions), narrower or wider ones if those leave
+  // more than an eighth of the lanes idle, flat order if all do.  The face
+  // update runs in flat order (measured fastest).
+  t.ctx = 0;
+  {
+    static const int pref64[] = {32, 64, 16, 128};
+    static const int prefmx[] = {128, 64, 256, 32};
+    const int* pref = fp64 ? pref64 : prefmx;
+    for (int c = 0; c < 4; c++) {
+      const int w = pref[c], h = kTPB / w;
+      const double used = (double)g.nf[0] * g.nf[1];
+      const double all = (double)((g.nf[0] + w - 1) / w * w) * ((g.nf[1] + h - 1) / h * h);
+      if (8.0 * (all - used) <= all) {
+        t.ctx = w;
+        break;
+      }
+    }
+    // measurement override: MHD_CTX = 0 (flat), 16, 32, 64, 128 or 256
+    if (const char* v = std::getenv("MHD_CTX")) {
+      const int w = std::atoi(v);
+      if (w == 0 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256) t.ctx = w;
+    }
+  }
   const long long P = (long long)g.nf[0] * g.nf[1] * g.nf[2];
-  t.ntile[mhd::kCTE] = (int)((P + kTPB - 1) / kTPB);
-  t.ntile[mhd::kCTF] = t.ntile[mhd::kCTE];
+  if (t.ctx == 0) {
+    t.ntile[mhd::kCTE] = (int)((P + kTPB - 1) / kTPB);
+  } else {
+    const long long cy = kTPB / t.ctx;
+    const long long nbx = (g.nf[0] + t.ctx - 1) / t.ctx, nby = (g.nf[1] + cy - 1) / cy;
+    t.ntile[mhd::kCTE] = (int)(nbx * nby * g.nf[2]);
+  }
+  t.ntile[mhd::kCTF] = (int)((P + kTPB - 1) / kTPB);
+
   t.ntile[mhd::kLAM] = (int)((g.N + kTPB - 1) / kTPB);
   return t;
 }
@@ -245,7 +277,7 @@ Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
   off += align_up(sizeof(int));
   for (int b = 0; b < cfg->nboxes; b++) {
     Geom g = geom_of(cfg->boxes[b]);
-    Tiling t = tiling_of(g, ysl, zsl);
+    Tiling t = tiling_of(g, ysl, zsl, cfg->precision == MHD_FP64);
     size_t bb = box_bytes(g, t, rs, state_copies(cfg));
     p.box_off.push_back(off);
     p.box_bytes.push_back(bb);
@@ -286,7 +318,7 @@ struct mhd_ctx {
   // launch variant: register budget of the x sweep and of the marches (min
   // waves per SIMD), march segment length, persistent grid
   int var_x = 1, var_m = 1, var_seg = 32, var_pers = 0;
-  int var_xcd = 0;  // XCD-grouped tile order (measured slower on the 256^3 blast)
+  int var_xcd = 0;  // XCD-grouped tile order per kernel kind (bit mask)
   int cu_count = 0;
   bool tuned = false;
   char* backup = nullptr;  // state copy for the autotuner's trial steps
@@ -394,7 +426,7 @@ int apply_tiling(mhd_ctx* c, int seg) {
   c->var_seg = seg;
   for (int k = 0; k < 6; k++) c->total[k] = 0;
   for (int bi = 0; bi < nb; bi++) {
-    Tiling t = tiling_of(c->geom[bi], seg, seg);
+    Tiling t = tiling_of(c->geom[bi], seg, seg, c->precision == MHD_FP64);
     Box& b = c->hbox[bi];
     b.ysl = t.ysl;
     b.yseg = t.yseg;
@@ -540,7 +572,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
   for (int bi = 0; bi < nb; bi++) {
     const mhd_box& mb = cfg->boxes[bi];
     Geom g = geom_of(mb);
-    Tiling t = tiling_of(g, c->var_seg, c->var_seg);
+    Tiling t = tiling_of(g, c->var_seg, c->var_seg, c->precision == MHD_FP64);
     c->geom[bi] = g;
     Box& b = c->hbox[bi];
     std::memset(&b, 0, sizeof(Box));
@@ -583,6 +615,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xft = t.xft;
+    b.ctx = t.ctx;
     b.emf = cfg->ct_emf;
     b.ysl = t.ysl;
     b.yseg = t.yseg;
@@ -771,7 +804,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
       c->var_pers = pe;
     }
   }
-  if (const char* v = std::getenv("MHD_XCD")) c->var_xcd = std::atoi(v) != 0;
+  if (const char* v = std::getenv("MHD_XCD")) c->var_xcd = std::atoi(v) & 31;
   rc = build_ctx(c, cfg);
   if (rc) {
     g_create_error = c->err;

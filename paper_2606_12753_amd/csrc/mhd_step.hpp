@@ -31,7 +31,8 @@ struct StepCtx {
                        // 1 monotonised central, 2 van Leer)
   int fz;              // every box has one cell along z and more along y:
                        // the y march completes each stage, no z march
-  int xcd;             // XCD-grouped tile order
+  int xcd;             // XCD-grouped tile order, bit k for kernel kind k
+                       // (kXS .. kCTF)
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
   int* ev_kind;        // timing: kernel kind of each pair
@@ -94,9 +95,9 @@ inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
 template <typename real, int SL>
 inline int enqueue_step_sl(const StepCtx& sc) {
   Launch L = sc.L;
-  L.xcd = sc.xcd;
+  L.xcd = 0;
   auto grid = [&](int kind) {
-    int g = sc.xcd ? ((sc.total[kind] + 7) >> 3) << 3 : sc.total[kind];
+    int g = (sc.xcd >> kind) & 1 ? ((sc.total[kind] + 7) >> 3) << 3 : sc.total[kind];
     if (sc.grid[kind] > 0 && sc.grid[kind] < g) g = sc.grid[kind];
     return g < 1 ? 1 : g;
   };
@@ -124,6 +125,7 @@ inline int enqueue_step_sl(const StepCtx& sc) {
     L.comb = kComb[r][s];
     L.lam = s == 0;
     L.ntiles = sc.total[kXS];
+    L.xcd = (sc.xcd >> kXS) & 1;
     mark(MHD_K_SWEEP_X, true);
     if (sc.rs)
       launch_x<real, 1, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
@@ -137,6 +139,7 @@ inline int enqueue_step_sl(const StepCtx& sc) {
       mark(MHD_K_DT, false);
     }
     L.ntiles = sc.total[kYS];
+    L.xcd = (sc.xcd >> kYS) & 1;
     mark(MHD_K_SWEEP_Y, true);
     if (sc.fz) {
       if (sc.rs)
@@ -152,6 +155,7 @@ inline int enqueue_step_sl(const StepCtx& sc) {
     mark(MHD_K_SWEEP_Y, false);
     if (!sc.fz) {
       L.ntiles = sc.total[kZS];
+      L.xcd = (sc.xcd >> kZS) & 1;
       mark(MHD_K_SWEEP_Z, true);
       if (sc.rs)
         launch_march<real, 2, 1, 0, SL>(sc.var_m, dim3(grid(kZS)), sc.stream, L);
@@ -160,10 +164,12 @@ inline int enqueue_step_sl(const StepCtx& sc) {
       mark(MHD_K_SWEEP_Z, false);
     }
     L.ntiles = sc.total[kCTE];
+    L.xcd = (sc.xcd >> kCTE) & 1;
     mark(MHD_K_CT_EDGE, true);
     hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
     mark(MHD_K_CT_EDGE, false);
     L.ntiles = sc.total[kCTF];
+    L.xcd = (sc.xcd >> kCTF) & 1;
     mark(MHD_K_CT_FACE, true);
     hipLaunchKernelGGL(k_ct_face<real>, dim3(grid(kCTF)), dim3(kTPB), 0, sc.stream, L);
     mark(MHD_K_CT_FACE, false);
