@@ -531,10 +531,14 @@ int autotune(mhd_ctx* c) {
   auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
   auto set_seg = [&](int v) { return apply_tiling(c, v); };
   auto set_pers = [&](int v) { set_persistent(c, v); return MHD_OK; };
-  for (int v : {2, 3, 5, 6, 7, 8, 9, 10})
-    if ((rc = try_var(&c->var_m, v, set_m))) return rc;
-  for (int v : {3, 4})
-    if ((rc = try_var(&c->var_x, v, set_x))) return rc;
+  // the x and march variants apply to the default slope kind only (the
+  // others run one variant)
+  if (c->sl == 0) {
+    for (int v : {2, 3, 5, 6, 7, 8, 9, 10})
+      if ((rc = try_var(&c->var_m, v, set_m))) return rc;
+    for (int v : {3, 4})
+      if ((rc = try_var(&c->var_x, v, set_x))) return rc;
+  }
   for (int v : {16, 64, 128})
     if ((rc = try_var(&c->var_seg, v, set_seg))) return rc;
   if ((rc = try_var(&c->var_pers, 1 - c->var_pers, set_pers))) return rc;
@@ -882,7 +886,10 @@ int mhd_step(mhd_ctx* c, int32_t nsteps, double t_stop) {
       int rc = enqueue_step(c);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->stream, &g);
-      if (rc) return rc;
+      if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+      }
       if (e != hipSuccess) return fail(c, MHD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
       c->graph = g;
       HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
