@@ -432,6 +432,56 @@ def test_dt_query_and_t_stop():
     assert t == ob.get_state()[2]
 
 
+OPTIONS = dict(rk=3, solver="hll", recon="char", limiter="mc", emf="e0")
+
+
+def test_ensemble_2d_and_3d_with_every_option():
+    """An ensemble of 3D, 2D and 1D boxes (so the z march runs) with every
+    non-default scheme option at once, graph replay and a persistent grid:
+    each box bit for bit with the oracle."""
+    boxes, states = [], []
+    for n, seed, bc in [((20, 18, 14), 41, (0, 1, 0)), ((33, 21, 1), 42, (1, 0, 0)),
+                        ((1, 1, 40), 43, (0, 0, 1))]:
+        w = W.random_smooth(n=n, seed=seed, bc=bc)
+        boxes += w.boxes
+        states += w.states
+    wl = W.Workload("mix-options", boxes, states, 3)
+    res = gpu_run(wl, 3, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT, **OPTIONS)
+    for i, g in enumerate(res):
+        o = oracle_run(boxes[i], states[i], 3, **OPTIONS)
+        assert_fp64_parity(g, o, f"options box {i}")
+
+
+def test_t_stop_and_graph_replays_with_options():
+    """With every option: the t_stop clamp lands on the oracle's time, and
+    each graph replay equals the eager step bit for bit."""
+    wl = W.random_smooth(n=(18, 14, 10), seed=44)
+    spec, st = wl.boxes[0], wl.states[0]
+    ob = O.OracleBox(spec, **OPTIONS)
+    ob.set_state(st.cons, st.bface)
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH, **OPTIONS) as g, \
+            mhd.Sim([spec], **OPTIONS) as e:
+        g.set_state(0, st.cons, st.bface, 0.0)
+        e.set_state(0, st.cons, st.bface, 0.0)
+        dt, _ = g.dt(0)
+        assert dt == ob.dt()
+        for k in range(3):
+            g.step(1)
+            e.step(1)
+            cg, bg, tg = g.get_state(0)
+            ce, be, te = e.get_state(0)
+            assert tg == te, k
+            for a, b in zip(cg + bg, ce + be):
+                assert np.array_equal(a, b), k
+        e.step(10, t_stop=5.5 * dt)
+        ce, be, te = e.get_state(0)
+    ob.step(10, 5.5 * dt)
+    oc, obf, ot = ob.get_state()
+    assert te == ot
+    for a, b in zip(ce + be, oc + obf):
+        assert np.array_equal(a, b)
+
+
 def test_set_get_roundtrip_host_and_device():
     import torch
     wl = W.random_smooth(n=(10, 9, 8), seed=11, bc=(0, 1, 0))
