@@ -207,15 +207,20 @@ def run_gpu(wl, precision, steps, warmup, flags, repeats=1, rk=2, solver="hlld",
     return out
 
 
-def fractions(ms_per_step, cells, table, peak_flops):
+def fractions(ms_per_step, cells, table, peak_flops, triad_gbs=None):
     """Roofline fractions of a whole step: the per-direction design's
     algorithmic bytes (every kernel, both stages) at 8 TB/s, and the method's
     compulsory state traffic (320 B per cell-update) or its flops, whichever
-    bounds, over the measured step time."""
+    bounds, over the measured step time.  With the measured triad bandwidth,
+    also the design's bytes at that achievable rate (context, not a peak)."""
     t = ms_per_step * 1e-3
-    design = sum(b1 + b2 for b1, b2 in table.values()) * cells / (HBM_PEAK_GBS * 1e9)
+    nbytes = sum(b1 + b2 for b1, b2 in table.values()) * cells
+    design = nbytes / (HBM_PEAK_GBS * 1e9)
     method = max(320 * cells / (HBM_PEAK_GBS * 1e9), FLOPS_PER_CELL_UPDATE * cells / peak_flops)
-    return {"design_hbm": round(design / t, 4), "method": round(method / t, 4)}
+    out = {"design_hbm": round(design / t, 4), "method": round(method / t, 4)}
+    if triad_gbs:
+        out["design_vs_measured_triad"] = round(nbytes / (triad_gbs * 1e9) / t, 4)
+    return out
 
 
 def pcie_inclusive(wl, precision, steps, variant):
@@ -785,7 +790,8 @@ def main():
             "ms_per_step": round(rmx["ms"] / a.steps, 4),
             "speedup_vs_fp64": round(ms / rmx["ms"], 3),
             "ms_per_step_repeats": [round(t / a.steps, 4) for t in rmx["times"]],
-            "fractions": fractions(rmx["ms"] / a.steps, cells, BYTES_MIXED, FP32_PEAK_FLOPS),
+            "fractions": fractions(rmx["ms"] / a.steps, cells, BYTES_MIXED, FP32_PEAK_FLOPS,
+                                   stream["triad_GBs"]),
             "accuracy_vs_fp64": acc,
             "after_steps": a.warmup + a.steps,
             "variant": rmx["variant"],
@@ -815,7 +821,8 @@ def main():
                    "cells": cells, "launch": "hipGraph replay per step",
                    "variant": r64["variant"]},
         "roofline": roof,
-        "fractions": fractions(ms / a.steps, cells, BYTES_FP64, FP64_PEAK_FLOPS),
+        "fractions": fractions(ms / a.steps, cells, BYTES_FP64, FP64_PEAK_FLOPS,
+                               stream["triad_GBs"]),
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "mixed": mixed,
         "hbm_stream": stream,
