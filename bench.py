@@ -90,9 +90,10 @@ def parse():
     ap.add_argument("--counter-pass", action="store_true",
                     help="dispatches for a rocprofv3 --pmc run (calibration copy, then "
                          "--steps unfused steps of each precision)")
-    ap.add_argument("--variant64", default="1,1,32,0", help="x,m,seg,persistent of the FP64 run")
-    ap.add_argument("--variant-mixed", default="1,1,32,0",
-                    help="x,m,seg,persistent of the mixed run")
+    ap.add_argument("--variant64", default="1,1,64,0,64",
+                    help="x,m,segy,persistent,segz of the FP64 run")
+    ap.add_argument("--variant-mixed", default="1,1,64,0,128",
+                    help="x,m,segy,persistent,segz of the mixed run")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic record from two counter-pass runs")
     ap.add_argument("--fetch-command", default="", help="command of the FETCH_SIZE run")
@@ -157,7 +158,11 @@ def kernel_name(kind, real, variant):
 def launch_key(kind, real, variant):
     """What fixes a kernel's code and launch shape: its instance, the march
     segment length (marches only) and the persistent grid."""
-    seg = f"|seg={variant[2]}" if kind in ("sweep_y", "sweep_z") else ""
+    seg = ""
+    if kind == "sweep_y":
+        seg = f"|seg={variant[2]}"
+    elif kind == "sweep_z":
+        seg = f"|seg={variant[4] if len(variant) > 4 else variant[2]}"
     return f"{kernel_name(kind, real, variant)}{seg}|persistent={variant[3]}"
 
 
@@ -390,8 +395,10 @@ def cpu_baseline(n, steps, threads):
 
 def parse_variant(text):
     v = [int(t) for t in text.split(",")]
-    if len(v) != 4:
-        raise SystemExit(f"bench.py: variant {text!r} is not x,m,seg,persistent")
+    if len(v) == 4:
+        v.append(v[2])
+    if len(v) != 5:
+        raise SystemExit(f"bench.py: variant {text!r} is not x,m,seg,persistent[,segz]")
     return v
 
 

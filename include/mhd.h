@@ -196,13 +196,13 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
  * waves per SIMD without prefetch, 5 / 6 / 7: the sliding window kept in
  * LDS, with prefetch / without / at least 3 waves per SIMD, 8 / 9 / 10:
  * variants 2 / 6 / 7 whose z march keeps the swept state of its last three
- * cells in LDS for the RK combine instead of reading it again), [2] march
- * segment length (cells),
- * [3] persistent grid (0/1).
+ * cells in LDS for the RK combine instead of reading it again), [2] y march
+ * segment length (cells), [3] persistent grid (0/1), [4] z march segment
+ * length (cells).
  * The variants differ only in scheduling: FP64 results are identical.  With
  * MHD_REC_CHAR or a limiter other than minmod the sweeps run one variant
  * ([0] and [1] are then ignored). */
-int mhd_tuning(mhd_ctx *ctx, int32_t variant[4]);
+int mhd_tuning(mhd_ctx *ctx, int32_t variant[5]);
 
 /* Frees the context and every buffer the library allocated (a caller
  * workspace is left alone).  NULL is a no-op. */

@@ -317,7 +317,7 @@ struct mhd_ctx {
   int grid[6] = {0, 0, 0, 0, 0, 0};
   // launch variant: register budget of the x sweep and of the marches (min
   // waves per SIMD), march segment length, persistent grid
-  int var_x = 1, var_m = 1, var_seg = 32, var_pers = 0;
+  int var_x = 1, var_m = 1, var_seg = 64, var_segz = 64, var_pers = 0;
   int var_xcd = 0;  // XCD-grouped tile order per kernel kind (bit mask)
   int cu_count = 0;
   bool tuned = false;
@@ -421,12 +421,14 @@ void set_persistent(mhd_ctx* c, int on) {
 
 // re-tile the y/z marches with segment length seg (device tables updated
 // on the context stream)
-int apply_tiling(mhd_ctx* c, int seg) {
+// segment lengths of the y and z marches
+int apply_tiling(mhd_ctx* c, int segy, int segz) {
   const int nb = (int)c->boxes.size();
-  c->var_seg = seg;
+  c->var_seg = segy;
+  c->var_segz = segz;
   for (int k = 0; k < 6; k++) c->total[k] = 0;
   for (int bi = 0; bi < nb; bi++) {
-    Tiling t = tiling_of(c->geom[bi], seg, seg, c->precision == MHD_FP64);
+    Tiling t = tiling_of(c->geom[bi], segy, segz, c->precision == MHD_FP64);
     Box& b = c->hbox[bi];
     b.ysl = t.ysl;
     b.yseg = t.yseg;
@@ -529,7 +531,8 @@ int autotune(mhd_ctx* c) {
   };
   auto set_x = [&](int v) { c->var_x = v; return MHD_OK; };
   auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
-  auto set_seg = [&](int v) { return apply_tiling(c, v); };
+  auto set_seg = [&](int v) { return apply_tiling(c, v, c->var_segz); };
+  auto set_segz = [&](int v) { return apply_tiling(c, c->var_seg, v); };
   auto set_pers = [&](int v) { set_persistent(c, v); return MHD_OK; };
   // the x and march variants apply to the default slope kind only (the
   // others run one variant)
@@ -539,8 +542,10 @@ int autotune(mhd_ctx* c) {
     for (int v : {3, 4})
       if ((rc = try_var(&c->var_x, v, set_x))) return rc;
   }
-  for (int v : {16, 64, 128})
-    if ((rc = try_var(&c->var_seg, v, set_seg))) return rc;
+  for (int v : {16, 32, 64, 128})
+    if (v != c->var_seg && (rc = try_var(&c->var_seg, v, set_seg))) return rc;
+  for (int v : {16, 32, 64, 128})
+    if (v != c->var_segz && (rc = try_var(&c->var_segz, v, set_segz))) return rc;
   if ((rc = try_var(&c->var_pers, 1 - c->var_pers, set_pers))) return rc;
   c->tuned = true;
   return MHD_OK;
@@ -576,7 +581,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
   for (int bi = 0; bi < nb; bi++) {
     const mhd_box& mb = cfg->boxes[bi];
     Geom g = geom_of(mb);
-    Tiling t = tiling_of(g, c->var_seg, c->var_seg, c->precision == MHD_FP64);
+    Tiling t = tiling_of(g, c->var_seg, c->var_segz, c->precision == MHD_FP64);
     c->geom[bi] = g;
     Box& b = c->hbox[bi];
     std::memset(&b, 0, sizeof(Box));
@@ -797,14 +802,21 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     }
     c->own_stream = true;
   }
+  // default march segments (measured on 256^3): 64 cells along y; along z
+  // 64 in FP64, 128 in the mixed path
+  c->var_segz = cfg->precision == MHD_FP64 ? 64 : 128;
   if (const char* v = std::getenv("MHD_VARIANT")) {
-    // "x,m,seg,persistent": fixed launch variant (tests, experiments)
-    int x = 1, m = 1, sg = 32, pe = 0;
-    if (std::sscanf(v, "%d,%d,%d,%d", &x, &m, &sg, &pe) == 4 && (x == 1 || x == 3 || x == 4) &&
-        (m >= 1 && m <= 10) && sg >= 1 && sg <= 4096 && (pe == 0 || pe == 1)) {
+    // "x,m,seg,persistent[,segz]": fixed launch variant (tests, experiments);
+    // seg is the y march segment, and the z march's too unless segz is given
+    int x = 1, m = 1, sg = 32, pe = 0, sz = -1;
+    const int got = std::sscanf(v, "%d,%d,%d,%d,%d", &x, &m, &sg, &pe, &sz);
+    if (got == 4) sz = sg;
+    if ((got == 4 || got == 5) && (x == 1 || x == 3 || x == 4) && (m >= 1 && m <= 10) &&
+        sg >= 1 && sg <= 4096 && sz >= 1 && sz <= 4096 && (pe == 0 || pe == 1)) {
       c->var_x = x;
       c->var_m = m;
       c->var_seg = sg;
+      c->var_segz = sz;
       c->var_pers = pe;
     }
   }
@@ -990,13 +1002,14 @@ int mhd_kernel_times(mhd_ctx* c, double ms[MHD_NKERNELS], int64_t launches[MHD_N
   return MHD_OK;
 }
 
-int mhd_tuning(mhd_ctx* c, int32_t variant[4]) {
+int mhd_tuning(mhd_ctx* c, int32_t variant[5]) {
   if (!c) return MHD_E_INVAL;
   if (!variant) return fail(c, MHD_E_INVAL, "variant is NULL");
   variant[0] = c->var_x;
   variant[1] = c->var_m;
   variant[2] = c->var_seg;
   variant[3] = c->var_pers;
+  variant[4] = c->var_segz;
   return MHD_OK;
 }
 

@@ -310,9 +310,9 @@ class Sim:
         return {k: (ms[i], int(n[i])) for i, k in enumerate(KERNELS)}
 
     def tuning(self):
-        """Launch variant in use: (x-sweep waves/SIMD, march waves/SIMD,
-        march segment length, persistent grid)."""
-        v = (C.c_int32 * 4)()
+        """Launch variant in use: (x-sweep waves/SIMD, march variant, y march
+        segment length, persistent grid, z march segment length)."""
+        v = (C.c_int32 * 5)()
         self._check(self._lib.mhd_tuning(self._h, v))
         return tuple(int(x) for x in v)
 

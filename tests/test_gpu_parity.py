@@ -791,7 +791,8 @@ def test_ensemble_96_boxes_full_size():
 # ---------------------------------------------------------------- variants
 
 @pytest.mark.parametrize("variant", ["1,1,32,0", "3,4,16,1", "4,3,64,0", "1,2,128,1", "4,5,7,0",
-                                     "1,6,32,1", "3,7,16,0", "1,8,32,0", "3,9,7,1", "1,10,64,0"])
+                                     "1,6,32,1", "3,7,16,0", "1,8,32,0", "3,9,7,1", "1,10,64,0",
+                                     "1,8,64,0,128", "3,9,16,1,5"])
 def test_launch_variants_bitwise_identical(variant, monkeypatch):
     """Register budgets, segment lengths and grid shapes change scheduling
     only: FP64 results are identical across all launch variants."""
@@ -817,7 +818,8 @@ def test_autotune_restores_state_and_matches():
         cons, bface, t = sim.get_state(0)
         v = sim.tuning()
         cnt = sim.counters(0)
-    assert v[0] in (1, 3, 4) and 1 <= v[1] <= 10 and v[2] >= 1 and v[3] in (0, 1)
+    assert len(v) == 5
+    assert v[0] in (1, 3, 4) and 1 <= v[1] <= 10 and v[2] >= 1 and v[3] in (0, 1) and v[4] >= 1
     assert t == ref[2] and cnt == ref[3]
     for a, b in zip(cons + bface, ref[0] + ref[1]):
         assert np.array_equal(a, b)
