@@ -1,0 +1,85 @@
+"""Host-side logic of bench.py (no GPU): launch-variant parsing, the
+kernel names and launch keys that tie rocprofv3 records to launches, the
+roofline fractions, and the ingestion of counter records."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_parse_variant_four_or_five_entries():
+    assert bench.parse_variant("1,9,64,0") == [1, 9, 64, 0, 64]
+    assert bench.parse_variant("3,8,64,1,128") == [3, 8, 64, 1, 128]
+    with pytest.raises(SystemExit):
+        bench.parse_variant("1,2,3")
+
+
+def test_kernel_names_and_launch_keys():
+    v = [1, 9, 64, 0, 128]
+    assert bench.kernel_name("sweep_x", "double", v) == "mhd::k_sweep_x<double, 1, 0, 0>"
+    # the y march has no LDS ring: variants 8, 9, 10 run as 2, 6, 7 there
+    assert bench.kernel_name("sweep_y", "float", v) == \
+        "mhd::k_sweep_march<float, 1, 1, 0, 1, 0, 0, 0, 0>"
+    assert bench.kernel_name("sweep_z", "float", v) == \
+        "mhd::k_sweep_march<float, 2, 1, 0, 1, 1, 0, 0, 0>"
+    assert bench.kernel_name("ct_edge", "double", v) == "mhd::k_ct_edge<double>"
+    assert bench.launch_key("sweep_y", "float", v).endswith("|seg=64|persistent=0")
+    assert bench.launch_key("sweep_z", "float", v).endswith("|seg=128|persistent=0")
+    assert bench.launch_key("sweep_x", "double", v) == "mhd::k_sweep_x<double, 1, 0, 0>|persistent=0"
+    for name, want in (("void mhd::k_sweep_x<double, 3, 0, 0>(mhd::Launch)", ("fp64", "sweep_x")),
+                       ("void mhd::k_sweep_march<float, 2, 1, 0, 0, 1, 0, 0, 0>(mhd::Launch)",
+                        ("mixed", "sweep_z")),
+                       ("void mhd::k_ct_face<float>(mhd::Launch)", ("mixed", "ct_face")),
+                       ("__amd_rocclr_copyBuffer", None)):
+        assert bench.kind_of(name) == want
+
+
+def test_fractions_arithmetic():
+    cells = 1000
+    table = {"a": (100, 100), "b": (50, 70)}
+    f = bench.fractions(1.0, cells, table, 1e12, triad_gbs=4000.0)
+    nbytes = (200 + 120) * cells
+    assert f["design_hbm"] == round(nbytes / (bench.HBM_PEAK_GBS * 1e9) / 1e-3, 4)
+    assert f["design_vs_measured_triad"] == round(nbytes / 4e12 / 1e-3, 4)
+    assert "design_vs_measured_triad" not in bench.fractions(1.0, cells, table, 1e12)
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for i, (k, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": counter,
+                        "Counter_Value": v})
+
+
+def test_ingest_counters_scales_by_the_calibration_copy(tmp_path, monkeypatch):
+    """FETCH_SIZE reads half the copy's bytes and WRITE_SIZE all of them in
+    this synthetic record: the scales are 2 and 1, and each kernel's traffic
+    is its averaged readings times those scales."""
+    kib = bench.COPY_BYTES / 1024
+    x64 = "void mhd::k_sweep_x<double, 1, 0, 0>(mhd::Launch)"
+    fetch = [("__amd_rocclr_copyBuffer", kib / 2)] * 3 + [(x64, 1000.0), (x64, 1200.0)]
+    write = [("__amd_rocclr_copyBuffer", kib)] * 3 + [(x64, 500.0), (x64, 700.0)]
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    _counter_csv(f, "FETCH_SIZE", fetch)
+    _counter_csv(w, "WRITE_SIZE", write)
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    args = bench.argparse.Namespace(ingest_counters=(str(f), str(w)), n=8, fetch_command="f",
+                                    write_command="w", variant64="1,2,64,0,64",
+                                    variant_mixed="1,8,64,0,128")
+    bench.ingest_counters(args)
+    rec = json.loads(out.read_text())
+    assert rec["scale"] == {"fetch": 2.0, "write": 1.0}
+    k = rec["fp64"]["kernels"]["sweep_x"]
+    assert k["dispatches"] == 2 and k["fetch_kib"] == 1100.0 and k["write_kib"] == 600.0
+    assert k["bytes"] == int((1100.0 * 2.0 + 600.0) * 1024)
+    assert k["launch"] == bench.launch_key("sweep_x", "double", [1, 2, 64, 0, 64])
