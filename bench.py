@@ -102,6 +102,10 @@ def parse():
                     help="write the kernel-trace summary from a rocprofv3 --kernel-trace "
                          "--stats run of this script")
     ap.add_argument("--trace-command", default="", help="command of the kernel-trace run")
+    ap.add_argument("--ingest-sq", nargs=2, metavar=("SQ_CSV", "TRACE_DIR"),
+                    help="write the SQ-counter record from a --pmc run of the counter pass and "
+                         "a kernel trace of the same variants")
+    ap.add_argument("--sq-command", default="", help="command of the SQ-counter run")
     ap.add_argument("--trace-out", default="kernel_trace_paper_cases.md",
                     help="file under profiles/ for the summary of a run without a bench line")
     return ap.parse_args()
@@ -501,6 +505,72 @@ def ingest_counters(a):
                       for k in ("fp64", "mixed")}))
 
 
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second (4 cycles each)
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+               "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES"]
+
+
+def ingest_sq(a):
+    """Writes the instruction-level record of the benchmark's kernels from
+    one rocprofv3 --pmc run of the counter pass (the SQ_COUNTERS) and a
+    kernel trace of the same launch variants: per kernel, VALU instructions
+    per wave, VALU issue rate against the chip's issue ceiling (256 CUs x 4
+    SIMDs x 2.4 GHz, 4 cycles per wave64 instruction), LDS bank-conflict
+    cycles per LDS instruction, and the registers, LDS and scratch of its
+    code object."""
+    import csv
+    sq_csv, tdir = a.ingest_sq
+    per = {}
+    with open(sq_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            k = kind_of(r["Kernel_Name"])
+            if k is None:
+                continue
+            rec = per.setdefault((k, r["Kernel_Name"]), {})
+            rec.setdefault(r["Counter_Name"], {}).setdefault(int(r["Dispatch_Id"]), 0.0)
+            rec[r["Counter_Name"]][int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+    dur, res = {}, {}
+    with open(os.path.join(tdir, "run_kernel_trace.csv"), newline="") as fh:
+        for r in csv.DictReader(fh):
+            n = r["Kernel_Name"]
+            dur.setdefault(n, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+            res[n] = (r.get("VGPR_Count") or r.get("Arch_VGPR_Count"), r["SGPR_Count"],
+                      r["LDS_Block_Size"], r["Scratch_Size"])
+    lines = [f"# SQ counters: blast_3d {a.n}^3, the benchmark's kernels", "",
+             "Commands (from the repository root):", "", "```", a.sq_command, a.trace_command, "```",
+             "", f"Kernel source hash {source_sha()}; variants FP64 {a.variant64}, mixed "
+             f"{a.variant_mixed}.  VALU issue = SQ_INSTS_VALU / (duration x "
+             f"{VALU_ISSUE_PER_S / 1e9:.0f} G wave-instructions/s), the fraction of the chip's "
+             "VALU issue slots used; durations are the trace's averages for the kernel in this "
+             "unfused counter pass (longer than the graph-replayed bench's).  VGPR_Count, "
+             "SGPR_Count, LDS and scratch are rocprofv3's per-dispatch fields (VGPR_Count is half "
+             "the compiler's register count on this target: 72 for the FP64 x sweep's 142).", "",
+             "| precision | kernel | waves | VALU / wave | SALU / wave | VMEM rd / wave | "
+             "LDS / wave | LDS conflict cycles / LDS instr | avg us | VALU issue | VGPR_Count | "
+             "SGPR_Count | LDS bytes | scratch bytes |",
+             "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for ((key, kind), name), rec in sorted(per.items(), key=lambda x: (x[0][0][0], KINDS.index(x[0][0][1]))):
+        def mean(c):
+            v = rec.get(c, {})
+            return sum(v.values()) / len(v) if v else float("nan")
+        waves = mean("SQ_WAVES")
+        valu = mean("SQ_INSTS_VALU")
+        lds = mean("SQ_INSTS_LDS")
+        d = dur.get(name)
+        avg = sum(d) / len(d) if d else float("nan")
+        issue = valu / (avg * VALU_ISSUE_PER_S) if d else float("nan")
+        vg, sg, lb, sc = res.get(name, ("-", "-", "-", "-"))
+        conf = mean("SQ_LDS_BANK_CONFLICT") / lds if lds > 0 else 0.0
+        lines.append(f"| {key} | `{name.replace('void ', '').replace('(mhd::Launch)', '')}` | "
+                     f"{waves:.0f} | {valu / waves:.0f} | {mean('SQ_INSTS_SALU') / waves:.0f} | "
+                     f"{mean('SQ_INSTS_VMEM_RD') / waves:.1f} | {lds / waves:.1f} | {conf:.3f} | "
+                     f"{avg * 1e6:.1f} | {issue:.2f} | {vg} | {sg} | {lb} | {sc} |")
+    out = os.path.join(ROOT, "profiles", f"sq_counters_blast_{a.n}.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(a):
     """Writes the kernel-trace summary: rocprofv3's per-kernel statistics and,
     for the dominant kernel of each precision, the average duration of the
@@ -745,6 +815,9 @@ def main():
         return
     if a.summarize_trace:
         summarize_trace(a)
+        return
+    if a.ingest_sq:
+        ingest_sq(a)
         return
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
