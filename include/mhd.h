@@ -5,12 +5,13 @@
  * that arXiv 2606.12753 §2.2.3 describes: per direction, reconstruction of
  * primitive variables, a Riemann solve at every interface and a
  * flux-conservative update; constrained transport (CT) for the magnetic
- * field; Runge-Kutta stepping.  Concretely: PLM-minmod reconstruction, HLLD
- * fluxes with HLL fallback (or HLL alone), the flux-divergence update, contact-upwinded CT
- * corner EMFs with the face-field update, the CFL time step from a
- * max-reduction of the fast magnetosonic rate and the SSP Runge-Kutta
- * stage combines (two or three stages), on 3D structured boxes (2D and 1D as
- * boxes with inactive axes of one cell).
+ * field; Runge-Kutta stepping.  Concretely: PLM reconstruction (minmod, MC
+ * or van Leer slopes of primitive or characteristic variables), HLLD fluxes
+ * with HLL fallback (or HLL alone), the flux-divergence update, CT corner
+ * EMFs (contact-upwinded, E0 or arithmetic average) with the face-field
+ * update, the CFL time step from a max-reduction of the fast magnetosonic
+ * rate and the SSP Runge-Kutta stage combines (two or three stages), on 3D
+ * structured boxes (2D and 1D as boxes with inactive axes of one cell).
  *
  * All entry points return MHD_OK (0) or a negative status and never throw,
  * abort or exit across the ABI.  A context is used by one host thread at a

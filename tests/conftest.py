@@ -7,6 +7,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Parallel test workers (pytest -n K) share the cores: give each worker's
+# OpenMP oracle (and the subprocesses it starts) its share, since spinning
+# OpenMP teams that outnumber the cores make small loops crawl.  Results do
+# not depend on the thread count.
+_workers = int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "0") or 0)
+if _workers > 1 and "OMP_NUM_THREADS" not in os.environ:
+    os.environ["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // _workers))
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP C-ABI library)")
