@@ -89,6 +89,8 @@ struct orc_box {
   double *R[NQ];           /* cell residual */
   double *ED[3];           /* corner EMF along axis c */
   double *RB[3];           /* face rate */
+  double *SP[3][2];        /* outer wave speeds S_L, S_R on d-faces (read by
+                              the upwind-CT corner EMF only) */
   double t;
   long long nfloor, nhll, nbad;
 };
@@ -673,6 +675,7 @@ static double *alloc_arr(size_t np) {
       X(b->RB[d_]);                                         \
       for (q_ = 0; q_ < NQ; q_++) X(b->FH[d_][q_]);         \
       for (c_ = 0; c_ < 3; c_++) X(b->EF[d_][c_]);          \
+      for (c_ = 0; c_ < 2; c_++) X(b->SP[d_][c_]);          \
     }                                                       \
     for (q_ = 0; q_ < 8; q_++) X(b->W[q_]);                 \
   } while (0)
@@ -1007,9 +1010,119 @@ static void sweep(orc_box *b, int d) {
         b->EF[d][t1][fidx] = f[6];
         b->EF[d][t2][fidx] = -f[5];
         b->FM[d][fidx] = fm;
+        if (b->emf == ORC_EMF_UCT_HLL) {
+          double sl, sr;
+          wave_speeds(wl, wr, bn, b->gamma, &sl, &sr);
+          b->SP[d][0][fidx] = sl;
+          b->SP[d][1][fidx] = sr;
+        }
       }
   }
   b->nhll += nhll;
+}
+
+/* Value of q at the side of a cell facing the corner: the cell value q0
+ * carried half a cell up (side 0, the cell lies below the corner) or down
+ * (side 1) with the limited slope of q0 between its neighbours qm and qp;
+ * no slope along an inactive axis. */
+static double to_corner(const orc_box *b, int active, int side, double qm, double q0,
+                        double qp) {
+  double d = active ? orc_limit(b->lim, q0 - qm, qp - q0) : 0.0;
+  return side == 0 ? q0 + 0.5 * d : q0 - 0.5 * d;
+}
+
+/* Upper bound of the right-going (left-going when left != 0) signal speed
+ * at a corner from the outer wave speeds of its two faces, at least 0 */
+static double speed_bound(double s0, double s1, int left) {
+  if (left) {
+    double m = s0 < s1 ? s0 : s1;
+    return m < 0.0 ? -m : 0.0;
+  }
+  double m = s0 > s1 ? s0 : s1;
+  return m > 0.0 ? m : 0.0;
+}
+
+double orc_uct_hll(const double va[4], const double vb[4], const double ba[2],
+                   const double bb[2], const double alpha[4]) {
+  double apa = alpha[0], ama = alpha[1], apb = alpha[2], amb = alpha[3];
+  double e[4];
+  int k;
+  /* E_c = v_b B_a - v_a B_b of each corner state */
+  for (k = 0; k < 4; k++) e[k] = vb[k] * ba[k >> 1] - va[k] * bb[k & 1];
+  /* HLL along both axes: the lower state of an axis is weighted by the
+   * right-going bound, the upper state by the left-going one; each axis adds
+   * the HLL diffusion of the field component it carries (the flux of B_a
+   * along b is E_c, the flux of B_b along a is -E_c) */
+  double num = apa * apb * e[0] + ama * apb * e[1] + apa * amb * e[2] + ama * amb * e[3];
+  double sa = apa + ama, sb = apb + amb;
+  return num / (sa * sb) - apb * amb / sb * (ba[1] - ba[0]) +
+         apa * ama / sa * (bb[1] - bb[0]);
+}
+
+/* Upwind-CT corner EMF along c at corner position pos (a-face index ia =
+ * pos[a], b-face index ib = pos[b]): the four cells around the edge give
+ * the corner states (velocities carried to the corner with their limited
+ * slopes along a and b), the a-faces (ia; ib-1), (ia; ib) and the b-faces
+ * (ib; ia-1), (ib; ia) give the field carried along the other axis and the
+ * speed bounds.  An inactive axis has equal states on both sides; its
+ * weights are 1. */
+static double uct_corner(const orc_box *b, int c, const int pos[3]) {
+  int a = (c + 1) % 3, bb = (c + 2) % 3;
+  int ax[2] = {a, bb};
+  double alpha[4] = {1.0, 1.0, 1.0, 1.0};
+  for (int e = 0; e < 2; e++) {
+    int d = ax[e], t = ax[1 - e];
+    if (!b->active[d]) continue;
+    int p0[3] = {pos[0], pos[1], pos[2]};
+    p0[t] -= 1;
+    size_t i0 = IXp(b, p0), i1 = IXp(b, pos);
+    alpha[2 * e] = speed_bound(b->SP[d][1][i0], b->SP[d][1][i1], 0);
+    alpha[2 * e + 1] = speed_bound(b->SP[d][0][i0], b->SP[d][0][i1], 1);
+  }
+  double va[4], vb[4], fa[2], fb[2];
+  for (int k = 0; k < 4; k++) {
+    int sa = k & 1, sb = k >> 1;
+    int pc[3] = {pos[0], pos[1], pos[2]}; /* cell (ia-1+sa, ib-1+sb) */
+    pc[a] += sa - 1;
+    pc[bb] += sb - 1;
+    int am[3] = {pc[0], pc[1], pc[2]}, ap[3] = {pc[0], pc[1], pc[2]};
+    int bm[3] = {pc[0], pc[1], pc[2]}, bp[3] = {pc[0], pc[1], pc[2]};
+    am[a] -= 1;
+    ap[a] += 1;
+    bm[bb] -= 1;
+    bp[bb] += 1;
+    for (int e = 0; e < 2; e++) {
+      const double *q = b->W[1 + ax[e]];
+      double q0 = q[IXp(b, pc)];
+      /* half the a slope, then half the b slope of the same cell */
+      double x = to_corner(b, b->active[a], sa, q[IXp(b, am)], q0, q[IXp(b, ap)]);
+      double db = b->active[bb] ? orc_limit(b->lim, q0 - q[IXp(b, bm)], q[IXp(b, bp)] - q0) : 0.0;
+      x = sb == 0 ? x + 0.5 * db : x - 0.5 * db;
+      if (e == 0)
+        va[k] = x;
+      else
+        vb[k] = x;
+    }
+  }
+  for (int s2 = 0; s2 < 2; s2++) {
+    /* a-face field at (ia; ib-1+s2), carried along b */
+    int pf[3] = {pos[0], pos[1], pos[2]};
+    pf[bb] += s2 - 1;
+    int fm[3] = {pf[0], pf[1], pf[2]}, fp[3] = {pf[0], pf[1], pf[2]};
+    fm[bb] -= 1;
+    fp[bb] += 1;
+    const double *qa = b->B[a];
+    fa[s2] = to_corner(b, b->active[bb], s2, qa[IXp(b, fm)], qa[IXp(b, pf)], qa[IXp(b, fp)]);
+    /* b-face field at (ib; ia-1+s2), carried along a */
+    int pg[3] = {pos[0], pos[1], pos[2]};
+    pg[a] += s2 - 1;
+    int gm[3] = {pg[0], pg[1], pg[2]}, gp[3] = {pg[0], pg[1], pg[2]};
+    gm[a] -= 1;
+    gp[a] += 1;
+    const double *qb = b->B[bb];
+    fb[s2] = to_corner(b, b->active[a], s2, qb[IXp(b, gm)], qb[IXp(b, pg)], qb[IXp(b, gp)]);
+  }
+  return orc_uct_hll(va, vb, fa, fb, alpha);
 }
 
 /* corner EMFs along c at a-faces 0..n_a, b-faces 0..n_b, c cells 0..n_c-1 */
@@ -1033,6 +1146,10 @@ static void corner_emfs(orc_box *b, int c) {
         pab[a] -= 1;
         pab[bb] -= 1;
         size_t i11 = IXp(b, pos), ia0 = IXp(b, pa), ib0 = IXp(b, pb), i00 = IXp(b, pab);
+        if (b->emf == ORC_EMF_UCT_HLL) {
+          b->ED[c][i11] = uct_corner(b, c, pos);
+          continue;
+        }
         double fa1 = b->EF[a][c][i11], fa0 = b->EF[a][c][ia0];
         double fb1 = b->EF[bb][c][i11], fb0 = b->EF[bb][c][ib0];
         /* cells: oa = 0 -> ia-1, ob = 0 -> ib-1 */
@@ -1203,7 +1320,9 @@ int orc_set_limiter(orc_box *b, int lim) {
 }
 
 int orc_set_emf(orc_box *b, int emf) {
-  if (emf != ORC_EMF_CONTACT && emf != ORC_EMF_E0 && emf != ORC_EMF_ARITH) return -1;
+  if (emf != ORC_EMF_CONTACT && emf != ORC_EMF_E0 && emf != ORC_EMF_ARITH &&
+      emf != ORC_EMF_UCT_HLL)
+    return -1;
   b->emf = emf;
   return 0;
 }

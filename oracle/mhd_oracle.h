@@ -69,11 +69,14 @@ int orc_set_solver(orc_box *b, int solver);
 int orc_set_recon(orc_box *b, int rec);
 /* Corner EMF of the constrained transport: ORC_EMF_CONTACT (the default,
  * contact-upwinded average, see orc_ct_corner), ORC_EMF_E0 (the same
- * average with both sides of every derivative averaged) or ORC_EMF_ARITH
- * (mean of the four face EMFs); -1 otherwise. */
+ * average with both sides of every derivative averaged), ORC_EMF_ARITH
+ * (mean of the four face EMFs) or ORC_EMF_UCT_HLL (upwind CT: the
+ * two-dimensional HLL flux of the four reconstructed corner states, see
+ * orc_uct_hll); -1 otherwise. */
 #define ORC_EMF_CONTACT 0
 #define ORC_EMF_E0 1
 #define ORC_EMF_ARITH 2
+#define ORC_EMF_UCT_HLL 3
 int orc_set_emf(orc_box *b, int emf);
 double orc_ct_corner_kind(int kind, double fa1, double fa0, double fb1, double fb0,
                           const double ec[4], double ma1, double ma0, double mb1,
@@ -135,6 +138,16 @@ double orc_ct_mass_flux(const double wl[7], const double wr[7], double bn,
 double orc_ct_corner(double fa1, double fa0, double fb1, double fb0,
                      const double ec[4], double ma1, double ma0, double mb1,
                      double mb0);
+/* Upwind-CT corner EMF along c = (a, b) x (Londrillo & Del Zanna 2004,
+ * HLL form) from the four corner states: va[k], vb[k] the velocity
+ * components along a and b of state k = 2*sb + sa (sa, sb = 0: the lower
+ * side along a, b; 1: the upper side); ba[sb] the a-face field carried to
+ * the corner from the lower (0) and upper (1) side along b; bb[sa] the
+ * b-face field from the lower and upper side along a; alpha = {a+_a, a-_a,
+ * a+_b, a-_b} the right- and left-going speed bounds (>= 0, each pair with a
+ * positive sum). */
+double orc_uct_hll(const double va[4], const double vb[4], const double ba[2],
+                   const double bb[2], const double alpha[4]);
 
 #ifdef __cplusplus
 }

@@ -4,7 +4,7 @@
  *
  *   mhd_oracle --in STATE --out STATE --steps N [--t-stop T] [--threads K]
  *              [--rk 2|3] [--solver hlld|hll] [--recon prim|char]
- *              [--limiter minmod|mc|vanleer] [--emf contact|e0|arith]
+ *              [--limiter minmod|mc|vanleer] [--emf contact|e0|arith|uct_hll]
  *              [--pfloor P] [--report REPORT.json]
  *
  * STATE is one box in the boundary layout of the library (C order [z][y][x],
@@ -52,7 +52,7 @@ int main(int argc, char **argv) {
   static const char *const solvers[] = {"hlld", "hll"};
   static const char *const recs[] = {"prim", "char"};
   static const char *const lims[] = {"minmod", "mc", "vanleer"};
-  static const char *const emfs[] = {"contact", "e0", "arith"};
+  static const char *const emfs[] = {"contact", "e0", "arith", "uct_hll"};
   for (int i = 1; i < argc; i++) {
     const char *a = argv[i];
     if (i + 1 >= argc) die("missing value");
@@ -68,7 +68,7 @@ int main(int argc, char **argv) {
     else if (!strcmp(a, "--solver")) solver = pick(v, solvers, 2, "solver");
     else if (!strcmp(a, "--recon")) rec = pick(v, recs, 2, "recon");
     else if (!strcmp(a, "--limiter")) lim = pick(v, lims, 3, "limiter");
-    else if (!strcmp(a, "--emf")) emf = pick(v, emfs, 3, "emf");
+    else if (!strcmp(a, "--emf")) emf = pick(v, emfs, 4, "emf");
     else die("unknown option");
   }
   if (!in || !out || steps < 0) die("--in, --out and --steps are required");

@@ -22,8 +22,8 @@ _dp = C.POINTER(C.c_double)
 SOLVERS = {"hlld": 0, "hll": 1}
 # reconstructions (values of ORC_REC_PRIM / ORC_REC_CHAR)
 RECONS = {"prim": 0, "char": 1}
-# corner EMFs (values of ORC_EMF_CONTACT / ORC_EMF_E0 / ORC_EMF_ARITH)
-EMFS = {"contact": 0, "e0": 1, "arith": 2}
+# corner EMFs (values of ORC_EMF_CONTACT / ORC_EMF_E0 / ORC_EMF_ARITH / ORC_EMF_UCT_HLL)
+EMFS = {"contact": 0, "e0": 1, "arith": 2, "uct_hll": 3}
 # slope limiters (values of ORC_LIM_MINMOD / ORC_LIM_MC / ORC_LIM_VANLEER)
 LIMITERS = {"minmod": 0, "mc": 1, "vanleer": 2}
 
@@ -58,6 +58,8 @@ def _lib():
         lib.orc_set_emf.restype = C.c_int
         lib.orc_ct_corner_kind.argtypes = [C.c_int] + [C.c_double] * 4 + [_dp] + [C.c_double] * 4
         lib.orc_ct_corner_kind.restype = C.c_double
+        lib.orc_uct_hll.argtypes = [_dp] * 5
+        lib.orc_uct_hll.restype = C.c_double
         lib.orc_prim_eigen.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, _dp]
         lib.orc_slope.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp]
         lib.orc_set_limiter.argtypes = [C.c_void_p, C.c_int]
@@ -327,13 +329,21 @@ def ct_mass_flux(wl, wr, bn, gamma):
 
 
 def ct_corner(fa1, fa0, fb1, fb0, ec, ma1, ma0, mb1, mb0, kind="contact"):
+    if kind not in ("contact", "e0", "arith"):
+        raise ValueError("ct_corner averages face EMFs: contact, e0 or arith")
     ec = _vec(ec, 4)
     return _lib().orc_ct_corner_kind(EMFS[kind], fa1, fa0, fb1, fb0, _ptr(ec), ma1, ma0, mb1,
                                      mb0)
 
 
+def uct_hll(va, vb, ba, bb, alpha):
+    """Upwind-CT (HLL) corner EMF from the four corner states; see orc_uct_hll."""
+    va, vb, ba, bb, alpha = _vec(va, 4), _vec(vb, 4), _vec(ba, 2), _vec(bb, 2), _vec(alpha, 4)
+    return _lib().orc_uct_hll(_ptr(va), _ptr(vb), _ptr(ba), _ptr(bb), _ptr(alpha))
+
+
 __all__ = [
     "OracleBox", "cons_to_prim", "fast_speed", "minmod", "plm_face", "phys_flux", "hlld",
-    "hll", "ct_mass_flux", "ct_corner", "prim_eigen", "slope", "limit", "threads", "write_state", "read_state", "SOLVERS", "RECONS",
+    "hll", "ct_mass_flux", "ct_corner", "uct_hll", "prim_eigen", "slope", "limit", "threads", "write_state", "read_state", "SOLVERS", "RECONS",
     "EMFS", "LIMITERS",
 ]

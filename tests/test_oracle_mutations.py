@@ -80,6 +80,20 @@ MUTATIONS = [
     ("hll_upwind_term_sign", "f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;",
      "f[c] = (sr * fL[c] - sl * fR[c] - sl * sr * (uR[c] - uL[c])) * isd;",
      "test_oracle_scheme.py::test_hll_stationary_contact_closed_form"),
+    ("uct_diffusion_sign", "return num / (sa * sb) - apb * amb / sb * (ba[1] - ba[0]) +",
+     "return num / (sa * sb) + apb * amb / sb * (ba[1] - ba[0]) +",
+     "test_oracle_point.py::test_uct_hll_reduces_to_hll_along_each_axis "
+     "test_oracle_scheme.py::test_uct_hll_1d_equals_the_hll_face_flux"),
+    ("uct_weights_swapped", "double num = apa * apb * e[0] + ama * apb * e[1]",
+     "double num = ama * apb * e[0] + apa * apb * e[1]",
+     "test_oracle_point.py::test_uct_hll_upwind_uniform_and_mirror"),
+    ("uct_corner_slope_side", "return side == 0 ? q0 + 0.5 * d : q0 - 0.5 * d;",
+     "return side == 0 ? q0 - 0.5 * d : q0 + 0.5 * d;",
+     "test_oracle_scheme.py::test_uct_hll_1d_equals_the_hll_face_flux"),
+    ("uct_speed_bound_from_left_speed",
+     "alpha[2 * e] = speed_bound(b->SP[d][1][i0], b->SP[d][1][i1], 0);",
+     "alpha[2 * e] = speed_bound(b->SP[d][0][i0], b->SP[d][0][i1], 0);",
+     "test_oracle_scheme.py::test_uct_hll_1d_equals_the_hll_face_flux"),
 ]
 
 

@@ -514,3 +514,61 @@ def test_limiters_symmetric_and_odd():
             assert s == O.limit(b, a, name)
             assert -s == O.limit(-a, -b, name)
             assert (s == 0.0) == (a * b <= 0.0)
+
+
+# ---------------------------------------------------------------- upwind CT
+
+def _hll_1d(fl, fr, ul, ur, ap, am):
+    """HLL flux with right- / left-going bounds ap, am >= 0 (written out)."""
+    return (ap * fl + am * fr - ap * am * (ur - ul)) / (ap + am)
+
+
+def test_uct_hll_reduces_to_hll_along_each_axis():
+    """Corner states that do not change along b: the upwind-CT EMF is minus
+    the HLL flux along a of the b-field (flux of B_b along a: v_a B_b - v_b
+    B_a = -E_c), whatever the b speed bounds; likewise along b for states
+    that do not change along a (flux of B_a along b: E_c)."""
+    rng = np.random.default_rng(71)
+    for _ in range(500):
+        va_lo, va_hi, vb_lo, vb_hi = rng.normal(size=4)
+        bb_lo, bb_hi, ba = rng.normal(size=3)
+        ap, am, bp, bm = rng.uniform(0.05, 3.0, 4)
+        e = O.uct_hll([va_lo, va_hi, va_lo, va_hi], [vb_lo, vb_hi, vb_lo, vb_hi], [ba, ba],
+                      [bb_lo, bb_hi], [ap, am, bp, bm])
+        fl = va_lo * bb_lo - vb_lo * ba
+        fr = va_hi * bb_hi - vb_hi * ba
+        assert e == pytest.approx(-_hll_1d(fl, fr, bb_lo, bb_hi, ap, am), rel=1e-12, abs=1e-13)
+        # along b: states vary with sb only
+        ba_lo, ba_hi, bbv = rng.normal(size=3)
+        e = O.uct_hll([va_lo, va_lo, va_hi, va_hi], [vb_lo, vb_lo, vb_hi, vb_hi], [ba_lo, ba_hi],
+                      [bbv, bbv], [ap, am, bp, bm])
+        gl = vb_lo * ba_lo - va_lo * bbv
+        gr = vb_hi * ba_hi - va_hi * bbv
+        assert e == pytest.approx(_hll_1d(gl, gr, ba_lo, ba_hi, bp, bm), rel=1e-12, abs=1e-13)
+
+
+def test_uct_hll_upwind_uniform_and_mirror():
+    rng = np.random.default_rng(72)
+    for _ in range(500):
+        va, vb = rng.normal(size=4), rng.normal(size=4)
+        ba, bb = rng.normal(size=2), rng.normal(size=2)
+        al = rng.uniform(0.05, 3.0, 4)
+        # supersonic towards +a and +b: the lower-lower state alone
+        e = O.uct_hll(va, vb, ba, bb, [al[0], 0.0, al[2], 0.0])
+        assert e == pytest.approx(vb[0] * ba[0] - va[0] * bb[0], rel=1e-13, abs=1e-14)
+        # towards -a and -b: the upper-upper state alone
+        e = O.uct_hll(va, vb, ba, bb, [0.0, al[1], 0.0, al[3]])
+        assert e == pytest.approx(vb[3] * ba[1] - va[3] * bb[1], rel=1e-13, abs=1e-14)
+        # one state everywhere: the cell EMF
+        e = O.uct_hll([va[0]] * 4, [vb[0]] * 4, [ba[0]] * 2, [bb[0]] * 2, al)
+        assert e == pytest.approx(vb[0] * ba[0] - va[0] * bb[0], rel=1e-13, abs=1e-14)
+        # mirror a -> -a: lower and upper sides along a trade places, v_a and
+        # B_b change sign, the two a bounds swap; E_c is unchanged
+        e = O.uct_hll(va, vb, ba, bb, al)
+        m = [1, 0, 3, 2]
+        em = O.uct_hll(-va[m], vb[m], ba, -bb[::-1], [al[1], al[0], al[2], al[3]])
+        assert em == pytest.approx(e, rel=1e-12, abs=1e-13)
+        # mirror b -> -b
+        m = [2, 3, 0, 1]
+        em = O.uct_hll(va[m], -vb[m], -ba[::-1], bb, [al[0], al[1], al[3], al[2]])
+        assert em == pytest.approx(e, rel=1e-12, abs=1e-13)

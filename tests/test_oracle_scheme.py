@@ -112,7 +112,8 @@ def test_uniform_dt_closed_form():
     (3, 3, "hlld", "prim", "contact"), (4, 2, "hll", "prim", "contact"),
     (5, 3, "hll", "prim", "contact"), (6, 2, "hlld", "char", "contact"),
     (7, 3, "hll", "char", "contact"),
-    (8, 2, "hlld", "prim", "e0"), (9, 2, "hlld", "prim", "arith")])
+    (8, 2, "hlld", "prim", "e0"), (9, 2, "hlld", "prim", "arith"),
+    (10, 2, "hlld", "prim", "uct_hll"), (11, 3, "hll", "char", "uct_hll")])
 def test_conservation_divb_mean_field(seed, rk, solver, recon, emf):
     wl = W.random_smooth(n=(12, 10, 8), seed=seed)
     b = make(wl, rk=rk, solver=solver, recon=recon, emf=emf)
@@ -571,3 +572,79 @@ def test_limiters_alfven_second_order_and_invariants(limiter, recon):
         s1 = math.fsum(cons[q].ravel())
         assert abs(s1 - s0) <= 1e-13 * math.fsum(np.abs(wl.states[0].cons[q]).ravel())
     assert b.counters() == {"floor": 0, "hll": 0, "bad": 0}
+
+
+# ---------------------------------------------------------------- upwind CT
+
+def _brio_wu_1d(axis, n=96, gamma=2.0):
+    """Brio & Wu's shock tube along one axis (the others inactive), with a
+    second tangential component and a flow, so both corner EMFs of the axis
+    carry fluxes and some faces are supersonic."""
+    nn = [1, 1, 1]
+    nn[axis] = n
+    bc = [0, 0, 0]
+    bc[axis] = W.OUTFLOW
+    spec = W.BoxSpec(tuple(nn), bc=tuple(bc), gamma=gamma, cfl=0.4)
+    x = W.centres(spec, axis)
+    shp = (nn[2], nn[1], nn[0])
+    view = [1, 1, 1]
+    view[2 - axis] = n
+    left = (x < 0.5).reshape(view)
+    rho = np.broadcast_to(np.where(left, 1.0, 0.125), shp)
+    p = np.broadcast_to(np.where(left, 1.0, 0.1), shp)
+    vel = [0.0, 0.0, 0.0]
+    vel[axis] = np.broadcast_to(np.where(left, 1.2, -0.4), shp)
+    t1, t2 = (axis + 1) % 3, (axis + 2) % 3
+    bface = [None, None, None]
+    bface[axis] = np.full(W.face_shapes(spec)[axis], 0.75)
+    bface[t1] = np.broadcast_to(np.where(left, 1.0, -1.0), W.face_shapes(spec)[t1]).copy()
+    bface[t2] = np.broadcast_to(np.where(left, 0.5, 0.2), W.face_shapes(spec)[t2]).copy()
+    st = W.conserved(spec, rho, vel[0], vel[1], vel[2], p, bface)
+    return spec, st
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_uct_hll_1d_equals_the_hll_face_flux(axis):
+    """On a grid-aligned one-dimensional flow the corner states of the upwind
+    CT average are the face states of the sweep (corner velocities and the
+    transverse face fields carried with the same limited slopes) and its
+    speed bounds are the face's outer speeds, so the upwind-CT EMF is the HLL
+    flux of the tangential field at the face.  With the HLL solver at every
+    face, the contact-upwinded average returns that same face flux: both
+    schemes then agree to rounding (not bit for bit: the two formulas round
+    differently).  A sign, weight or side mistake in the upwind CT breaks
+    this."""
+    spec, st = _brio_wu_1d(axis)
+    out = {}
+    for emf in ("contact", "uct_hll"):
+        b = O.OracleBox(spec, solver="hll", emf=emf)
+        b.set_state(st.cons, st.bface)
+        _run_to(b, 0.1)
+        cons, bf, _ = b.get_state()
+        out[emf] = list(cons) + list(bf)
+        b.close()
+    for q, (a, c) in enumerate(zip(out["contact"], out["uct_hll"])):
+        scale = np.max(np.abs(a)) + 1e-300
+        assert np.max(np.abs(a - c)) <= 1e-11 * max(scale, 1.0), (q, np.max(np.abs(a - c)))
+    # the field did change (the tangential components are not trivial)
+    t1 = (axis + 1) % 3
+    assert np.max(np.abs(out["uct_hll"][5 + t1] - st.bface[t1])) > 0.1
+
+
+def test_uct_hll_uniform_conservation_alfven():
+    """Upwind CT: a uniform state stays unchanged bit for bit (with outflow
+    walls); mass, momentum, energy and the mean face field are conserved and
+    div B stays at rounding on a random smooth state; on the oblique
+    circularly polarised Alfven wave its errors match the contact-upwinded
+    average's within a few per cent and fall at the same rate."""
+    wl = W.uniform(n=(6, 5, 4), bc=(0, 1, 0))
+    b = make(wl, emf="uct_hll")
+    b.step(3)
+    cons, bf, _ = b.get_state()
+    for c, c0 in zip(list(cons) + list(bf), list(wl.states[0].cons) + list(wl.states[0].bface)):
+        assert np.array_equal(c, c0)
+    ns = [8, 16, 32]
+    uct = [_cp_error(W.cp_alfven_oblique(n), emf="uct_hll") for n in ns]
+    ct = [_cp_error(W.cp_alfven_oblique(n)) for n in ns]
+    assert all(abs(a / c - 1) < 0.05 for a, c in zip(uct, ct)), (uct, ct)
+    assert uct[2] < uct[1] < uct[0] and math.log2(uct[1] / uct[2]) > 1.2, uct

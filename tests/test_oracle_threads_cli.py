@@ -28,6 +28,7 @@ def run_threads(wl, steps, n, **kw):
     (W.random_smooth(n=(14, 11, 9), seed=71, bc=(1, 0, 1)), {}),
     (W.orszag_tang_2d(n=48), {"rk": 3, "solver": "hll", "recon": "char"}),
     (W.riemann_2d(n=40), {"limiter": "mc", "emf": "e0"}),
+    (W.random_smooth(n=(10, 9, 8), seed=73, bc=(0, 1, 1)), {"emf": "uct_hll", "limiter": "vanleer"}),
 ])
 def test_oracle_thread_count_does_not_change_results(wl, kw):
     try:
