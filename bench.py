@@ -737,10 +737,12 @@ def paper_workload(a, flags):
 def options_bench(a, flags):
     """Cost of the scheme options on the benchmark input (blast, n^3): the
     default (primitive slopes, HLLD, SSP-RK2, contact-upwinded corner EMFs)
-    against SSP-RK3, HLL at every face, characteristic slopes, the E0 and
-    arithmetic corner EMFs and the MC and van Leer limiters, FP64 and mixed; median of three repeats
-    of a.steps steps, per-launch kernel times, and the x sweep's algorithmic
-    HBM rate (its bytes do not depend on the options)."""
+    against SSP-RK3, HLL at every face, characteristic slopes, the E0,
+    arithmetic and upwind-CT corner EMFs and the MC and van Leer limiters,
+    FP64 and mixed; median of three repeats of a.steps steps, per-launch
+    kernel times, and the x sweep's algorithmic HBM rate (its bytes do not
+    depend on the options; the upwind CT adds the stores of the face wave
+    speeds)."""
     from paper_2606_12753_amd import mhd, workloads
     print(f"# options: building blast {a.n}^3 input", file=sys.stderr, flush=True)
     wl = workloads.blast_3d(n=a.n)
@@ -751,6 +753,7 @@ def options_bench(a, flags):
             ("char", dict(rk=2, solver="hlld", recon="char", emf="contact")),
             ("emf_e0", dict(rk=2, solver="hlld", recon="prim", emf="e0")),
             ("emf_arith", dict(rk=2, solver="hlld", recon="prim", emf="arith")),
+            ("emf_uct_hll", dict(rk=2, solver="hlld", recon="prim", emf="uct_hll")),
             ("limiter_mc", dict(rk=2, solver="hlld", recon="prim", emf="contact", limiter="mc")),
             ("limiter_vanleer", dict(rk=2, solver="hlld", recon="prim", emf="contact",
                                      limiter="vanleer"))]

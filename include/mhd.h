@@ -8,7 +8,8 @@
  * field; Runge-Kutta stepping.  Concretely: PLM reconstruction (minmod, MC
  * or van Leer slopes of primitive or characteristic variables), HLLD fluxes
  * with HLL fallback (or HLL alone), the flux-divergence update, CT corner
- * EMFs (contact-upwinded, E0 or arithmetic average) with the face-field
+ * EMFs (contact-upwinded, E0 or arithmetic average, or upwind CT) with the
+ * face-field
  * update, the CFL time step from a max-reduction of the fast magnetosonic
  * rate and the SSP Runge-Kutta stage combines (two or three stages), on 3D
  * structured boxes (2D and 1D as boxes with inactive axes of one cell).
@@ -84,6 +85,13 @@ extern "C" {
                              its two sides */
 #define MHD_EMF_ARITH 2   /* mean of the four face EMFs (Balsara & Spicer
                              1999) */
+#define MHD_EMF_UCT_HLL 3 /* upwind CT (Londrillo & Del Zanna 2004, HLL
+                             form): the two-dimensional HLL flux of the four
+                             corner states (cell velocities and face fields
+                             carried to the corner with limited slopes),
+                             with speed bounds from the outer wave speeds of
+                             the adjacent faces; the face EMFs are not used.
+                             Needs two more face arrays per axis. */
 
 /* where caller arrays live */
 #define MHD_HOST 0
@@ -139,7 +147,8 @@ typedef struct {
                               workspace) */
   int32_t riemann;         /* MHD_RS_HLLD (0) or MHD_RS_HLL */
   int32_t recon;           /* MHD_REC_PRIM (0) or MHD_REC_CHAR */
-  int32_t ct_emf;          /* MHD_EMF_CONTACT (0), MHD_EMF_E0 or MHD_EMF_ARITH */
+  int32_t ct_emf;          /* MHD_EMF_CONTACT (0), MHD_EMF_E0, MHD_EMF_ARITH
+                              or MHD_EMF_UCT_HLL */
   int32_t limiter;         /* MHD_LIM_MINMOD (0), MHD_LIM_MC or MHD_LIM_VANLEER */
 } mhd_config;
 

@@ -73,6 +73,8 @@ struct Box {
                       // mixed path rounds it to FP32 once; the RK combine
                       // itself is FP64)
   void* ED[3];        // corner EMF along each axis
+  void* SP[3][2];     // outer wave speeds S_L, S_R on the faces normal to
+                      // each axis (upwind CT only; null otherwise)
   double* lam;        // per-tile max CFL rate (length: max(x tiles, cell tiles))
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
@@ -80,7 +82,9 @@ struct Box {
   int ctx;            // corner-EMF kernel: tile width along x (kTPB / ctx
                       // rows), 0 for flat order
   int emf;            // corner EMF: 0 contact-upwinded, 1 E0 (derivatives
-                      // averaged), 2 mean of the four face EMFs
+                      // averaged), 2 mean of the four face EMFs, 3 upwind CT
+  int lim;            // slope limiter (0 minmod, 1 MC, 2 van Leer), for the
+                      // upwind-CT corner states
   int ysl, yseg;      // y march: cells per segment, segments
   int zsl, zseg;      // z march
   int ntile[6];       // tiles per kernel kind
@@ -631,8 +635,8 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 // Riemann flux at one face.  RS = 0: HLLD, HLL when the HLLD star states are
 // not physical; RS = 1: HLL at every face.  f[7] = (mass, mom n, mom t1,
 // mom t2, energy, B_t1, B_t2); *fm is the mass flux handed to the CT
-// upwinding (zero when zero up to rounding).  Returns 1 when HLLD fell back
-// to HLL.
+// upwinding (zero when zero up to rounding); sp = (S_L, S_R), the outer wave
+// speeds (read by the upwind CT).  Returns 1 when HLLD fell back to HLL.
 //
 // The flux of the Riemann fan at x/t = 0 lies on the side of the contact
 // given by sign(S_M): the solver computes both single-star states (both
@@ -641,7 +645,8 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 // is left of (right of) x/t = 0, with selects instead of divergent branches.
 template <typename real, int RS>
 __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr, real bn,
-                                       real gamma, real igm1, real* f, real* fm) {
+                                       real gamma, real igm1, real* f, real* fm,
+                                       real* sp) {
   // max(c_fL, c_fR) as the square root of the larger square: a correctly
   // rounded square root is monotone, so this is the same value with one
   // square root fewer
@@ -758,6 +763,8 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
   }
   real thr = Eps<real>::mflux * (wl.v[0] + wr.v[0]) * (ab(sl) + ab(sr));
   *fm = ab(f[0]) <= thr ? (real)0 : f[0];
+  sp[0] = sl;
+  sp[1] = sr;
   return used;
 }
 
@@ -997,8 +1004,12 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         }
         const int fi = fidx(b, 0, f, j, k);
         const real bn = (real)ld<double>(b.B[s][0], fi);
-        real F[7], fm;
-        const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
+        real F[7], fm, sp[2];
+        const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
+        if (b.emf == 3) {
+          st<real>(b.SP[0][0], fi, sp[0]);
+          st<real>(b.SP[0][1], fi, sp[1]);
+        }
         st<real>(b.FX[0], fi, F[0]);
         st<real>(b.FX[1], fi, F[1]);
         st<real>(b.FX[2], fi, F[2]);
@@ -1262,8 +1273,8 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     // face index f along D is in [0, n]; periodic face n is face 0
     const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
     const real bn = (real)ld<double>(b.B[s][D], fi);
-    real F[7], fm;
-    const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm);
+    real F[7], fm, sp[2];
+    const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
     // lab-frame hydro flux: (rho, mx, my, mz, E)
     real fl[kNQ];
     fl[0] = F[0];
@@ -1274,6 +1285,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
       st<real>(b.EF[D][0], fi, F[6]);
       st<real>(b.EF[D][1], fi, -F[5]);
       st<real>(b.MF[D], fi, fm);
+      if (b.emf == 3) {
+        st<real>(b.SP[D][0], fi, sp[0]);
+        st<real>(b.SP[D][1], fi, sp[1]);
+      }
       if (used) atomicAdd(&b.cnt[1], 1ull);
     }
     if (f > j0) {
@@ -1422,6 +1437,164 @@ __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   pos[1] = by * cy + (int)threadIdx.x / cx;
   pos[2] = r / nby;
   return pos[0] < b.nf[0] && pos[1] < b.nf[1];
+}
+
+// Slope limiter chosen at run time (the upwind-CT corner states).
+template <typename real>
+__device__ __forceinline__ real limit_rt(int lim, real a, real b) {
+  if (lim == 1) return limit<1>(a, b);
+  if (lim == 2) return limit<2>(a, b);
+  return limit<0>(a, b);
+}
+
+// Value q0 of a cell carried half a cell towards a corner: up (side 0, the
+// cell lies below the corner) or down (side 1), with its limited slope
+// between the neighbours qm and qp; no slope along an inactive axis.
+template <typename real>
+__device__ __forceinline__ real to_corner(int lim, int act, int side, real qm, real q0, real qp) {
+  const real d = act ? limit_rt(lim, q0 - qm, qp - q0) : (real)0;
+  return side == 0 ? q0 + (real)0.5 * d : q0 - (real)0.5 * d;
+}
+
+// Largest right-going (left = 0) or left-going (left = 1) signal speed of
+// two faces' outer wave speeds, at least zero.
+template <typename real>
+__device__ __forceinline__ real speed_bound(real s0, real s1, int left) {
+  if (left) {
+    const real m = s0 < s1 ? s0 : s1;
+    return m < (real)0 ? -m : (real)0;
+  }
+  const real m = s0 > s1 ? s0 : s1;
+  return m > (real)0 ? m : (real)0;
+}
+
+// Upwind-CT corner EMF along c (Londrillo & Del Zanna 2004, HLL form) at
+// corner position pos (a-face index pos[a], b-face index pos[b], (a, b, c)
+// cyclic) of state s.  The four cells around the edge give four corner
+// states: their velocities along a and b carried to the corner with the
+// limited slopes along a, then b.  The a-face field of the two a-faces at
+// the corner is carried along b, the b-face field along a.  Speed bounds:
+// the outer wave speeds of the same faces.  The corner EMF is the HLL flux
+// of the four states along both axes, E_c = v_b B_a - v_a B_b of each
+// weighted by the bound towards it, plus the HLL diffusion of B_a along b and
+// of B_b along a.  An inactive axis has equal states on both sides and
+// weights 1.
+template <typename real>
+__device__ __forceinline__ real uct_corner(CBox& b, int s, int c, const int pos[3]) {
+  const int a = (c + 1) % 3, bb = (c + 2) % 3;
+  const int lim = b.lim;
+  // mapped indices pos - 2 .. pos + 1 along a and b (map_cell wraps a
+  // periodic axis by one period only, which covers two cells when n >= 2;
+  // an axis of one cell maps everything to cell 0)
+  int ma[4], mb[4];
+#pragma unroll
+  for (int o = 0; o < 4; o++) {
+    ma[o] = b.n[a] == 1 ? 0 : map_cell(pos[a] - 2 + o, b.n[a], b.per[a]);
+    mb[o] = b.n[bb] == 1 ? 0 : map_cell(pos[bb] - 2 + o, b.n[bb], b.per[bb]);
+  }
+  real al[4] = {(real)1, (real)1, (real)1, (real)1};
+  int q[3];
+  q[c] = pos[c];
+  if (b.act[a]) {  // a-faces (ia; ib-1), (ia; ib)
+    q[a] = pos[a];
+    q[bb] = mb[1];
+    const int f0 = fidx(b, a, q[0], q[1], q[2]);
+    q[bb] = mb[2];
+    const int f1 = fidx(b, a, q[0], q[1], q[2]);
+    al[0] = speed_bound(ld<real>(b.SP[a][1], f0), ld<real>(b.SP[a][1], f1), 0);
+    al[1] = speed_bound(ld<real>(b.SP[a][0], f0), ld<real>(b.SP[a][0], f1), 1);
+  }
+  if (b.act[bb]) {  // b-faces (ib; ia-1), (ib; ia)
+    q[bb] = pos[bb];
+    q[a] = ma[1];
+    const int f0 = fidx(b, bb, q[0], q[1], q[2]);
+    q[a] = ma[2];
+    const int f1 = fidx(b, bb, q[0], q[1], q[2]);
+    al[2] = speed_bound(ld<real>(b.SP[bb][1], f0), ld<real>(b.SP[bb][1], f1), 0);
+    al[3] = speed_bound(ld<real>(b.SP[bb][0], f0), ld<real>(b.SP[bb][0], f1), 1);
+  }
+  // velocities along a and b of the cells (ma[oa], mb[ob]); the corners of
+  // the 4 x 4 block are not needed
+  real va[4][4], vb[4][4];
+#pragma unroll
+  for (int oa = 0; oa < 4; oa++)
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++) {
+      va[oa][ob] = vb[oa][ob] = (real)0;
+      if ((oa == 0 || oa == 3) && (ob == 0 || ob == 3)) continue;
+      q[a] = ma[oa];
+      q[bb] = mb[ob];
+      const int ci = cidx(b, q[0], q[1], q[2]);
+      const double ir = 1.0 / ld<double>(b.U[s][0], ci);
+      va[oa][ob] = (real)(ld<double>(b.U[s][1 + a], ci) * ir);
+      vb[oa][ob] = (real)(ld<double>(b.U[s][1 + bb], ci) * ir);
+    }
+  real cva[4], cvb[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int sa = k & 1, sb = k >> 1, oa = 1 + sa, ob = 1 + sb;
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+      real (*v)[4] = e == 0 ? va : vb;
+      const real v0 = v[oa][ob];
+      real x = to_corner(lim, b.act[a], sa, v[oa - 1][ob], v0, v[oa + 1][ob]);
+      const real db = b.act[bb] ? limit_rt(lim, v0 - v[oa][ob - 1], v[oa][ob + 1] - v0) : (real)0;
+      x = sb == 0 ? x + (real)0.5 * db : x - (real)0.5 * db;
+      if (e == 0)
+        cva[k] = x;
+      else
+        cvb[k] = x;
+    }
+  }
+  real fa[2], fb[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; s2++) {
+    q[c] = pos[c];
+    q[a] = pos[a];  // a-face (ia; ib-1+s2), carried along b
+    real g[3];
+#pragma unroll
+    for (int o = 0; o < 3; o++) {
+      q[bb] = mb[s2 + o];
+      g[o] = (real)ld<double>(b.B[s][a], fidx(b, a, q[0], q[1], q[2]));
+    }
+    fa[s2] = to_corner(lim, b.act[bb], s2, g[0], g[1], g[2]);
+    q[bb] = pos[bb];  // b-face (ib; ia-1+s2), carried along a
+#pragma unroll
+    for (int o = 0; o < 3; o++) {
+      q[a] = ma[s2 + o];
+      g[o] = (real)ld<double>(b.B[s][bb], fidx(b, bb, q[0], q[1], q[2]));
+    }
+    fb[s2] = to_corner(lim, b.act[a], s2, g[0], g[1], g[2]);
+  }
+  real e[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) e[k] = cvb[k] * fa[k >> 1] - cva[k] * fb[k & 1];
+  const real num = al[0] * al[2] * e[0] + al[1] * al[2] * e[1] + al[0] * al[3] * e[2] +
+                   al[1] * al[3] * e[3];
+  const real sa = al[0] + al[1], sb = al[2] + al[3];
+  return num / (sa * sb) - al[2] * al[3] / sb * (fa[1] - fa[0]) +
+         al[0] * al[1] / sa * (fb[1] - fb[0]);
+}
+
+// Upwind-CT corner EMFs (b.emf = 3), tiled like k_ct_edge: a kernel of its
+// own, so that the heavier gather of the upwind states does not raise the
+// register count of the face-EMF averages.
+template <typename real>
+__global__ __launch_bounds__(kTPB) void k_ct_uct(Launch L) {
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
+    const int bi = find_box(table(L.base) + kCTE * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
+    int pos[3];
+    if (!ct_pos(b, lt, pos)) continue;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      if (pos[c] >= b.n[c]) continue;
+      st<real>(b.ED[c], eidx(b, c, pos[0], pos[1], pos[2]), uct_corner<real>(b, L.stage, c, pos));
+    }
+  }
 }
 
 // Corner EMFs: for every corner position one lane computes the EMF along

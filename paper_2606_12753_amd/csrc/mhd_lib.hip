@@ -171,8 +171,8 @@ int validate_config(const mhd_config* cfg, std::string& err) {
     return MHD_E_INVAL;
   }
   if (cfg->ct_emf != MHD_EMF_CONTACT && cfg->ct_emf != MHD_EMF_E0 &&
-      cfg->ct_emf != MHD_EMF_ARITH) {
-    err = "config: ct_emf must be MHD_EMF_CONTACT, MHD_EMF_E0 or MHD_EMF_ARITH";
+      cfg->ct_emf != MHD_EMF_ARITH && cfg->ct_emf != MHD_EMF_UCT_HLL) {
+    err = "config: ct_emf must be MHD_EMF_CONTACT, MHD_EMF_E0, MHD_EMF_ARITH or MHD_EMF_UCT_HLL";
     return MHD_E_INVAL;
   }
   for (int b = 0; b < cfg->nboxes; b++) {
@@ -269,7 +269,7 @@ size_t backup_bytes_of(const Geom& g) {
 // stage states (SSP-RK3)
 int state_copies(const mhd_config* cfg) { return cfg->rk_stages == 3 ? 3 : 2; }
 
-size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies) {
+size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies, bool uct) {
   size_t s = 0;
   s += copies * mhd::kNQ * slot(g.N * 8);
   for (int d = 0; d < 3; d++) s += copies * slot(g.F[d] * 8);
@@ -278,6 +278,8 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies) {
   for (int d = 0; d < 3; d++) s += 3 * slot(g.F[d] * rs);  // EF x2 + MF
   s += mhd::kNQ * slot(g.N * rs);               // R
   for (int c = 0; c < 3; c++) s += slot(g.E[c] * rs);  // ED
+  if (uct)
+    for (int d = 0; d < 3; d++) s += 2 * slot(g.F[d] * rs);  // SP
   s += slot((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8);  // lam
   s += slot(4 * 8);                             // scal
   s += slot(3 * 8);                             // cnt
@@ -297,7 +299,7 @@ Plan make_plan(const mhd_config* cfg, int ysl, int zsl) {
   for (int b = 0; b < cfg->nboxes; b++) {
     Geom g = geom_of(cfg->boxes[b]);
     Tiling t = tiling_of(g, ysl, zsl, cfg->precision == MHD_FP64);
-    size_t bb = box_bytes(g, t, rs, state_copies(cfg));
+    size_t bb = box_bytes(g, t, rs, state_copies(cfg), cfg->ct_emf == MHD_EMF_UCT_HLL);
     p.box_off.push_back(off);
     p.box_bytes.push_back(bb);
     off += bb;
@@ -321,6 +323,7 @@ struct mhd_ctx {
   int rs = 0;  // Riemann solver (MHD_RS_*)
   int fz = 0;  // every box: one cell along z, more along y (no z march)
   int sl = 0;  // slope kind: recon + 2 * limiter (MHD_REC_*, MHD_LIM_*)
+  int uct = 0;  // corner EMFs by the upwind CT (MHD_EMF_UCT_HLL)
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -390,6 +393,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.fz = c->fz;
   sc.sl = c->sl;
   sc.xcd = c->var_xcd;
+  sc.uct = c->uct;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
   sc.ev = timing ? c->ev.data() : nullptr;
@@ -638,6 +642,11 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     }
     for (int q = 0; q < mhd::kNQ; q++) b.R[q] = take(g.N * rs);
     for (int cc = 0; cc < 3; cc++) b.ED[cc] = take(g.E[cc] * rs);
+    if (cfg->ct_emf == MHD_EMF_UCT_HLL)
+      for (int d = 0; d < 3; d++) {
+        b.SP[d][0] = take(g.F[d] * rs);
+        b.SP[d][1] = take(g.F[d] * rs);
+      }
     b.lam = reinterpret_cast<double*>(
         take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));
     b.scal = reinterpret_cast<double*>(take(4 * 8));
@@ -645,6 +654,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     b.xft = t.xft;
     b.ctx = t.ctx;
     b.emf = cfg->ct_emf;
+    b.lim = cfg->limiter;
     b.ysl = t.ysl;
     b.yseg = t.yseg;
     b.zsl = t.zsl;
@@ -802,6 +812,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->rk = cfg->rk_stages == 3 ? 3 : 2;
   c->rs = cfg->riemann;
   c->sl = cfg->recon + 2 * cfg->limiter;
+  c->uct = cfg->ct_emf == MHD_EMF_UCT_HLL;
   c->fz = 1;
   for (int b = 0; b < cfg->nboxes; b++)
     if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;

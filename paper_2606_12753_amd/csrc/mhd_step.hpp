@@ -33,6 +33,7 @@ struct StepCtx {
                        // the y march completes each stage, no z march
   int xcd;             // XCD-grouped tile order, bit k for kernel kind k
                        // (kXS .. kCTF)
+  int uct;             // corner EMFs by the upwind CT (k_ct_uct)
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
   int* ev_kind;        // timing: kernel kind of each pair
@@ -166,7 +167,10 @@ inline int enqueue_step_sl(const StepCtx& sc) {
     L.ntiles = sc.total[kCTE];
     L.xcd = (sc.xcd >> kCTE) & 1;
     mark(MHD_K_CT_EDGE, true);
-    hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+    if (sc.uct)
+      hipLaunchKernelGGL(k_ct_uct<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+    else
+      hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
     mark(MHD_K_CT_EDGE, false);
     L.ntiles = sc.total[kCTF];
     L.xcd = (sc.xcd >> kCTF) & 1;

@@ -45,7 +45,9 @@ RECONS = {"prim": MHD_REC_PRIM, "char": MHD_REC_CHAR}
 MHD_EMF_CONTACT = 0
 MHD_EMF_E0 = 1
 MHD_EMF_ARITH = 2
-EMFS = {"contact": MHD_EMF_CONTACT, "e0": MHD_EMF_E0, "arith": MHD_EMF_ARITH}
+MHD_EMF_UCT_HLL = 3
+EMFS = {"contact": MHD_EMF_CONTACT, "e0": MHD_EMF_E0, "arith": MHD_EMF_ARITH,
+        "uct_hll": MHD_EMF_UCT_HLL}
 MHD_LIM_MINMOD = 0
 MHD_LIM_MC = 1
 MHD_LIM_VANLEER = 2

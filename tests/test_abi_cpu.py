@@ -95,11 +95,16 @@ def test_validation_before_device(lib):
     with pytest.raises(mhd.MhdError) as ei:
         mhd.mhd_workspace_bytes([])
     assert ei.value.code == mhd.MHD_E_INVAL
-    for kw in ({"rk": 4}, {"solver": 2}, {"recon": 2}, {"emf": 3}, {"limiter": 3}):
+    for kw in ({"rk": 4}, {"solver": 2}, {"recon": 2}, {"emf": 4}, {"emf": -1}, {"limiter": 3}):
         with pytest.raises(mhd.MhdError) as ei:
             mhd.mhd_workspace_bytes([good], **kw)
         assert ei.value.code == mhd.MHD_E_INVAL, kw
     assert mhd.mhd_workspace_bytes([good], solver="hll") == nbytes
+    # the upwind CT keeps the outer wave speeds of every face: two more face
+    # arrays per axis, in the arithmetic type of the path
+    uct = mhd.mhd_workspace_bytes([good], emf="uct_hll")
+    assert uct > nbytes
+    assert mhd.mhd_workspace_bytes([good], emf="uct_hll", precision=mhd.MHD_MIXED) < uct
     # the largest accepted box: 2^29 cells (periodic), and one active axis
     big = mhd.mhd_workspace_bytes([W.BoxSpec((1024, 1024, 512))])
     assert big > (1 << 29) * 8 * 16

@@ -218,13 +218,14 @@ def test_char_reconstruction_fp64(n, bc, rk, solver, flags):
     assert_fp64_parity(g, o, f"char {n} {bc} rk{rk} {solver}")
 
 
-@pytest.mark.parametrize("emf", ["e0", "arith"])
+@pytest.mark.parametrize("emf", ["e0", "arith", "uct_hll"])
 @pytest.mark.parametrize("n,bc,recon", [((30, 26, 22), (1, 0, 0), "prim"),
                                         ((24, 20, 1), (0, 1, 0), "char"),
                                         ((9, 1, 40), (1, 0, 1), "prim")])
 def test_corner_emf_kinds_fp64(n, bc, recon, emf):
-    """E0 and arithmetic corner EMFs: bit for bit with the oracle (3D, 2D
-    with the fused y march, and a box with one inactive axis)."""
+    """E0, arithmetic and upwind-CT corner EMFs: bit for bit with the
+    oracle (3D, 2D with the fused y march, and a box with one inactive
+    axis; outflow walls on each axis)."""
     wl = W.random_smooth(n=n, seed=sum(n) + len(emf), bc=bc)
     g = gpu_run(wl, 4, flags=mhd.MHD_F_GRAPH, recon=recon, emf=emf)[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, recon=recon, emf=emf)
@@ -264,7 +265,7 @@ def test_limiters_shocks_and_mixed():
 def test_corner_emf_kinds_orszag_tang_and_mixed():
     wl = W.orszag_tang_2d(n=64)
     spec = wl.boxes[0]
-    for emf in ("e0", "arith"):
+    for emf in ("e0", "arith", "uct_hll"):
         o = oracle_run(spec, wl.states[0], 40, emf=emf)
         g = gpu_run(wl, 40, flags=mhd.MHD_F_GRAPH, emf=emf)[0]
         assert_fp64_parity(g, o, f"OT2D {emf}")
@@ -823,3 +824,35 @@ def test_autotune_restores_state_and_matches():
     assert t == ref[2] and cnt == ref[3]
     for a, b in zip(cons + bface, ref[0] + ref[1]):
         assert np.array_equal(a, b)
+
+
+UCT_OPTIONS = dict(rk=3, solver="hlld", recon="prim", limiter="vanleer", emf="uct_hll")
+
+
+def test_upwind_ct_ensemble_and_blast():
+    """Upwind CT in an ensemble of 3D, 2D and 1D boxes with outflow walls
+    (SSP-RK3, van Leer slopes, graph replay, persistent grid) and through
+    the strong shocks of a small blast: bit for bit with the oracle; the
+    mixed path within its bar, div B at rounding."""
+    boxes, states = [], []
+    for n, seed, bc in [((22, 17, 13), 51, (1, 0, 0)), ((31, 19, 1), 52, (0, 1, 0)),
+                        ((1, 36, 1), 53, (0, 1, 0))]:
+        w = W.random_smooth(n=n, seed=seed, bc=bc)
+        boxes += w.boxes
+        states += w.states
+    wl = W.Workload("mix-uct", boxes, states, 3)
+    res = gpu_run(wl, 3, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT, **UCT_OPTIONS)
+    for i, g in enumerate(res):
+        o = oracle_run(boxes[i], states[i], 3, **UCT_OPTIONS)
+        assert_fp64_parity(g, o, f"uct box {i}")
+    wl2 = W.blast_3d(n=24)
+    spec2, st2 = wl2.boxes[0], wl2.states[0]
+    o = oracle_run(spec2, st2, 20, emf="uct_hll")
+    g = gpu_run(wl2, 20, flags=mhd.MHD_F_GRAPH, emf="uct_hll")[0]
+    assert_fp64_parity(g, o, "blast uct")
+    m = gpu_run(wl2, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, emf="uct_hll")[0]
+    mp, mb = pressure_bmag(spec2, m[0], m[1])
+    op, ob = pressure_bmag(spec2, o[0], o[1])
+    for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
+        assert rel_l1(a, b) <= TOLMIX, name
+    assert divb_norm(spec2, m[1])[0] <= 1e-12
