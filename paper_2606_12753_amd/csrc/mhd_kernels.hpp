@@ -75,6 +75,8 @@ struct Box {
   void* ED[3];        // corner EMF along each axis
   void* SP[3][2];     // outer wave speeds S_L, S_R on the faces normal to
                       // each axis (upwind CT only; null otherwise)
+  void* V[3];         // cell velocity, written by the x sweep (upwind CT
+                      // only; null otherwise)
   double* lam;        // per-tile max CFL rate (length: max(x tiles, cell tiles))
   double* scal;       // [0] dt, [1] t, [2] t_stop, [3] dt of the current state
   unsigned long long* cnt;  // [0] floor hits, [1] HLL fallbacks, [2] bad cells
@@ -954,6 +956,11 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
           st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
           st<real>(b.Ec[2], c, (real)(w.vy * w.bx - w.vx * w.by));
+          if (b.emf == 3) {
+            st<real>(b.V[0], c, (real)w.vx);
+            st<real>(b.V[1], c, (real)w.vy);
+            st<real>(b.V[2], c, (real)w.vz);
+          }
           if (fl) count(b.cnt, fl);
           if (L.lam) {
             const double l = cfl_rate(b, w);
@@ -1040,6 +1047,11 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
           st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
           st<real>(b.Ec[1], c, (real)ecy);
           st<real>(b.Ec[2], c, (real)ecz);
+          if (b.emf == 3) {
+            st<real>(b.V[0], c, (real)w.vx);
+            st<real>(b.V[1], c, (real)w.vy);
+            st<real>(b.V[2], c, (real)w.vz);
+          }
           if (fl) count(b.cnt, fl);
           if (L.lam) {
             const double l = cfl_rate(b, w);
@@ -1513,8 +1525,8 @@ __device__ __forceinline__ real uct_corner(CBox& b, int s, int c, const int pos[
     al[2] = speed_bound(ld<real>(b.SP[bb][1], f0), ld<real>(b.SP[bb][1], f1), 0);
     al[3] = speed_bound(ld<real>(b.SP[bb][0], f0), ld<real>(b.SP[bb][0], f1), 1);
   }
-  // velocities along a and b of the cells (ma[oa], mb[ob]); the corners of
-  // the 4 x 4 block are not needed
+  // velocities along a and b of the cells (ma[oa], mb[ob]), as the x sweep
+  // recovered them; the corners of the 4 x 4 block are not needed
   real va[4][4], vb[4][4];
 #pragma unroll
   for (int oa = 0; oa < 4; oa++)
@@ -1525,9 +1537,8 @@ __device__ __forceinline__ real uct_corner(CBox& b, int s, int c, const int pos[
       q[a] = ma[oa];
       q[bb] = mb[ob];
       const int ci = cidx(b, q[0], q[1], q[2]);
-      const double ir = 1.0 / ld<double>(b.U[s][0], ci);
-      va[oa][ob] = (real)(ld<double>(b.U[s][1 + a], ci) * ir);
-      vb[oa][ob] = (real)(ld<double>(b.U[s][1 + bb], ci) * ir);
+      va[oa][ob] = ld<real>(b.V[a], ci);
+      vb[oa][ob] = ld<real>(b.V[bb], ci);
     }
   real cva[4], cvb[4];
 #pragma unroll

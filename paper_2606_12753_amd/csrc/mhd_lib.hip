@@ -278,8 +278,10 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies, bool uct
   for (int d = 0; d < 3; d++) s += 3 * slot(g.F[d] * rs);  // EF x2 + MF
   s += mhd::kNQ * slot(g.N * rs);               // R
   for (int c = 0; c < 3; c++) s += slot(g.E[c] * rs);  // ED
-  if (uct)
+  if (uct) {
     for (int d = 0; d < 3; d++) s += 2 * slot(g.F[d] * rs);  // SP
+    s += 3 * slot(g.N * rs);                                 // V
+  }
   s += slot((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8);  // lam
   s += slot(4 * 8);                             // scal
   s += slot(3 * 8);                             // cnt
@@ -646,6 +648,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
       for (int d = 0; d < 3; d++) {
         b.SP[d][0] = take(g.F[d] * rs);
         b.SP[d][1] = take(g.F[d] * rs);
+        b.V[d] = take(g.N * rs);
       }
     b.lam = reinterpret_cast<double*>(
         take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));
