@@ -735,6 +735,27 @@ int copy_faces(mhd_ctx* c, const Geom& g, int d, double* dst, const double* src,
     }
     return MHD_OK;
   }
+  if (kind != hipMemcpyDeviceToDevice) {
+    // host side: rows are packed or unpacked on the host around one plain
+    // copy, so that no pitched copy touches pageable host memory (a pitched
+    // copy may be staged through whole pitch spans and write the face-n
+    // column of the rows it skips)
+    const size_t wd = width / 8, ip = int_pitch / 8, ep = ext_pitch / 8, fw = d == 0 ? 1 : nx;
+    std::vector<double> tmp(rows * ip);
+    if (to_internal) {
+      for (size_t r = 0; r < rows; r++) std::memcpy(&tmp[r * ip], src + r * ep, width);
+      HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), rows * int_pitch, kind, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+      HIPCHK(c, hipMemcpyAsync(tmp.data(), src, rows * int_pitch, kind, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (size_t r = 0; r < rows; r++) {
+        std::memcpy(dst + r * ep, &tmp[r * ip], width);
+        std::memcpy(dst + r * ep + wd, &tmp[r * ip], fw * 8);  // face n = face 0
+      }
+    }
+    return MHD_OK;
+  }
   if (to_internal) {
     HIPCHK(c, hipMemcpy2DAsync(dst, int_pitch, src, ext_pitch, width, rows, kind, c->stream));
   } else {
