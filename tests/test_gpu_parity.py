@@ -505,6 +505,40 @@ def test_set_get_roundtrip_host_and_device():
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("n", [(33, 17, 9), (8, 40, 1), (1, 12, 30), (64, 64, 64)])
+def test_periodic_faces_host_copies(n):
+    """Host copies of periodic face arrays: after steps the returned arrays
+    hold face n equal to face 0 on every periodic axis, equal to what a
+    device-side get_state returns, and a second host read (into arrays that
+    already hold data) gives the same bits."""
+    import torch
+    wl = W.random_smooth(n=n, seed=sum(n), bc=(0, 0, 0))
+    spec, st = wl.boxes[0], wl.states[0]
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        sim.step(3)
+        cons, bface, _ = sim.get_state(0)
+        oc = [torch.empty(a.shape, dtype=torch.float64, device="cuda") for a in st.cons]
+        obf = [torch.empty(a.shape, dtype=torch.float64, device="cuda") for a in st.bface]
+        sim.get_state(0, out=(oc, obf))
+        torch.cuda.synchronize()
+        again = ([np.full(a.shape, np.nan) for a in st.cons], [np.full(a.shape, 7.0) for a in st.bface])
+        sim.get_state(0, out=again)
+    for d in range(3):
+        f = bface[d]
+        if d == 0:
+            assert np.array_equal(f[:, :, -1], f[:, :, 0])
+        elif d == 1:
+            assert np.array_equal(f[:, -1, :], f[:, 0, :])
+        else:
+            assert np.array_equal(f[-1], f[0])
+        assert np.array_equal(f, obf[d].cpu().numpy())
+        assert np.array_equal(f, again[1][d])
+    for a, b, c in zip(cons, oc, again[0]):
+        assert np.array_equal(a, b.cpu().numpy()) and np.array_equal(a, c)
+    assert divb_norm(spec, bface)[0] <= 1e-12
+
+
 def test_periodic_face_mismatch_rejected():
     import torch
     wl = W.random_smooth(n=(8, 8, 8), seed=12)
