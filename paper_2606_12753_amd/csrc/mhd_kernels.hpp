@@ -953,11 +953,10 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         if constexpr (REC) sw[7][sidx] = (real)w.bx;
         if (own && i >= 0 && i < nx) {
           const int c = cidx(b, i, j, k);
-          if (b.emf != 3) {  // the upwind CT reads velocities, not EMFs
-            st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
-            st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
-            st<real>(b.Ec[2], c, (real)(w.vy * w.bx - w.vx * w.by));
-          } else {
+          st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
+          st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
+          st<real>(b.Ec[2], c, (real)(w.vy * w.bx - w.vx * w.by));
+          if (b.emf == 3) {
             st<real>(b.V[0], c, (real)w.vx);
             st<real>(b.V[1], c, (real)w.vy);
             st<real>(b.V[2], c, (real)w.vz);
@@ -1023,11 +1022,9 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         st<real>(b.FX[2], fi, F[2]);
         st<real>(b.FX[3], fi, F[3]);
         st<real>(b.FX[4], fi, F[4]);
-        if (b.emf != 3) {
-          st<real>(b.EF[0][0], fi, F[6]);
-          st<real>(b.EF[0][1], fi, -F[5]);
-          st<real>(b.MF[0], fi, fm);
-        }
+        st<real>(b.EF[0][0], fi, F[6]);
+        st<real>(b.EF[0][1], fi, -F[5]);
+        st<real>(b.MF[0], fi, fm);
         if (used) atomicAdd(&b.cnt[1], 1ull);
       }
     } else {
@@ -1042,18 +1039,15 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         const double ecy = w.vx * w.bz - w.vz * w.bx;
         const double ecz = w.vy * w.bx - w.vx * w.by;
         const int fi = fidx(b, 0, f, j, k);
-        if (b.emf != 3) {
-          st<real>(b.EF[0][0], fi, (real)ecy);
-          st<real>(b.EF[0][1], fi, (real)ecz);
-          st<real>(b.MF[0], fi, (real)ld<double>(b.U[s][1], cidx(b, im, j, k)));
-        }
+        st<real>(b.EF[0][0], fi, (real)ecy);
+        st<real>(b.EF[0][1], fi, (real)ecz);
+        st<real>(b.MF[0], fi, (real)ld<double>(b.U[s][1], cidx(b, im, j, k)));
         if (f == 0) {
           const int c = cidx(b, 0, j, k);
-          if (b.emf != 3) {
-            st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
-            st<real>(b.Ec[1], c, (real)ecy);
-            st<real>(b.Ec[2], c, (real)ecz);
-          } else {
+          st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
+          st<real>(b.Ec[1], c, (real)ecy);
+          st<real>(b.Ec[2], c, (real)ecz);
+          if (b.emf == 3) {
             st<real>(b.V[0], c, (real)w.vx);
             st<real>(b.V[1], c, (real)w.vy);
             st<real>(b.V[2], c, (real)w.vz);
@@ -1300,11 +1294,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     if (D == 1) { fl[2] = F[1]; fl[3] = F[2]; fl[1] = F[3]; }
     else { fl[3] = F[1]; fl[1] = F[2]; fl[2] = F[3]; }
     if (f < j1 || (f == n && extra)) {
-      if (b.emf != 3) {
-        st<real>(b.EF[D][0], fi, F[6]);
-        st<real>(b.EF[D][1], fi, -F[5]);
-        st<real>(b.MF[D], fi, fm);
-      } else {
+      st<real>(b.EF[D][0], fi, F[6]);
+      st<real>(b.EF[D][1], fi, -F[5]);
+      st<real>(b.MF[D], fi, fm);
+      if (b.emf == 3) {
         st<real>(b.SP[D][0], fi, sp[0]);
         st<real>(b.SP[D][1], fi, sp[1]);
       }
@@ -1322,7 +1315,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
         else
           st<real>(b.R[q], cprev, (real)r);
       }
-      if (FZ && b.emf != 3) {
+      if constexpr (FZ) {
         // z faces of the cell (one cell along z: no z flux divergence): the
         // face EMFs are the cell EMF and the mass flux is the momentum
         const real ex = ld<real>(b.Ec[0], cprev), ey = ld<real>(b.Ec[1], cprev);
@@ -1359,11 +1352,9 @@ __device__ __forceinline__ void inactive_column(CBox& b, int s, int dst, int com
     int fi_, fj_, fk_;
     pos(f, fi_, fj_, fk_);
     const int fi = fidx(b, D, fi_, fj_, fk_);
-    if (b.emf != 3) {
-      st<real>(b.EF[D][0], fi, ld<real>(b.Ec[t1], c));
-      st<real>(b.EF[D][1], fi, ld<real>(b.Ec[t2], c));
-      st<real>(b.MF[D], fi, (real)ld<double>(b.U[s][1 + D], c));
-    }
+    st<real>(b.EF[D][0], fi, ld<real>(b.Ec[t1], c));
+    st<real>(b.EF[D][1], fi, ld<real>(b.Ec[t2], c));
+    st<real>(b.MF[D], fi, (real)ld<double>(b.U[s][1 + D], c));
   }
   int ci, cj, ck;
   pos(0, ci, cj, ck);
