@@ -823,8 +823,8 @@ def main():
         ingest_sq(a)
         return
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
-              "(the multi-GPU path is a design, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
+              "(sharding across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2606_12753_amd import mhd, workloads

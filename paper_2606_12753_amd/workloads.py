@@ -10,8 +10,8 @@ bits.  It holds none of the scheme's arithmetic.
 Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64) drawn in
 C order (z, y, x).  The paper (arXiv 2606.12753 §2.2.3) names its test
 problems (3D Orszag-Tang, 2D Riemann) but prints no initial data, so the
-recipes below are the standard textbook set-ups with the readings listed in
-DESIGN.md.
+recipes below are the standard textbook set-ups; each docstring states the
+choices its recipe makes.
 """
 from __future__ import annotations
 
