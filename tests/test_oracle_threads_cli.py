@@ -42,7 +42,12 @@ def test_oracle_thread_count_does_not_change_results(wl, kw):
         O.threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
 
 
-def test_cli_equals_wrapper(tmp_path):
+@pytest.mark.parametrize("flags,kw", [
+    (["--rk", "3", "--recon", "char"], {"rk": 3, "recon": "char"}),
+    (["--solver", "hll", "--limiter", "mc", "--emf", "uct_hll"],
+     {"solver": "hll", "limiter": "mc", "emf": "uct_hll"}),
+])
+def test_cli_equals_wrapper(tmp_path, flags, kw):
     wl = W.random_smooth(n=(12, 10, 7), seed=72, bc=(0, 1, 0))
     spec, st = wl.boxes[0], wl.states[0]
     src, dst, rep = tmp_path / "in.bin", tmp_path / "out.bin", tmp_path / "r.json"
@@ -51,9 +56,9 @@ def test_cli_equals_wrapper(tmp_path):
     assert n == spec.n and bc == spec.bc and t == 0.0
     for a, b in zip(cons + bface, list(st.cons) + list(st.bface)):
         assert np.array_equal(a, b)
-    subprocess.run([CLI, "--in", str(src), "--out", str(dst), "--steps", "5", "--threads", "3",
-                    "--rk", "3", "--recon", "char", "--report", str(rep)], check=True)
-    b = O.OracleBox(spec, rk=3, recon="char")
+    subprocess.run([CLI, "--in", str(src), "--out", str(dst), "--steps", "5", "--threads", "3"]
+                   + flags + ["--report", str(rep)], check=True)
+    b = O.OracleBox(spec, **kw)
     b.set_state(st.cons, st.bface)
     b.step(5)
     oc, ob, ot = b.get_state()
