@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -90,10 +91,12 @@ def parse():
     ap.add_argument("--counter-pass", action="store_true",
                     help="dispatches for a rocprofv3 --pmc run (calibration copy, then "
                          "--steps unfused steps of each precision)")
-    ap.add_argument("--variant64", default="1,1,64,0,64",
-                    help="x,m,segy,persistent,segz of the FP64 run")
-    ap.add_argument("--variant-mixed", default="1,1,64,0,128",
-                    help="x,m,segy,persistent,segz of the mixed run")
+    ap.add_argument("--variant64", default=None,
+                    help="x,m,segy,persistent,segz of the FP64 run (ingestion: default "
+                         "from the recorded command, else 1,1,64,0,64)")
+    ap.add_argument("--variant-mixed", default=None,
+                    help="x,m,segy,persistent,segz of the mixed run (ingestion: default "
+                         "from the recorded command, else 1,1,64,0,128)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic record from two counter-pass runs")
     ap.add_argument("--fetch-command", default="", help="command of the FETCH_SIZE run")
@@ -108,7 +111,20 @@ def parse():
     ap.add_argument("--sq-command", default="", help="command of the SQ-counter run")
     ap.add_argument("--trace-out", default="kernel_trace_paper_cases.md",
                     help="file under profiles/ for the summary of a run without a bench line")
-    return ap.parse_args()
+    a = ap.parse_args()
+    recorded = " ".join((a.fetch_command, a.write_command, a.sq_command))
+    for attr, flag, default in (("variant64", "--variant64", "1,1,64,0,64"),
+                                ("variant_mixed", "--variant-mixed", "1,1,64,0,128")):
+        if getattr(a, attr) is None:
+            setattr(a, attr, variant_in_command(recorded, flag) or default)
+    return a
+
+
+def variant_in_command(cmd, flag):
+    """The value given to `flag` in a recorded command line, or None: counter
+    records are keyed by the launch variants their runs used."""
+    m = re.search(re.escape(flag) + r"\s+([0-9,]+)", cmd or "")
+    return m.group(1) if m else None
 
 
 SOURCES = ["csrc/mhd_kernels.hpp", "csrc/mhd_step.hpp", "csrc/mhd_lib.hip", "csrc/mhd_fp32.hip",

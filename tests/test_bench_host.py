@@ -83,3 +83,22 @@ def test_ingest_counters_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     assert k["dispatches"] == 2 and k["fetch_kib"] == 1100.0 and k["write_kib"] == 600.0
     assert k["bytes"] == int((1100.0 * 2.0 + 600.0) * 1024)
     assert k["launch"] == bench.launch_key("sweep_x", "double", [1, 2, 64, 0, 64])
+
+
+def test_counter_records_take_the_variants_of_their_commands(monkeypatch):
+    """Ingestion keys a counter record by the launch variants the recorded
+    counter runs used, unless they are given explicitly."""
+    cmd = ("rocprofv3 --pmc FETCH_SIZE -f csv -d out -o run -- python -u bench.py --counter-pass "
+           "--steps 2 --variant64 1,2,64,0,64 --variant-mixed 1,8,64,0,128")
+    assert bench.variant_in_command(cmd, "--variant-mixed") == "1,8,64,0,128"
+    assert bench.variant_in_command("python bench.py", "--variant64") is None
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--ingest-counters", "f.csv", "w.csv",
+                                      "--fetch-command", cmd])
+    a = bench.parse()
+    assert (a.variant64, a.variant_mixed) == ("1,2,64,0,64", "1,8,64,0,128")
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--ingest-counters", "f.csv", "w.csv",
+                                      "--fetch-command", cmd, "--variant64", "3,9,16,1,32"])
+    assert bench.parse().variant64 == "3,9,16,1,32"
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.variant64, a.variant_mixed) == ("1,1,64,0,64", "1,1,64,0,128")
