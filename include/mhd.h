@@ -69,8 +69,8 @@ extern "C" {
                           Roe & Balsara 1996 normalisation); a cell whose
                           slope would give a non-positive face density or
                           pressure takes the primitive slope.  The paper
-                          names both ("primitive (or characteristic)",
-                          its section 2.2.3). */
+                          allows reconstruction in either variable set
+                          (its section 2.2.3). */
 
 /* slope limiter of the PLM reconstruction (in either variable set) */
 #define MHD_LIM_MINMOD 0  /* minmod */
@@ -159,32 +159,68 @@ typedef struct mhd_ctx mhd_ctx;
 int mhd_workspace_bytes(const mhd_config *cfg, uint64_t *bytes);
 
 /* Validates cfg (before any device call), then creates a context on the
- * current HIP device.  *out is set only on MHD_OK. */
+ * current HIP device.  *out is set only on MHD_OK.
+ * Defines: the set of independent structured boxes on which the main cycle of
+ * the paper's section 2.2.3 runs, with the scheme options that section leaves
+ * open (integrator stages, Riemann solver, reconstruction variables, corner
+ * EMF, limiter).  Ownership: cfg and cfg->boxes are copied; a caller
+ * workspace (cfg->workspace) must stay allocated until mhd_destroy.
+ * Errors: MHD_E_INVAL (bad field, nothing allocated), MHD_E_NOMEM (device
+ * allocation failed or workspace too small), MHD_E_DEVICE (HIP error). */
 int mhd_create(const mhd_config *cfg, mhd_ctx **out);
 
 /* Copies the state of one box in (boundary layout; where = MHD_HOST or
  * MHD_DEVICE) and sets its time.  Returns after the copy has completed.
- * MHD_E_INVAL if a periodic axis has last face != first face. */
+ * Defines: the conserved state of the conservation laws the code evolves
+ * (paper section 2.2 and its 2.2.3): mass, momentum and total energy per
+ * cell, and the face-centred magnetic field that constrained transport
+ * evolves (one normal component per face, so the discrete divergence of a
+ * cell is the sum of its face differences).  Arguments: box in
+ * [0, nboxes); cons[5] and bface[3] as described at the top of this file,
+ * read only, not retained; t the box time.  Resets the box's event counters
+ * and its non-physical flag.  Errors: MHD_E_INVAL if box is out of range, a
+ * pointer is NULL, where is unknown or a periodic axis has last face !=
+ * first face (nothing changed); MHD_E_DEVICE on a copy failure. */
 int mhd_set_state(mhd_ctx *ctx, int32_t box, const double *const cons[5],
                   const double *const bface[3], double t, int32_t where);
 
 /* Enqueues nsteps full Runge-Kutta steps (rk_stages stages each) of every box
  * on the context stream.
+ * Defines: the main cycle of the paper's section 2.2.3.  Each stage
+ * reconstructs primitive (or characteristic) variables per direction,
+ * solves a Riemann problem at every interface (HLLD, or HLL for the
+ * paper's 2D Riemann runs) and applies the flux-conservative update, then
+ * constrained transport updates the face field; the Runge-Kutta stage
+ * combine closes the stage (third order by default in the paper; two
+ * stages here unless rk_stages = 3).
  * Each box steps with its own CFL time step computed on the device from its
  * state at the start of the step, clamped to t_stop - t when t_stop > 0
  * (steps at t >= t_stop are no-ops).  Returns without waiting; device errors
- * surface at the next mhd_dt / mhd_get_state. */
+ * surface at the next mhd_dt / mhd_get_state.  Errors: MHD_E_INVAL if
+ * nsteps < 0; MHD_E_STATE if a box has no state yet or its last set_state
+ * was rejected; MHD_E_DEVICE on a launch failure. */
 int mhd_step(mhd_ctx *ctx, int32_t nsteps, double t_stop);
 
 /* Waits for the stream, then returns the CFL time step the next step of the
- * box would take (no t_stop clamp) and the box time.  MHD_E_NONPHYS if a
- * non-physical cell was met since the last set_state (values still
- * returned). */
+ * box would take (no t_stop clamp) and the box time.
+ * Defines: the time step from the largest signal speed over the box, the
+ * maximum that the Riemann sweep of the paper's section 3.1.1 listing
+ * writes into its cmax array: dt = cfl / max over cells and active axes d of
+ * (|v_d| + c_f,d) / dx_d, c_f,d the fast magnetosonic speed along d.
+ * Arguments: dt_next and t are host pointers, written on MHD_OK and
+ * MHD_E_NONPHYS.  Errors: MHD_E_INVAL (box out of range, NULL pointer),
+ * MHD_E_STATE (no state), MHD_E_NONPHYS if a non-physical cell was met
+ * since the last set_state (values still returned), MHD_E_DEVICE. */
 int mhd_dt(mhd_ctx *ctx, int32_t box, double *dt_next, double *t);
 
 /* Waits for the stream, then copies the state of one box out (boundary
- * layout; where = MHD_HOST or MHD_DEVICE).  MHD_E_NONPHYS as for mhd_dt
- * (the state is still copied). */
+ * layout; where = MHD_HOST or MHD_DEVICE).
+ * Defines: the conserved state of the paper's section 2.2 (as for
+ * mhd_set_state) after the steps enqueued so far; on periodic axes the last
+ * face is written equal to the first.  Arguments: cons[5], bface[3] are
+ * caller arrays of the boundary layout, written; t (host pointer, may be
+ * NULL) receives the box time.  Errors: MHD_E_INVAL, MHD_E_STATE,
+ * MHD_E_NONPHYS as for mhd_dt (the state is still copied), MHD_E_DEVICE. */
 int mhd_get_state(mhd_ctx *ctx, int32_t box, double *const cons[5],
                   double *const bface[3], double *t, int32_t where);
 

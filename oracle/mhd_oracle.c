@@ -38,12 +38,12 @@
  *   cell's cell-centred state and the tangential faces; the CFL rate of a cell
  *   is the max over active axes of (|v_d| + c_f,d)/dx_d.
  *
- * Floating-point evaluation: a quotient that shares its denominator with
- * others is formed as one reciprocal and products (1/rho for the velocities
- * and the fast speed, 1/(gamma-1), 1/dx, and the common denominators of the
- * HLLD contact speed, star states and double-star averages), in the same
- * order as the GPU library, so that FP64 results can be compared bit for
- * bit.
+ * Floating-point evaluation: every quotient is an IEEE division written as
+ * the formula writes it (m/rho, p/(gamma-1), flux differences over dx, the
+ * HLLD and HLL quotients), with no fused multiply-add.  The oracle's
+ * rounding is its own: it is not arranged to follow any other
+ * implementation, so agreement with one is agreement to rounding, not bit
+ * for bit.
  *
  * Parity pins live in tests/ (consistency, exact contact and rotational
  * discontinuities, conservation, div B, uniform state, symmetry, second-order
@@ -74,7 +74,7 @@ struct orc_box {
   int rec;              /* reconstruction: ORC_REC_PRIM or ORC_REC_CHAR */
   int emf;              /* corner EMF: ORC_EMF_CONTACT, ORC_EMF_E0, ORC_EMF_ARITH */
   int lim;              /* slope limiter: ORC_LIM_MINMOD, ORC_LIM_MC, ORC_LIM_VANLEER */
-  double dx[3], idx[3]; /* cell size and its reciprocal */
+  double dx[3];         /* cell size */
   double gamma, cfl, pfloor;
   int sx, sy, sz;      /* padded extents: n + 2 NG + 1 (one extra face) */
   size_t np;           /* elements per padded array */
@@ -148,10 +148,9 @@ double orc_limit(int lim, double a, double b) {
 int orc_cons_to_prim(const double u[5], const double bc[3], double gamma,
                      double pfloor, double w[8]) {
   double rho = u[0];
-  double ir = 1.0 / rho;
-  double vx = u[1] * ir;
-  double vy = u[2] * ir;
-  double vz = u[3] * ir;
+  double vx = u[1] / rho;
+  double vy = u[2] / rho;
+  double vz = u[3] / rho;
   double ek = 0.5 * rho * (vx * vx + vy * vy + vz * vz);
   double em = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
   double p = (gamma - 1.0) * (u[4] - ek - em);
@@ -203,12 +202,11 @@ void orc_plm_face(double qm2, double qm1, double q0, double qp1, double *ql,
 void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
                     double R[7][7], double L[7][7]) {
   double rho = w[0], u = w[1], p = w[4], by = w[5], bz = w[6];
-  double ir = 1.0 / rho;
   double sr = sqrt(rho);
-  double a2 = gamma * p * ir;
+  double a2 = gamma * p / rho;
   double a = sqrt(a2);
-  double bn2 = bn * bn * ir;
-  double bt2 = (by * by + bz * bz) * ir;
+  double bn2 = bn * bn / rho;
+  double bt2 = (by * by + bz * bz) / rho;
   double dd = a2 - bn2;
   double disc = dd * dd + bt2 * (2.0 * (a2 + bn2) + bt2);
   double sq = sqrt(disc);
@@ -281,17 +279,17 @@ void orc_prim_eigen(const double w[7], double bn, double gamma, double lam[7],
   R[0][3] = 1.0;
   /* left rows */
   L[0][1] = -N * af * cf;  L[0][2] = N * qs * bey;  L[0][3] = N * qs * bez;
-  L[0][4] = N * af * ir;  L[0][5] = N * As * bey * ir;  L[0][6] = N * As * bez * ir;
+  L[0][4] = N * af / rho;  L[0][5] = N * As * bey / rho;  L[0][6] = N * As * bez / rho;
   L[6][1] = N * af * cf;  L[6][2] = -N * qs * bey;  L[6][3] = -N * qs * bez;
-  L[6][4] = N * af * ir;  L[6][5] = N * As * bey * ir;  L[6][6] = N * As * bez * ir;
+  L[6][4] = N * af / rho;  L[6][5] = N * As * bey / rho;  L[6][6] = N * As * bez / rho;
   L[1][2] = -0.5 * bez;  L[1][3] = 0.5 * bey;
   L[1][5] = -0.5 * sg * bez / sr;  L[1][6] = 0.5 * sg * bey / sr;
   L[5][2] = -0.5 * bez;  L[5][3] = 0.5 * bey;
   L[5][5] = 0.5 * sg * bez / sr;  L[5][6] = -0.5 * sg * bey / sr;
   L[2][1] = -N * as * cs;  L[2][2] = -N * qf * bey;  L[2][3] = -N * qf * bez;
-  L[2][4] = N * as * ir;  L[2][5] = -N * Af * bey * ir;  L[2][6] = -N * Af * bez * ir;
+  L[2][4] = N * as / rho;  L[2][5] = -N * Af * bey / rho;  L[2][6] = -N * Af * bez / rho;
   L[4][1] = N * as * cs;  L[4][2] = N * qf * bey;  L[4][3] = N * qf * bez;
-  L[4][4] = N * as * ir;  L[4][5] = -N * Af * bey * ir;  L[4][6] = -N * Af * bez * ir;
+  L[4][4] = N * as / rho;  L[4][5] = -N * Af * bey / rho;  L[4][6] = -N * Af * bez / rho;
   L[3][0] = 1.0;  L[3][4] = -1.0 / a2;
 }
 
@@ -337,10 +335,9 @@ void orc_slope(const double qm[7], const double q0[7], const double qp[7], doubl
 /* fast magnetosonic speed along the normal of (bn, bt1, bt2) */
 double orc_fast_speed(double rho, double p, double bn, double bt1, double bt2,
                       double gamma) {
-  double ir = 1.0 / rho;
-  double a2 = gamma * p * ir;
-  double b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * ir;
-  double bn2 = bn * bn * ir;
+  double a2 = gamma * p / rho;
+  double b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / rho;
+  double bn2 = bn * bn / rho;
   double s = a2 + b2;
   double disc = s * s - 4.0 * a2 * bn2;
   if (disc < 0.0) disc = 0.0;
@@ -355,7 +352,7 @@ void orc_phys_flux(const double w[7], double bn, double gamma, double f[7],
   double bsq = bn * bn + b1 * b1 + b2 * b2;
   double pt = p + 0.5 * bsq;
   double vb = vn * bn + vt1 * b1 + vt2 * b2;
-  double en = p * (1.0 / (gamma - 1.0)) + 0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) +
+  double en = p / (gamma - 1.0) + 0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) +
               0.5 * bsq;
   u[0] = rho;
   u[1] = rho * vn;
@@ -389,9 +386,8 @@ static void hll_with(const double uL[7], const double fL[7], const double uR[7],
     for (c = 0; c < 7; c++) f[c] = fR[c];
     return;
   }
-  double isd = 1.0 / (sr - sl);
   for (c = 0; c < 7; c++)
-    f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;
+    f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) / (sr - sl);
 }
 
 static void wave_speeds(const double wl[7], const double wr[7], double bn,
@@ -427,8 +423,7 @@ static void star_side(const double w[7], const double u[7], double pt,
                       double sa, double sm, double pts, double bn, star_t *s) {
   double sd = sa - w[1];
   double sms = sa - sm;
-  double isms = 1.0 / sms;
-  double rs = w[0] * sd * isms;
+  double rs = w[0] * sd / sms;
   double dd = w[0] * sd * sms - bn * bn;
   double vt1s, vt2s, bt1s, bt2s;
   if (fabs(dd) <= EPS_DEG * pts) {
@@ -438,17 +433,14 @@ static void star_side(const double w[7], const double u[7], double pt,
     bt1s = w[5];
     bt2s = w[6];
   } else {
-    double idd = 1.0 / dd;
-    double cv = bn * (sm - w[1]) * idd;
-    double cb = (w[0] * sd * sd - bn * bn) * idd;
-    vt1s = w[2] - w[5] * cv;
-    vt2s = w[3] - w[6] * cv;
-    bt1s = w[5] * cb;
-    bt2s = w[6] * cb;
+    vt1s = w[2] - bn * w[5] * (sm - w[1]) / dd;
+    vt2s = w[3] - bn * w[6] * (sm - w[1]) / dd;
+    bt1s = w[5] * (w[0] * sd * sd - bn * bn) / dd;
+    bt2s = w[6] * (w[0] * sd * sd - bn * bn) / dd;
   }
   double vb = w[1] * bn + w[2] * w[5] + w[3] * w[6];
   double vbs = sm * bn + vt1s * bt1s + vt2s * bt2s;
-  double ens = (sd * u[4] - pt * w[1] + pts * sm + bn * (vb - vbs)) * isms;
+  double ens = (sd * u[4] - pt * w[1] + pts * sm + bn * (vb - vbs)) / sms;
   s->rho = rs;
   s->vt1 = vt1s;
   s->vt2 = vt2s;
@@ -528,12 +520,12 @@ static int riemann_flux(const double wl[7], const double wr[7], double bn,
   double ptr = total_pressure(wr, bn);
   double sdl = sl - wl[1];
   double sdr = sr - wr[1];
-  double iden = 1.0 / (sdr * wr[0] - sdl * wl[0]);
   /* contact speed and star total pressure */
-  double sm = (sdr * wr[0] * wr[1] - sdl * wl[0] * wl[1] - ptr + ptl) * iden;
+  double sm = (sdr * wr[0] * wr[1] - sdl * wl[0] * wl[1] - ptr + ptl) /
+              (sdr * wr[0] - sdl * wl[0]);
   double pts = (sdr * wr[0] * ptl - sdl * wl[0] * ptr +
-                wl[0] * wr[0] * sdr * sdl * (wr[1] - wl[1])) *
-               iden;
+                wl[0] * wr[0] * sdr * sdl * (wr[1] - wl[1])) /
+               (sdr * wr[0] - sdl * wl[0]);
   int ok = (sl < sm) && (sm < sr) && (pts > 0.0);
   double fo[7];
   if (ok) {
@@ -555,11 +547,12 @@ static int riemann_flux(const double wl[7], const double wr[7], double bn,
         double ssl = sm - fabs(bn) / sql;
         double ssr = sm + fabs(bn) / sqr;
         double sgn = bn > 0.0 ? 1.0 : -1.0;
-        double iss = 1.0 / (sql + sqr);
-        double vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) * iss;
-        double vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) * iss;
-        double bt1ss = (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) * iss;
-        double bt2ss = (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) * iss;
+        double vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) / (sql + sqr);
+        double vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) / (sql + sqr);
+        double bt1ss =
+            (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) / (sql + sqr);
+        double bt2ss =
+            (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) / (sql + sqr);
         double vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
         if (sm > 0.0) {
           double fs[7], uss[7];
@@ -703,7 +696,6 @@ orc_box *orc_box_new(const int n[3], const double lo[3], const double hi[3],
     b->emf = ORC_EMF_CONTACT;
     b->lim = ORC_LIM_MINMOD;
     b->dx[d] = (hi[d] - lo[d]) / (double)n[d];
-    b->idx[d] = 1.0 / b->dx[d];
   }
   b->gamma = gamma;
   b->cfl = cfl;
@@ -1179,7 +1171,7 @@ static void stage_operator(orc_box *b) {
           double r = 0.0;
           for (int e = 0; e < 3; e++) {
             if (!b->active[e]) continue;
-            r = r - (b->FH[e][m][up[e]] - b->FH[e][m][c]) * b->idx[e];
+            r = r - (b->FH[e][m][up[e]] - b->FH[e][m][c]) / b->dx[e];
           }
           b->R[m][c] = r;
         }
@@ -1202,8 +1194,8 @@ static void stage_operator(orc_box *b) {
           pf[f] += 1;
           size_t c0 = IXp(b, pos);
           double t1 = 0.0, t2 = 0.0;
-          if (b->active[e]) t1 = (b->ED[f][IXp(b, pe)] - b->ED[f][c0]) * b->idx[e];
-          if (b->active[f]) t2 = (b->ED[e][IXp(b, pf)] - b->ED[e][c0]) * b->idx[f];
+          if (b->active[e]) t1 = (b->ED[f][IXp(b, pe)] - b->ED[f][c0]) / b->dx[e];
+          if (b->active[f]) t2 = (b->ED[e][IXp(b, pf)] - b->ED[e][c0]) / b->dx[f];
           b->RB[d][c0] = -(t1 - t2);
         }
     }
@@ -1228,7 +1220,7 @@ double orc_dt(orc_box *b) {
           if (!b->active[d]) continue;
           int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
           double cf = orc_fast_speed(w[0], w[4], w[5 + d], w[5 + t1], w[5 + t2], b->gamma);
-          double l = (fabs(w[1 + d]) + cf) * b->idx[d];
+          double l = (fabs(w[1 + d]) + cf) / b->dx[d];
           if (l > lmax) lmax = l;
         }
       }

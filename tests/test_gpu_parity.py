@@ -2,12 +2,18 @@
 oracle on the same seeded inputs.
 
 FP64 bar: relative L1 <= 1e-12 per variable (rho, m, E and the three face
-fields) after the fixed step count, with identical time, time step and event
-counters.  The library evaluates every FP64 formula in the oracle's order
-without FMA contraction, so the comparison is expected to be exact; the
-tolerance is the stated bar.  Mixed bar: relative L1 <= 1e-4 on rho, p and
-|B| (computed in FP64 from both final states) and normalised
-max|div B| <= 1e-12.
+fields) after the fixed step count; the element-wise maximum relative error
+(each difference over |oracle value| + the variable's mean magnitude) is
+printed beside it.  The two codes round independently (the oracle writes its
+quotients as divisions, the library as reciprocals and products, with its
+own contraction), so they agree to rounding, not bit for bit.  The time
+agrees within 1e-12 relative, a single time step computed from one state
+within TOL_DT.  Event counters (floor hits, HLL fallbacks, bad cells) are
+integers that both codes decide by the same FP64 comparisons; they are
+compared exactly.  Bitwise equality is asserted only between runs of the
+library itself (launch variants, graph against eager launches, resume).
+Mixed bar: relative L1 <= 1e-4 on rho, p and |B| (computed in FP64 from both
+final states) and normalised max|div B| <= 1e-12.
 """
 import math
 
@@ -22,6 +28,10 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOLMIX = 1e-4
+# One CFL time step from a state both codes hold bit for bit: the rate of a
+# cell takes about 30 FP64 operations (three of them square roots and
+# divisions), evaluated in different orders; a few ulp, bounded with margin.
+TOL_DT = 1e-13
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -36,6 +46,19 @@ def rel_l1(a, b):
     den = float(np.sum(np.abs(b)))
     num = float(np.sum(np.abs(a - b)))
     return num / den if den > 0 else num / max(1, b.size)
+
+
+def max_rel(a, b):
+    """Element-wise max of |a - b| / (|b| + mean|b|): a relative error that
+    a value near zero does not blow up."""
+    scale = float(np.mean(np.abs(b))) if b.size else 0.0
+    if scale == 0.0:
+        return float(np.max(np.abs(a - b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b) / (np.abs(b) + scale)))
+
+
+def close_dt(a, b, tol=TOL_DT):
+    return abs(a - b) <= tol * abs(b)
 
 
 def gpu_run(wl, nsteps, precision=mhd.MHD_FP64, flags=0, t_stop=0.0, boxes=None, rk=2,
@@ -67,13 +90,16 @@ def oracle_run(spec, st, nsteps, t_stop=0.0, rk=2, solver="hlld", recon="prim", 
 def assert_fp64_parity(g, o, label=""):
     gc, gb, gt, gcnt = g
     oc, ob, ot, ocnt = o
-    assert gt == ot, (label, gt, ot)
+    assert abs(gt - ot) <= TOL64 * abs(ot), (label, gt, ot)
     names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
-    worst = 0.0
-    for name, a, b in zip(names, gc + gb, oc + ob):
+    worst, worst_el = 0.0, 0.0
+    for name, a, b in zip(names, list(gc) + list(gb), list(oc) + list(ob)):
         e = rel_l1(a, b)
         worst = max(worst, e)
+        worst_el = max(worst_el, max_rel(a, b))
         assert e <= TOL64, (label, name, e)
+    print(f"[fp64 parity] {label}: max rel L1 {worst:.2e}, max element rel {worst_el:.2e}, "
+          f"t rel {abs(gt - ot) / abs(ot) if ot else 0.0:.1e}, counters {gcnt}", flush=True)
     assert gcnt == ocnt, (label, gcnt, ocnt)
     return worst
 
@@ -131,8 +157,9 @@ def test_random_state_fp64(n, bc):
     ((40, 36, 1), (0, 0, 0), 0),
 ])
 def test_rk3_fp64(n, bc, flags):
-    """Three-stage SSP Runge-Kutta: the library's FP64 steps equal the
-    oracle's bit for bit (stage states, combines and the extra state copy)."""
+    """Three-stage SSP Runge-Kutta: the library's FP64 steps agree with the
+    oracle's to the FP64 bar (stage states, combines and the extra state
+    copy)."""
     wl = W.random_smooth(n=n, seed=sum(n) + 7, bc=bc)
     g = gpu_run(wl, 4, flags=flags, rk=3)[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=3)
@@ -169,7 +196,7 @@ def test_rk3_orszag_tang_and_mixed():
                                   ((5, 40, 33), (1, 1, 1))])
 def test_hll_everywhere_fp64(n, bc, rk):
     """HLL at every face (MHD_RS_HLL): the library's FP64 steps equal the
-    oracle's bit for bit, with a zero fallback counter."""
+    oracle's to the FP64 bar, with a zero fallback counter."""
     wl = W.random_smooth(n=n, seed=sum(n) + rk, bc=bc)
     g = gpu_run(wl, 4, rk=rk, solver="hll")[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=rk, solver="hll")
@@ -190,7 +217,7 @@ def test_hll_launch_variants_bitwise(variant, monkeypatch):
 
 def test_riemann_2d_hll_fp64_and_mixed():
     """The thin 2D case at 96 x 96 (ragged against every tile shape), HLL
-    and SSP-RK3, 40 steps with graph replay: FP64 bit for bit; the mixed path
+    and SSP-RK3, 40 steps with graph replay: FP64 within its bar; the mixed path
     within its bar."""
     wl = W.riemann_2d(n=96)
     spec = wl.boxes[0]
@@ -210,8 +237,8 @@ def test_riemann_2d_hll_fp64_and_mixed():
 @pytest.mark.parametrize("n,bc", [((30, 26, 22), (1, 0, 0)), ((17, 9, 1), (0, 1, 0)),
                                   ((5, 40, 33), (1, 1, 1)), ((1, 1, 48), (0, 0, 1))])
 def test_char_reconstruction_fp64(n, bc, rk, solver, flags):
-    """Slopes limited in characteristic fields (MHD_REC_CHAR): bit for bit
-    with the oracle in 3D, 2D (fused y march) and 1D boxes."""
+    """Slopes limited in characteristic fields (MHD_REC_CHAR): within the
+    FP64 bar of the oracle in 3D, 2D (fused y march) and 1D boxes."""
     wl = W.random_smooth(n=n, seed=sum(n) + 3 * rk, bc=bc)
     g = gpu_run(wl, 4, flags=flags, rk=rk, solver=solver, recon="char")[0]
     o = oracle_run(wl.boxes[0], wl.states[0], 4, rk=rk, solver=solver, recon="char")
@@ -223,7 +250,7 @@ def test_char_reconstruction_fp64(n, bc, rk, solver, flags):
                                         ((24, 20, 1), (0, 1, 0), "char"),
                                         ((9, 1, 40), (1, 0, 1), "prim")])
 def test_corner_emf_kinds_fp64(n, bc, recon, emf):
-    """E0, arithmetic and upwind-CT corner EMFs: bit for bit with the
+    """E0, arithmetic and upwind-CT corner EMFs: within the FP64 bar of the
     oracle (3D, 2D with the fused y march, and a box with one inactive
     axis; outflow walls on each axis)."""
     wl = W.random_smooth(n=n, seed=sum(n) + len(emf), bc=bc)
@@ -245,7 +272,7 @@ def test_limiters_fp64(n, bc, recon, limiter):
 
 
 def test_limiters_shocks_and_mixed():
-    """Through shocks (Orszag-Tang 2D, 50 steps) bit for bit; the mixed
+    """Through shocks (Orszag-Tang 2D, 50 steps) within the FP64 bar; the mixed
     path within its bar."""
     wl = W.orszag_tang_2d(n=64)
     spec = wl.boxes[0]
@@ -279,7 +306,7 @@ def test_corner_emf_kinds_orszag_tang_and_mixed():
 
 def test_char_reconstruction_shocks_and_mixed():
     """Characteristic slopes through shocks (Orszag-Tang 2D, 60 steps, and
-    the 2D Riemann problem with HLL, 40 steps) bit for bit with the oracle,
+    the 2D Riemann problem with HLL, 40 steps) within the FP64 bar of the oracle,
     the positivity fallback included; the mixed path within its bar."""
     for wl, steps, kw in ((W.orszag_tang_2d(n=64), 60, {}),
                           (W.riemann_2d(n=80), 40, {"rk": 3, "solver": "hll"})):
@@ -309,10 +336,10 @@ def test_char_blast_256_full_size_sampled():
         cons, bface, t = sim.get_state(0)
     ob = O.OracleBox(spec, recon="char")
     ob.set_state(st.cons, st.bface)
-    assert dt_gpu == ob.dt()
+    assert close_dt(dt_gpu, ob.dt())
     del ob
     centres = [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25), (128, 154, 131)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres, recon="char")
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, recon="char", label="blast 256 char")
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
@@ -402,7 +429,7 @@ def test_ensemble_of_uneven_boxes():
 def test_ensemble_of_2d_boxes(rk, solver):
     """Every box with one cell along z and more along y: the y march
     completes each stage (RK combine and the z-face data, one or two z faces
-    per cell) and no z march runs; bit for bit with the oracle, including a
+    per cell) and no z march runs; within the FP64 bar of the oracle, including a
     box with one cell along x and outflow z faces."""
     boxes, states = [], []
     for n, seed, bc in [((40, 24, 1), 11, (0, 0, 0)), ((17, 33, 1), 12, (1, 1, 1)),
@@ -426,11 +453,13 @@ def test_dt_query_and_t_stop():
     with mhd.Sim([spec]) as sim:
         sim.set_state(0, st.cons, st.bface, 0.0)
         dt, t = sim.dt(0)
-        assert dt == ob.dt() and t == 0.0
+        assert close_dt(dt, ob.dt()) and t == 0.0
         sim.step(10, t_stop=2.5 * dt)
         _, _, t = sim.get_state(0)
     ob.step(10, 2.5 * dt)
-    assert t == ob.get_state()[2]
+    # both stop at t_stop: the last step is clamped to the remaining time
+    assert abs(t - ob.get_state()[2]) <= TOL64 * t
+    assert abs(t - 2.5 * dt) <= 1e-15 * t
 
 
 OPTIONS = dict(rk=3, solver="hll", recon="char", limiter="mc", emf="e0")
@@ -439,7 +468,7 @@ OPTIONS = dict(rk=3, solver="hll", recon="char", limiter="mc", emf="e0")
 def test_ensemble_2d_and_3d_with_every_option():
     """An ensemble of 3D, 2D and 1D boxes (so the z march runs) with every
     non-default scheme option at once, graph replay and a persistent grid:
-    each box bit for bit with the oracle."""
+    each box within the FP64 bar of the oracle."""
     boxes, states = [], []
     for n, seed, bc in [((20, 18, 14), 41, (0, 1, 0)), ((33, 21, 1), 42, (1, 0, 0)),
                         ((1, 1, 40), 43, (0, 0, 1))]:
@@ -465,7 +494,7 @@ def test_t_stop_and_graph_replays_with_options():
         g.set_state(0, st.cons, st.bface, 0.0)
         e.set_state(0, st.cons, st.bface, 0.0)
         dt, _ = g.dt(0)
-        assert dt == ob.dt()
+        assert close_dt(dt, ob.dt())
         for k in range(3):
             g.step(1)
             e.step(1)
@@ -478,9 +507,7 @@ def test_t_stop_and_graph_replays_with_options():
         ce, be, te = e.get_state(0)
     ob.step(10, 5.5 * dt)
     oc, obf, ot = ob.get_state()
-    assert te == ot
-    for a, b in zip(ce + be, oc + obf):
-        assert np.array_equal(a, b)
+    assert_fp64_parity((ce, be, te, {}), (oc, obf, ot, {}), "options t_stop")
 
 
 def test_set_get_roundtrip_host_and_device():
@@ -619,20 +646,18 @@ def _sub_box(spec, st, centre, r):
     wrap, outflow axes stop at the real boundary (whose outflow condition the
     sub-box then applies exactly); every cut side gets an outflow wall whose
     influence stays r cells away from the centre.  Returns the sub-box, its
-    state and the centre's index inside it."""
-    idx, fidx, off = [], [], []
+    state and, per axis, the global cell index of each sub-box cell."""
+    idx, fidx = [], []
     for d in range(3):
         n = spec.n[d]
         if spec.bc[d] == W.PERIODIC:
             a = np.arange(centre[d] - r, centre[d] + r + 1) % n
             idx.append(a)
             fidx.append(np.arange(centre[d] - r, centre[d] + r + 2) % n)
-            off.append(r)
         else:
             lo, hi = max(0, centre[d] - r), min(n, centre[d] + r + 1)
             idx.append(np.arange(lo, hi))
             fidx.append(np.arange(lo, hi + 1))
-            off.append(centre[d] - lo)
     cons = [np.ascontiguousarray(c[np.ix_(idx[2], idx[1], idx[0])]) for c in st.cons]
     bface = [
         np.ascontiguousarray(st.bface[0][np.ix_(idx[2], idx[1], fidx[0])]),
@@ -643,27 +668,59 @@ def _sub_box(spec, st, centre, r):
     nn = tuple(len(a) for a in idx)
     sub = W.BoxSpec(nn, lo=(0.0, 0.0, 0.0), hi=tuple(nn[d] * dx[d] for d in range(3)),
                     bc=(W.OUTFLOW,) * 3, gamma=spec.gamma, cfl=spec.cfl)
-    return sub, cons, bface, tuple(off)
+    return sub, cons, bface, idx
 
 
-def _check_sampled(spec, st, cons, bface, dt, centres, r=8, rk=2, solver="hlld", recon="prim"):
-    """One oracle step with the GPU's dt on the neighbourhood of each sampled
-    cell; compares the cell's conserved state and its three lower faces."""
+def _check_sampled(spec, st, cons, bface, dts, centres, r=8, rk=2, solver="hlld",
+                   recon="prim", label="sampled"):
+    """The oracle advances the neighbourhood of radius r of each sampled cell
+    with the GPU's time steps (dts: one per step, or one number for a single
+    step); every cell within r - reach of the centre, where reach = 3 cells
+    per stage is how far the cut boundary's influence can travel, and the
+    three lower faces of those cells are compared.  Over all samples, the
+    relative L1 error per variable must meet the FP64 bar."""
+    dts = [dts] if np.isscalar(dts) else list(dts)
+    reach = 3 * rk * len(dts)
+    inner = r - reach
+    assert inner >= 0, (r, reach)
+    gv = [[] for _ in range(8)]
+    ov = [[] for _ in range(8)]
     for c in centres:
-        sub, sc, sb, o = _sub_box(spec, st, c, r)
+        sub, sc, sb, idx = _sub_box(spec, st, c, r)
         ob = O.OracleBox(sub, rk=rk, solver=solver, recon=recon)
         ob.set_state(sc, sb)
-        ob.step_fixed_dt(dt)
+        for dt in dts:
+            ob.step_fixed_dt(dt)
         oc, obf, _ = ob.get_state()
-        i, j, k = c
-        oi, oj, ok = o
+        del ob
+        sel = []
+        for d in range(3):
+            pos = np.arange(len(idx[d]))
+            # sub-box cells within `inner` of the centre, or anywhere next to
+            # a real outflow wall (exact there)
+            g = idx[d]
+            sel.append(pos[np.abs(g - c[d]) <= inner] if spec.bc[d] != W.PERIODIC
+                       else pos[np.abs(pos - r) <= inner])
+        sk, sj, si = np.ix_(sel[2], sel[1], sel[0])
+        gk, gj, gi = np.ix_(idx[2][sel[2]], idx[1][sel[1]], idx[0][sel[0]])
         for q in range(5):
-            a, b = cons[q][k, j, i], oc[q][ok, oj, oi]
-            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, q, a, b)
-        for d, (a, b) in enumerate([(bface[0][k, j, i], obf[0][ok, oj, oi]),
-                                    (bface[1][k, j, i], obf[1][ok, oj, oi]),
-                                    (bface[2][k, j, i], obf[2][ok, oj, oi])]):
-            assert abs(a - b) <= TOL64 * max(abs(b), 1e-300), (c, "B", d, a, b)
+            gv[q].append(cons[q][gk, gj, gi].ravel())
+            ov[q].append(oc[q][sk, sj, si].ravel())
+        for d in range(3):
+            gv[5 + d].append(bface[d][gk, gj, gi].ravel())
+            ov[5 + d].append(obf[d][sk, sj, si].ravel())
+    names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
+    worst, worst_el, ncell = 0.0, 0.0, 0
+    for q in range(8):
+        a, b = np.concatenate(gv[q]), np.concatenate(ov[q])
+        ncell = a.size
+        e = rel_l1(a, b)
+        worst = max(worst, e)
+        worst_el = max(worst_el, max_rel(a, b))
+        assert e <= TOL64, (label, names[q], e)
+    print(f"[fp64 parity] {label}: {len(centres)} neighbourhoods, {ncell} cells, "
+          f"{len(dts)} step(s): max rel L1 {worst:.2e}, max element rel {worst_el:.2e}",
+          flush=True)
 
 
 def test_blast_256_full_size_sampled():
@@ -681,36 +738,129 @@ def test_blast_256_full_size_sampled():
         cons, bface, t = sim.get_state(0)
     ob = O.OracleBox(spec)
     ob.set_state(st.cons, st.bface)
-    assert dt_gpu == ob.dt()
+    assert close_dt(dt_gpu, ob.dt())
     assert t == dt_gpu
     del ob
     rng = np.random.default_rng(5)
     centres = [tuple(int(v) for v in rng.integers(0, 256, size=3)) for _ in range(4)]
     centres += [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres)
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, label="blast 256")
 
 
-def test_blast_256_full_size_full_state():
-    """The benchmark workload at full size (256^3) over 20 steps in the
-    benchmark's launch configuration (graph replay, autotuned variant):
-    every cell and face value, the time and the event counters equal the
-    threaded oracle's bit for bit."""
+def _host_threads():
     import os
+    return O.threads(min(16, os.cpu_count() or 1))
+
+
+def assert_mixed_bar(spec, m, o, label):
+    """Mixed path against the oracle: relative L1 of rho, p and |B| (formed
+    in FP64 from both final states) within 1e-4, normalised max|div B|
+    within 1e-12."""
+    mp, mb = pressure_bmag(spec, m[0], m[1])
+    op, ob = pressure_bmag(spec, o[0], o[1])
+    errs = {"rho": rel_l1(m[0][0], o[0][0]), "p": rel_l1(mp, op), "|B|": rel_l1(mb, ob)}
+    dvn, dva = divb_norm(spec, m[1])
+    print(f"[mixed] {label}: rel L1 " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+          + f"; div B normalised {dvn:.1e} (absolute {dva:.1e})", flush=True)
+    for k, e in errs.items():
+        assert e <= TOLMIX, (label, k, e)
+    assert dvn <= 1e-12, (label, dvn)
+
+
+@pytest.fixture(scope="module")
+def blast256_oracle_100():
+    """The benchmark workload (blast 256^3) advanced by the threaded oracle
+    over its fixed step count, 100 steps."""
     wl = W.blast_3d(n=256)
+    _host_threads()
+    return wl, oracle_run(wl.boxes[0], wl.states[0], 100)
+
+
+def test_blast_256_fixed_steps_full_state_fp64(blast256_oracle_100):
+    """The benchmark workload at full size over its fixed step count (100),
+    in the benchmark's launch configuration (graph replay, autotuned
+    variant): every cell and face value within the FP64 bar of the threaded
+    oracle, the time within 1e-12, the event counters (pressure floor hits
+    and HLL fallbacks occur here) equal."""
+    wl, o = blast256_oracle_100
+    g = gpu_run(wl, 100, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE)[0]
+    assert_fp64_parity(g, o, "blast 256 x 100")
+
+
+def test_blast_256_fixed_steps_mixed(blast256_oracle_100):
+    """The mixed path on the benchmark workload over its 100 fixed steps
+    against the oracle (low plasma beta: p = 0.1 against |B|^2/2 = 50)."""
+    wl, o = blast256_oracle_100
+    m = gpu_run(wl, 100, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE)[0]
+    assert_mixed_bar(wl.boxes[0], m, o, "blast 256 x 100")
+
+
+@pytest.fixture(scope="module")
+def turbulence512():
+    return W.turbulence_3d(n=512)
+
+
+def test_turbulence_512_full_state_10_steps(turbulence512):
+    """Decaying turbulence at its full size, 512^3, in the benchmark's launch
+    configuration: 10 steps of the FP64 path against the threaded oracle over
+    the whole state (every cell and face), and the mixed path against the
+    same oracle state.  (The oracle's 200 fixed steps would take about half
+    an hour on the host; the fixed step count is covered by
+    test_turbulence_512_fixed_steps_invariants.)"""
+    wl = turbulence512
     spec, st = wl.boxes[0], wl.states[0]
-    g = gpu_run(wl, 20, flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE)[0]
-    O.threads(min(16, os.cpu_count() or 1))
-    o = oracle_run(spec, st, 20)
-    assert_fp64_parity(g, o, "blast 256 x 20")
-    for a, b in zip(g[0] + g[1], o[0] + o[1]):
-        assert np.array_equal(a, b)
+    flags = mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE
+    g = gpu_run(wl, 10, flags=flags)[0]
+    m = gpu_run(wl, 10, precision=mhd.MHD_MIXED, flags=flags)[0]
+    _host_threads()
+    o = oracle_run(spec, st, 10)
+    assert_fp64_parity(g, o, "turbulence 512 x 10")
+    del g
+    assert_mixed_bar(spec, m, o, "turbulence 512 x 10")
+
+
+def _totals(cons):
+    return [math.fsum(c.ravel()) for c in cons], [float(np.sum(np.abs(c))) for c in cons]
+
+
+def test_turbulence_512_fixed_steps_invariants(turbulence512):
+    """Turbulence 512^3 over its fixed step count (200) in both precisions:
+    periodic box, so mass, momentum and energy totals are conserved (FP64:
+    to rounding; mixed: within the bound of its FP32 stage residual) and the
+    mean face field exactly; div B at rounding; the mixed state within the
+    mixed bar of the FP64 state (the FP64 path itself is held to the oracle
+    over the whole state in test_turbulence_512_full_state_10_steps)."""
+    wl = turbulence512
+    spec, st = wl.boxes[0], wl.states[0]
+    steps = 200
+    flags = mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE
+    s0, a0 = _totals(st.cons)
+    res = {}
+    for prec, name in ((mhd.MHD_FP64, "fp64"), (mhd.MHD_MIXED, "mixed")):
+        g = gpu_run(wl, steps, precision=prec, flags=flags)[0]
+        s1, _ = _totals(g[0])
+        drift = [abs(s1[q] - s0[q]) / a0[q] for q in range(5)]
+        dvn, dva = divb_norm(spec, g[1])
+        print(f"[invariants] turbulence 512 x {steps} {name}: total drift / sum|q| "
+              + " ".join(f"{v:.1e}" for v in drift)
+              + f"; div B normalised {dvn:.1e} (absolute {dva:.1e}); counters {g[3]}", flush=True)
+        bound = 1e-13 * math.sqrt(steps) if prec == mhd.MHD_FP64 else 2 * steps * 4 * 2.0 ** -24
+        for q in range(5):
+            assert drift[q] <= bound, (name, q, drift[q])
+        assert dvn <= 1e-12
+        for d in range(3):
+            m0 = math.fsum(st.bface[d].ravel())
+            m1 = math.fsum(g[1][d].ravel())
+            assert abs(m1 - m0) <= 1e-12 * max(1.0, math.fsum(np.abs(st.bface[d]).ravel())), d
+        res[name] = g
+    assert_mixed_bar(spec, res["mixed"], res["fp64"], f"turbulence 512 x {steps} vs GPU FP64")
 
 
 @pytest.mark.parametrize("case", ["orszag_tang_3d", "riemann_2d", "kelvin_helmholtz", "ensemble"])
 def test_full_size_full_state(case):
     """Full-size workloads over a few steps with graph replay and the
-    autotuned variant, every cell and face of every box bit for bit with
-    the threaded oracle: the paper's 352^3 Orszag-Tang case (SSP-RK3, 3
+    autotuned variant, every cell and face of every box within the FP64 bar
+    of the threaded oracle: the paper's 352^3 Orszag-Tang case (SSP-RK3, 3
     steps), its 3200^2 Riemann case (HLL, SSP-RK3, 4 steps), the
     768 x 384 x 384 shear layer with outflow walls (2 steps) and the
     96-box ensemble (2 steps, persistent grid)."""
@@ -729,8 +879,6 @@ def test_full_size_full_state(case):
     for b, g in enumerate(res):
         o = oracle_run(wl.boxes[b], wl.states[b], steps, **kw)
         assert_fp64_parity(g, o, f"{case} box {b}")
-        for x, y in zip(g[0] + g[1], o[0] + o[1]):
-            assert np.array_equal(x, y), (case, b)
 
 
 def test_orszag_tang_352_rk3_full_size_sampled():
@@ -748,13 +896,13 @@ def test_orszag_tang_352_rk3_full_size_sampled():
         cons, bface, t = sim.get_state(0)
     ob = O.OracleBox(spec)
     ob.set_state(st.cons, st.bface)
-    assert dt_gpu == ob.dt()
+    assert close_dt(dt_gpu, ob.dt())
     assert t == dt_gpu
     del ob
     rng = np.random.default_rng(11)
     centres = [tuple(int(v) for v in rng.integers(0, 352, size=3)) for _ in range(3)]
     centres += [(0, 0, 0), (351, 175, 351), (88, 264, 100)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3)
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3, label="OT 352 rk3")
 
 
 def test_riemann_2d_3200_hll_full_size_sampled():
@@ -773,12 +921,13 @@ def test_riemann_2d_3200_hll_full_size_sampled():
         assert sim.counters(0)["hll"] == 0
     ob = O.OracleBox(spec, rk=3, solver="hll")
     ob.set_state(st.cons, st.bface)
-    assert dt_gpu == ob.dt()
+    assert close_dt(dt_gpu, ob.dt())
     assert t == dt_gpu
     del ob
     centres = [(0, 0, 0), (3199, 3199, 0), (0, 3199, 0), (1599, 1600, 0), (1600, 1599, 0),
                (1599, 1599, 0), (1600, 5, 0), (2345, 1600, 0), (777, 2999, 0)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3, solver="hll")
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3, solver="hll",
+                   label="riemann 3200")
 
 
 def test_kelvin_helmholtz_full_size_sampled():
@@ -794,7 +943,7 @@ def test_kelvin_helmholtz_full_size_sampled():
     assert t == dt_gpu
     centres = [(0, 0, 0), (767, 383, 383), (400, 1, 200), (5, 382, 17), (384, 96, 192),
                (123, 287, 301), (700, 192, 0)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres)
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, label="KH 768x384x384")
 
 
 def test_ensemble_96_boxes_full_size():
@@ -814,13 +963,13 @@ def test_ensemble_96_boxes_full_size():
         spec, st = wl.boxes[b], wl.states[b]
         ob = O.OracleBox(spec)
         ob.set_state(st.cons, st.bface)
-        assert dts[b] == ob.dt(), b
+        assert close_dt(dts[b], ob.dt()), b
         del ob
         cons, bface, t = outs[b]
         assert t == dts[b]
         n = spec.n[0]
         centres = [(0, 0, 0), (n - 1, n // 2, 3), (n // 3, n - 1, n // 2)]
-        _check_sampled(spec, st, cons, bface, dts[b], centres)
+        _check_sampled(spec, st, cons, bface, dts[b], centres, label=f"ensemble box {b}")
 
 
 # ---------------------------------------------------------------- variants
@@ -866,7 +1015,7 @@ UCT_OPTIONS = dict(rk=3, solver="hlld", recon="prim", limiter="vanleer", emf="uc
 def test_upwind_ct_ensemble_and_blast():
     """Upwind CT in an ensemble of 3D, 2D and 1D boxes with outflow walls
     (SSP-RK3, van Leer slopes, graph replay, persistent grid) and through
-    the strong shocks of a small blast: bit for bit with the oracle; the
+    the strong shocks of a small blast: within the FP64 bar of the oracle; the
     mixed path within its bar, div B at rounding."""
     boxes, states = [], []
     for n, seed, bc in [((22, 17, 13), 51, (1, 0, 0)), ((31, 19, 1), 52, (0, 1, 0)),

@@ -292,6 +292,128 @@ def test_hll_fallback_on_strong_rarefaction():
     assert abs(f[0]) < 1e-12
 
 
+def _cf_textbook(w, bn):
+    """Fast magnetosonic speed along n: the larger root of
+    c^4 - (a^2 + b^2) c^2 + a^2 b_n^2 = 0 (a^2 = gamma p / rho, b = B/sqrt(rho))."""
+    a2 = G * w[4] / w[0]
+    b2 = (bn * bn + w[5] ** 2 + w[6] ** 2) / w[0]
+    bn2 = bn * bn / w[0]
+    return math.sqrt(0.5 * (a2 + b2 + math.sqrt((a2 + b2) ** 2 - 4.0 * a2 * bn2)))
+
+
+def _textbook_flux_state(w, bn):
+    """Physical flux and conserved vector of a face-frame state, from the
+    ideal-MHD conservation laws (7 components: rho, m_n, m_t1, m_t2, E,
+    B_t1, B_t2)."""
+    rho, u, v1, v2, p, b1, b2 = w
+    bsq = bn * bn + b1 * b1 + b2 * b2
+    pt = p + 0.5 * bsq
+    en = p / (G - 1.0) + 0.5 * rho * (u * u + v1 * v1 + v2 * v2) + 0.5 * bsq
+    vb = u * bn + v1 * b1 + v2 * b2
+    U = np.array([rho, rho * u, rho * v1, rho * v2, en, b1, b2])
+    F = np.array([rho * u, rho * u * u + pt - bn * bn, rho * u * v1 - bn * b1,
+                  rho * u * v2 - bn * b2, (en + pt) * u - bn * vb, u * b1 - v1 * bn,
+                  u * b2 - v2 * bn])
+    return F, U
+
+
+def _star_thermal_pressures(wl, wr, bn):
+    """Outer speeds, contact speed, star total pressure and the two
+    single-star thermal pressures of Miyoshi & Kusano (2005), from their
+    jump conditions: mass and momentum balance across S_L and S_R with one
+    normal velocity S_M and one total pressure in the star region (this
+    only decides which branch the state exercises)."""
+    c = max(_cf_textbook(wl, bn), _cf_textbook(wr, bn))
+    sl, sr = min(wl[1], wr[1]) - c, max(wl[1], wr[1]) + c
+    pt = [w[4] + 0.5 * (bn * bn + w[5] ** 2 + w[6] ** 2) for w in (wl, wr)]
+    ml, mr = wl[0] * (sl - wl[1]), wr[0] * (sr - wr[1])  # mass fluxes through S_L, S_R
+    sm = (mr * wr[1] - ml * wl[1] - pt[1] + pt[0]) / (mr - ml)
+    pts = pt[0] + ml * (sm - wl[1])  # momentum jump across S_L
+    ps = []
+    for w, s, m, ptw in ((wl, sl, ml, pt[0]), (wr, sr, mr, pt[1])):
+        rs = m / (s - sm)
+        den = m * (s - sm) - bn * bn
+        bt = [b * (m * (s - w[1]) - bn * bn) / den for b in (w[5], w[6])]
+        vt = [v - bn * b * (sm - w[1]) / den for v, b in ((w[2], w[5]), (w[3], w[6]))]
+        en = _textbook_flux_state(w, bn)[1][4]
+        vb = w[1] * bn + w[2] * w[5] + w[3] * w[6]
+        vbs = sm * bn + vt[0] * bt[0] + vt[1] * bt[1]
+        ens = ((s - w[1]) * en - ptw * w[1] + pts * sm + bn * (vb - vbs)) / (s - sm)
+        ps.append((G - 1.0) * (ens - 0.5 * rs * (sm * sm + vt[0] ** 2 + vt[1] ** 2)
+                               - 0.5 * (bn * bn + bt[0] ** 2 + bt[1] ** 2)))
+    return sl, sr, sm, pts, ps
+
+
+@pytest.mark.parametrize("mirror", [False, True])
+def test_hll_fallback_on_negative_star_thermal_pressure(mirror):
+    """A cold stationary jump of density and tangential field (B_n = 1,
+    p = 0.001): the contact speed lies strictly between the outer speeds
+    and the star total pressure is positive, but the single-star state on
+    the weak-field side would need a negative thermal pressure (the
+    compressed field alone exceeds the star total pressure).  The HLLD star
+    states are then not physical and the solver must return the HLL flux,
+    written out here from its closed form (Harten, Lax & van Leer 1983) with
+    the same outer speeds, and flag the fallback."""
+    wl = np.array([0.5, 0.0, 0.0, 0.0, 0.001, -1.5, 0.0])
+    wr = np.array([0.2, 0.0, 0.0, 0.0, 0.001, -0.5, 0.0])
+    bn = 1.0
+    if mirror:  # the same jump seen from the other side: x -> -x
+        flip = np.array([1.0, -1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+        wl, wr = wr * flip, wl * flip
+        bn = -bn
+    sl, sr, sm, pts, ps = _star_thermal_pressures(wl, wr, bn)
+    assert sl < sm < sr and pts > 0.0
+    assert min(ps) < -0.4 * pts and max(ps) > 0.0
+    f, used = O.hlld(wl, wr, bn, G)
+    assert used
+    fl, ul = _textbook_flux_state(wl, bn)
+    fr, ur = _textbook_flux_state(wr, bn)
+    hll = (sr * fl - sl * fr + sl * sr * (ur - ul)) / (sr - sl)
+    assert np.max(np.abs(f - hll)) <= 1e-14 * np.max(np.abs(hll)), (f, hll)
+    # the scheme counts the fallback: one x sweep over a two-state tube
+    # (piecewise constant, so the face at the jump sees exactly wl | wr)
+    spec = W.BoxSpec((8, 1, 1), bc=(W.OUTFLOW, W.PERIODIC, W.PERIODIC), gamma=G)
+    rho = np.where(np.arange(8) < 4, wl[0], wr[0]).reshape(1, 1, 8)
+    by = np.where(np.arange(8) < 4, wl[5], wr[5]).reshape(1, 1, 8)
+    bface = [np.full((1, 1, 9), bn), np.broadcast_to(by, (1, 2, 8)).copy(),
+             np.broadcast_to(np.zeros((1, 1, 8)), (2, 1, 8)).copy()]
+    st = W.conserved(spec, rho, 0.0, 0.0, 0.0, 0.001 + 0 * rho, bface)
+    ob = O.OracleBox(spec)
+    ob.set_state(st.cons, st.bface)
+    ob.rhs()
+    assert ob.counters()["hll"] == 1
+
+
+@pytest.mark.parametrize("degenerate_side", ["left", "right"])
+def test_hlld_degenerate_star_denominator_stationary_contact(degenerate_side):
+    """An isolated stationary contact (density jump at rest, equal pressure
+    and field) whose low-density side has an Alfven speed above its sound
+    speed and a tangential field of 1e-7 B_n: its fast speed, the outer
+    speed of that side, then equals its Alfven speed to O(B_t^2), so the
+    single-star denominator rho (S - u)(S - S_M) - B_n^2 vanishes to
+    rounding (the degenerate case of Miyoshi & Kusano 2005), while B_t is
+    not zero.  The solver must still resolve the contact exactly (a property
+    of HLLD proven in that paper): zero mass, energy and tangential-field
+    flux, normal momentum flux p_T - B_n^2, tangential momentum flux
+    -B_n B_t.  The limit of the star-state formulas as S_M -> u fixes the
+    tangential star velocity and field to the side's own values; any other
+    value enters the flux through the star or double-star states."""
+    bn, p, bt = 1.0, 0.1, 1e-7
+    lo, hi = 0.5, 1.0  # densities: Alfven speed 1.41 > sound speed 0.58 at 0.5
+    rl, rr = (lo, hi) if degenerate_side == "left" else (hi, lo)
+    wl = np.array([rl, 0.0, 0.0, 0.0, p, bt, -bt])
+    wr = np.array([rr, 0.0, 0.0, 0.0, p, bt, -bt])
+    c = max(_cf_textbook(wl, bn), _cf_textbook(wr, bn))
+    w = wl if degenerate_side == "left" else wr
+    s = -c if degenerate_side == "left" else c
+    pt = p + 0.5 * (bn * bn + 2 * bt * bt)
+    assert abs(w[0] * s * s - bn * bn) <= 1e-12 * pt  # degenerate denominator (S_M = u = 0)
+    f, used = O.hlld(wl, wr, bn, G)
+    assert not used
+    exact = np.array([0.0, pt - bn * bn, -bn * bt, bn * bt, 0.0, 0.0, 0.0])
+    assert np.max(np.abs(f - exact)) <= 1e-15 * c * pt, (f, exact)
+
+
 def test_hll_consistency():
     rng = np.random.default_rng(34)
     for _ in range(100):
