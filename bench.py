@@ -1,27 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the ideal-MHD hot path on one MI355X.
 
-Workload: the 3D magnetised blast wave, 256^3 periodic unit cube (seeded
-+-1e-6 density noise), PLM-minmod + HLLD + CT + SSP-RK2, CFL 0.3.  A step is
-one full SSP-RK2 step of the whole box (both stages, every kernel of the
-path); inputs are resident in HBM before the timed region.  The timed region
-is ``--steps`` graph-replayed steps on the library's stream, bracketed by HIP
-events, repeated ``--repeats`` times (each repeat re-sets the initial state
-and runs ``--warmup`` untimed steps first); ``value`` is FP64 cell-updates per
-second (cells x steps / median time).  The launch variant is chosen by the
-library's autotuner during the first warm-up (outside the timed region).
+Workload (default): decaying MHD turbulence on the periodic unit cube at
+512^3 cells (rho = 1, p = 0.6, mean B = (1, 0, 0), seeded solenoidal
+Gaussian-spectrum velocity peaked at k = 4 with rms 0.5), PLM-minmod + HLLD +
+CT + SSP-RK2, CFL 0.3: the largest single-GPU configuration, whose fixed step
+count is 200.  ``--workload blast`` times the 256^3 magnetised blast instead.
+A step is one full SSP-RK2 step of the whole box (both stages, every kernel
+of the path); inputs are resident in HBM before the timed region.  The timed
+region is ``--steps`` graph-replayed steps on the library's stream,
+bracketed by HIP events, repeated ``--repeats`` times (each repeat re-sets
+the initial state and runs ``--warmup`` untimed steps first); ``value`` is
+FP64 cell-updates per second (cells x steps / median time).  The launch
+variants are the autotuner's choice for the workload, fixed in
+BENCH_VARIANTS so that the counter records under profiles/ describe the
+kernels the line times (``--autotune`` lets the library choose again).
 ``fractions`` gives the step time against the per-direction design's
 algorithmic bytes at 8 TB/s and against the method's compulsory traffic or
 flops.
 
 Also reported on the same line: the mixed-precision rate on the same
-workload and its relative L1 error against the FP64 run after the same step
-count (rho, p, |B|) with max|div B| of both; a roofline object for the
-dominant kernel (algorithmic bytes per launch over its average launch time,
-measured with HIP events around each launch of a timing pass of the same
-kernels on the library's stream); the HBM traffic of that kernel from the
-committed rocprofv3 counter summary when it was taken on the current kernel
-source; and the CPU oracle's rate on a bounded sample of the same recipe.
+workload; the relative L1 error of the mixed path against the FP64 path
+after the workload's fixed step count (rho, p, |B|), with max|div B| and the
+drift of the mass, momentum and energy totals of both; a roofline object
+for the dominant kernel (algorithmic bytes per launch over its average
+launch time, measured with HIP events around each launch of a timing pass of
+the same kernels on the library's stream), with its HBM traffic and VALU
+issue fraction from the committed rocprofv3 records when they were taken on
+the current kernel source and variant; and the CPU oracle's rate on a
+bounded sample of the same recipe.
 
 ``--accuracy`` instead runs the mixed path against the FP64 path on the full
 turbulence (512^3, 200 steps), ensemble (96 boxes, 100 steps) and
@@ -42,7 +49,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_blast_256.json")
+
+# Benchmark workloads: per-axis size, fixed step count, the CPU sample's
+# size and steps, and the launch variants (x, march, y segment, persistent,
+# z segment) of the timed runs: the library autotuner's choice on one
+# MI355X for the current kernels (bench.py --autotune prints it).
+WORKLOADS = {
+    "turbulence": {"n": 512, "fixed_steps": 200, "cpu_n": 160, "cpu_steps": 40,
+                   "what": "turbulence_3d {n}^3 periodic, decaying solenoidal turbulence "
+                           "(beta ~ 1), PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3"},
+    "blast": {"n": 256, "fixed_steps": 100, "cpu_n": 256, "cpu_steps": 12,
+              "what": "blast_3d {n}^3 periodic, PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3"},
+}
+BENCH_VARIANTS = {
+    ("turbulence", 512): {"fp64": "1,2,64,0,64", "mixed": "1,9,64,0,128"},
+    ("blast", 256): {"fp64": "1,2,64,0,64", "mixed": "1,9,64,0,128"},
+}
+
+
+def make_workload(name, n):
+    from paper_2606_12753_amd import workloads
+    return workloads.turbulence_3d(n=n) if name == "turbulence" else workloads.blast_3d(n=n)
+
+
+def profile_file(kind, a, ext):
+    """profiles/<kind>_<workload>_<n>.<ext>: the record of one workload."""
+    return os.path.join(ROOT, "profiles", f"{kind}_{a.workload}_{a.n}.{ext}")
 
 # Algorithmic HBM bytes per cell and launch (compulsory reads and writes of
 # each kernel's inputs and outputs, each array element once; stage 1 /
@@ -71,12 +103,19 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed repeats (each re-sets the state); the median is reported")
-    ap.add_argument("--n", type=int, default=256, help="cells per axis of the blast box")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="turbulence")
+    ap.add_argument("--n", type=int, default=None,
+                    help="cells per axis of the box (default: the workload's own size)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variant")
-    ap.add_argument("--cpu-n", type=int, default=256, help="cells per axis of the CPU sample")
-    ap.add_argument("--cpu-steps", type=int, default=12, help="steps of the CPU sample")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner choose the launch variants (default: the "
+                         "workload's recorded choice)")
+    ap.add_argument("--fixed-steps", type=int, default=None,
+                    help="steps of the accuracy runs (default: the workload's fixed count)")
+    ap.add_argument("--cpu-n", type=int, default=None, help="cells per axis of the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=None, help="steps of the CPU sample")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
                     help="host threads of the CPU oracle (the box's CPU share is 16)")
     ap.add_argument("--accuracy", action="store_true")
@@ -112,11 +151,21 @@ def parse():
     ap.add_argument("--trace-out", default="kernel_trace_paper_cases.md",
                     help="file under profiles/ for the summary of a run without a bench line")
     a = ap.parse_args()
+    w = WORKLOADS[a.workload]
+    if a.n is None:
+        a.n = w["n"]
+    if a.fixed_steps is None:
+        a.fixed_steps = w["fixed_steps"]
+    if a.cpu_n is None:
+        a.cpu_n = w["cpu_n"]
+    if a.cpu_steps is None:
+        a.cpu_steps = w["cpu_steps"]
     recorded = " ".join((a.fetch_command, a.write_command, a.sq_command))
-    for attr, flag, default in (("variant64", "--variant64", "1,1,64,0,64"),
-                                ("variant_mixed", "--variant-mixed", "1,1,64,0,128")):
+    fixed = BENCH_VARIANTS.get((a.workload, a.n), {})
+    for attr, flag, key, default in (("variant64", "--variant64", "fp64", "1,1,64,0,64"),
+                                     ("variant_mixed", "--variant-mixed", "mixed", "1,1,64,0,128")):
         if getattr(a, attr) is None:
-            setattr(a, attr, variant_in_command(recorded, flag) or default)
+            setattr(a, attr, variant_in_command(recorded, flag) or fixed.get(key) or default)
     return a
 
 
@@ -129,7 +178,6 @@ def variant_in_command(cmd, flag):
 
 SOURCES = ["csrc/mhd_kernels.hpp", "csrc/mhd_step.hpp", "csrc/mhd_lib.hip", "csrc/mhd_fp32.hip",
            "csrc/mhd_opt64.hip", "csrc/mhd_opt32.hip", "build.py"]
-TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_blast_256.md")
 KINDS = ["sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"]
 COPY_BYTES = 1 << 30  # calibration copy of the counter pass
 # Floating-point operations of one cell-update (one full SSP-RK2 step of one
@@ -325,24 +373,33 @@ def kernel_times(wl, precision, steps, variant):
     return {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in kt.items()}
 
 
-def roofline(kt, cells, table, variant, precision):
-    per_step = {k: kt[k][0] * kt[k][1] for k in table}
-    dom = max(per_step, key=per_step.get)
-    bytes_per_launch = 0.5 * (table[dom][0] + table[dom][1]) * cells
-    avg_ms = kt[dom][0]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = None
+def recorded_kernel(path, precision, dom, variant):
+    """The entry of a committed counter record (HBM traffic or SQ counters)
+    for the dominant kernel, if the record was taken on the current kernel
+    source and with the launch variant the run used; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
         key = "fp64" if precision == 0 else "mixed"
         real = "double" if precision == 0 else "float"
         k = rec.get(key, {}).get("kernels", {}).get(dom)
         if rec.get("source_sha") == source_sha() and k \
                 and k.get("launch") == launch_key(dom, real, variant):
-            traffic = int(k["bytes"])
+            return k
     except (OSError, ValueError, KeyError, TypeError):
-        traffic = None
+        pass
+    return None
+
+
+def roofline(kt, cells, table, variant, precision, a):
+    per_step = {k: kt[k][0] * kt[k][1] for k in table}
+    dom = max(per_step, key=per_step.get)
+    bytes_per_launch = 0.5 * (table[dom][0] + table[dom][1]) * cells
+    avg_ms = kt[dom][0]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    k = recorded_kernel(profile_file("hbm_traffic", a, "json"), precision, dom, variant)
+    traffic = int(k["bytes"]) if k else None
+    sq = recorded_kernel(profile_file("sq_counters", a, "json"), precision, dom, variant)
     return {
         "kernel": dom,
         "bound": "hbm",
@@ -354,6 +411,11 @@ def roofline(kt, cells, table, variant, precision):
         "traffic_over_algorithmic": round(traffic / bytes_per_launch, 3) if traffic else None,
         "avg_launch_ms": round(avg_ms, 4),
         "bytes_per_launch": int(bytes_per_launch),
+        # share of the chip's VALU issue slots the kernel used (SQ counters;
+        # FP64 and FP32 wave instructions alike) and VALU instructions per
+        # wave: what bounds the FP64 sweeps before HBM does
+        "valu_issue": sq["valu_issue"] if sq else None,
+        "valu_per_wave": sq["valu_per_wave"] if sq else None,
     }
 
 
@@ -389,13 +451,12 @@ def compare(spec, st64, stmx):
             "max_divB_norm": {"fp64": n64, "mixed": nmx}}
 
 
-def cpu_baseline(n, steps, threads):
+def cpu_baseline(a, n, steps, threads):
     """The oracle as it is (FP64, OpenMP over its cell and face loops) on a
-    bounded sample of the benchmark input: `steps` steps of the blast recipe
-    on n^3 cells with `threads` host threads."""
+    bounded sample of the benchmark workload: `steps` steps of the same
+    recipe on n^3 cells with `threads` host threads."""
     import oracle
-    from paper_2606_12753_amd import workloads
-    wl = workloads.blast_3d(n=n)
+    wl = make_workload(a.workload, n)
     used = oracle.threads(threads)
     ob = oracle.OracleBox(wl.boxes[0])
     ob.set_state(wl.states[0].cons, wl.states[0].bface)
@@ -408,7 +469,8 @@ def cpu_baseline(n, steps, threads):
         "unit": "Mcell-updates/s",
         "cores": used,
         "kind": "oracle",
-        "sample": f"blast recipe at {n}^3 ({'the benchmark input' if n == 256 else 'same seed and set-up'}), "
+        "sample": f"{a.workload} recipe at {n}^3 ("
+                  f"{'the benchmark input' if n == a.n else 'same seed and set-up'}), "
                   f"{steps} steps, FP64 oracle on {used} host threads, {el:.1f} s",
     }
 
@@ -437,7 +499,7 @@ def counter_pass(a):
     torch.cuda.synchronize()
     del src, dst
     print("# counter pass: calibration copies done", file=sys.stderr, flush=True)
-    wl = workloads.blast_3d(n=a.n)
+    wl = make_workload(a.workload, a.n)
     for prec, text in ((mhd.MHD_FP64, a.variant64), (mhd.MHD_MIXED, a.variant_mixed)):
         os.environ["MHD_VARIANT"] = ",".join(str(v) for v in parse_variant(text))
         try:
@@ -473,7 +535,7 @@ def ingest_counters(a):
     over its reading; per kernel kind, KiB per dispatch averaged over the
     dispatches of the run (both RK stages)."""
     fetch_csv, write_csv = a.ingest_counters
-    out = {"workload": f"blast_3d {a.n}^3", "source_sha": source_sha(),
+    out = {"workload": f"{a.workload} {a.n}^3", "source_sha": source_sha(),
            "commands": {"fetch": a.fetch_command, "write": a.write_command},
            "calibration": {"copy_bytes": COPY_BYTES}}
     per = {}
@@ -514,7 +576,7 @@ def ingest_counters(a):
                              "bytes": int(byts), "algorithmic_bytes": int(alg),
                              "ratio": round(byts / alg, 3)}
         out[key] = {"variant": parse_variant(text), "kernels": kernels}
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(profile_file("hbm_traffic", a, "json"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps({k: {kk: v["ratio"] for kk, v in out[k]["kernels"].items()}
@@ -552,7 +614,7 @@ def ingest_sq(a):
             dur.setdefault(n, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
             res[n] = (r.get("VGPR_Count") or r.get("Arch_VGPR_Count"), r["SGPR_Count"],
                       r["LDS_Block_Size"], r["Scratch_Size"])
-    lines = [f"# SQ counters: blast_3d {a.n}^3, the benchmark's kernels", "",
+    lines = [f"# SQ counters: {a.workload} {a.n}^3, the benchmark's kernels", "",
              "Commands (from the repository root):", "", "```", a.sq_command, a.trace_command, "```",
              "", f"Kernel source hash {source_sha()}; variants FP64 {a.variant64}, mixed "
              f"{a.variant_mixed}.  VALU issue = SQ_INSTS_VALU / (duration x "
@@ -565,6 +627,10 @@ def ingest_sq(a):
              "LDS / wave | LDS conflict cycles / LDS instr | avg us | VALU issue | VGPR_Count | "
              "SGPR_Count | LDS bytes | scratch bytes |",
              "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    record = {"workload": f"{a.workload} {a.n}^3", "source_sha": source_sha(),
+              "commands": {"sq": a.sq_command, "trace": a.trace_command}}
+    for key, text in (("fp64", a.variant64), ("mixed", a.variant_mixed)):
+        record[key] = {"variant": parse_variant(text), "kernels": {}}
     for ((key, kind), name), rec in sorted(per.items(), key=lambda x: (x[0][0][0], KINDS.index(x[0][0][1]))):
         def mean(c):
             v = rec.get(c, {})
@@ -581,9 +647,19 @@ def ingest_sq(a):
                      f"{waves:.0f} | {valu / waves:.0f} | {mean('SQ_INSTS_SALU') / waves:.0f} | "
                      f"{mean('SQ_INSTS_VMEM_RD') / waves:.1f} | {lds / waves:.1f} | {conf:.3f} | "
                      f"{avg * 1e6:.1f} | {issue:.2f} | {vg} | {sg} | {lb} | {sc} |")
-    out = os.path.join(ROOT, "profiles", f"sq_counters_blast_{a.n}.md")
-    with open(out, "w") as fh:
+        real = "double" if key == "fp64" else "float"
+        variant = record[key]["variant"]
+        if kernel_name(kind, real, variant) in name:
+            record[key]["kernels"][kind] = {
+                "launch": launch_key(kind, real, variant), "kernel": name,
+                "valu_per_wave": round(valu / waves, 1), "valu_issue": round(issue, 3),
+                "lds_conflict_per_instr": round(conf, 4), "avg_us_unfused": round(avg * 1e6, 1),
+                "vgpr_count": vg, "scratch_bytes": sc}
+    with open(profile_file("sq_counters", a, "md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    with open(profile_file("sq_counters", a, "json"), "w") as fh:
+        json.dump(record, fh, indent=1)
+        fh.write("\n")
     print("\n".join(lines))
 
 
@@ -617,7 +693,7 @@ def summarize_trace(a):
             key = (r["Kernel_Name"], int(r["Grid_Size_X"]))
             trace.setdefault(key, []).append(
                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    lines = [f"# rocprofv3 kernel trace: blast_3d {a.n}^3, FP64 and mixed", "",
+    lines = [f"# rocprofv3 kernel trace: {a.workload} {a.n}^3, FP64 and mixed", "",
              "Command (from the repository root):", "", "```", a.trace_command, "```", "",
              f"Kernel source hash {bench.get('source_sha')}; bench line: FP64 "
              f"{bench['value']} Mcell-updates/s, variant {bench['config']['variant']}"
@@ -645,7 +721,7 @@ def summarize_trace(a):
         bench_us = roof["avg_launch_ms"] * 1e3
         lines.append(f"| {key} | `{want}` | {grid} | {cnt} | {avg:.1f} | {bench_us:.1f} | "
                      f"{avg / bench_us:.3f} |")
-    with open(TRACE_FILE, "w") as fh:
+    with open(profile_file("kernel_trace", a, "md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -760,8 +836,8 @@ def options_bench(a, flags):
     depend on the options; the upwind CT adds the stores of the face wave
     speeds)."""
     from paper_2606_12753_amd import mhd, workloads
-    print(f"# options: building blast {a.n}^3 input", file=sys.stderr, flush=True)
-    wl = workloads.blast_3d(n=a.n)
+    print(f"# options: building {a.workload} {a.n}^3 input", file=sys.stderr, flush=True)
+    wl = make_workload(a.workload, a.n)
     cells = wl.cells
     opts = [("default", dict(rk=2, solver="hlld", recon="prim", emf="contact")),
             ("rk3", dict(rk=3, solver="hlld", recon="prim", emf="contact")),
@@ -773,7 +849,7 @@ def options_bench(a, flags):
             ("limiter_mc", dict(rk=2, solver="hlld", recon="prim", emf="contact", limiter="mc")),
             ("limiter_vanleer", dict(rk=2, solver="hlld", recon="prim", emf="contact",
                                      limiter="vanleer"))]
-    out = {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+CT, CFL 0.3", "cells": cells,
+    out = {"workload": f"{a.workload} {a.n}^3 periodic, PLM-minmod+CT, CFL 0.3", "cells": cells,
            "steps": a.steps, "options": {}}
     for name, kw in opts:
         row = {}
@@ -861,29 +937,41 @@ def main():
     if a.options:
         options_bench(a, flags)
         return
-    print(f"# building blast {a.n}^3 input", file=sys.stderr, flush=True)
-    wl = workloads.blast_3d(n=a.n)
+    print(f"# building {a.workload} {a.n}^3 input", file=sys.stderr, flush=True)
+    wl = make_workload(a.workload, a.n)
     spec = wl.boxes[0]
     cells = wl.cells
     print("# HBM stream reference", file=sys.stderr, flush=True)
     stream = stream_bandwidth()
+    fixed = {}
+    if not a.autotune and not a.no_tune:
+        fixed = {mhd.MHD_FP64: parse_variant(a.variant64), mhd.MHD_MIXED: parse_variant(a.variant_mixed)}
+        flags = mhd.MHD_F_GRAPH
     print("# FP64 timed run", file=sys.stderr, flush=True)
-    r64 = run_gpu(wl, mhd.MHD_FP64, a.steps, a.warmup, flags, a.repeats)
+    r64 = with_variant(fixed.get(mhd.MHD_FP64), run_gpu, wl, mhd.MHD_FP64, a.steps, a.warmup,
+                       flags, a.repeats)
     r64["sim"].close()
     ms = r64["ms"]
     value = cells * a.steps / (ms * 1e-3) / 1e6
     print("# FP64 kernel timing pass", file=sys.stderr, flush=True)
     kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10), r64["variant"])
-    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64)
+    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64, a)
     print("# FP64 PCIe-inclusive run", file=sys.stderr, flush=True)
     pcie = pcie_inclusive(wl, mhd.MHD_FP64, a.steps, r64["variant"])
     mixed = None
+    print(f"# FP64 run over the fixed step count ({a.fixed_steps})", file=sys.stderr, flush=True)
+    s64, cnt64 = fixed_run(wl, mhd.MHD_FP64, a.fixed_steps, r64["variant"])
+    drift64 = drift(wl.states[0].cons, s64[0])
     if not a.no_mixed:
         print("# mixed timed run", file=sys.stderr, flush=True)
-        rmx = run_gpu(wl, mhd.MHD_MIXED, a.steps, a.warmup, flags, a.repeats)
+        rmx = with_variant(fixed.get(mhd.MHD_MIXED), run_gpu, wl, mhd.MHD_MIXED, a.steps,
+                           a.warmup, flags, a.repeats)
         rmx["sim"].close()
         ktm = kernel_times(wl, mhd.MHD_MIXED, min(a.steps, 10), rmx["variant"])
-        acc = compare(spec, r64["state"], rmx["state"])
+        print(f"# mixed run over the fixed step count ({a.fixed_steps})", file=sys.stderr,
+              flush=True)
+        smx, cntmx = fixed_run(wl, mhd.MHD_MIXED, a.fixed_steps, rmx["variant"])
+        acc = compare(spec, s64, smx)
         mixed = {
             "value": round(cells * a.steps / (rmx["ms"] * 1e-3) / 1e6, 2),
             "ms_per_step": round(rmx["ms"] / a.steps, 4),
@@ -892,15 +980,19 @@ def main():
             "fractions": fractions(rmx["ms"] / a.steps, cells, BYTES_MIXED, FP32_PEAK_FLOPS,
                                    stream["triad_GBs"]),
             "accuracy_vs_fp64": acc,
-            "after_steps": a.warmup + a.steps,
+            "after_steps": a.fixed_steps,
+            "conservation_drift": drift(wl.states[0].cons, smx[0]),
+            "counters": cntmx,
             "variant": rmx["variant"],
-            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED),
+            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED, a),
             "kernels_ms": {k: round(v[0], 4) for k, v in ktm.items() if v[1]},
         }
+        del smx
+    del s64
     cpu = None
     if not a.no_cpu:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(a.cpu_n, a.cpu_steps, a.cpu_threads)
+        cpu = cpu_baseline(a, a.cpu_n, a.cpu_steps, a.cpu_threads)
     line = {
         "metric": "Mcell-updates/s, FP64 vs mixed FP32 at stated L1 error; % HBM/FP64 roofline",
         "value": round(value, 2),
@@ -916,22 +1008,65 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"blast_3d {a.n}^3 periodic, PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3",
+        "config": {"workload": WORKLOADS[a.workload]["what"].format(n=a.n),
                    "cells": cells, "launch": "hipGraph replay per step",
-                   "variant": r64["variant"]},
+                   "variant": r64["variant"],
+                   "variant_source": "autotuned in this run" if not fixed
+                   else "the workload's recorded autotuner choice",
+                   "fixed_steps": a.fixed_steps},
         "roofline": roof,
         "fractions": fractions(ms / a.steps, cells, BYTES_FP64, FP64_PEAK_FLOPS,
                                stream["triad_GBs"]),
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
+        "conservation_drift": drift64,
+        "counters": cnt64,
         "mixed": mixed,
         "hbm_stream": stream,
         "pcie_inclusive": {"value": pcie, "unit": "Mcell-updates/s",
                            "what": f"host set_state + {a.steps} steps + host get_state, FP64"},
-        "counters": r64["counters"],
         "cpu_baseline": cpu,
         "source_sha": source_sha(),
     }
     print(json.dumps(line), flush=True)
+
+
+def with_variant(variant, fn, *args, **kw):
+    """fn(*args) with the library's launch variant fixed (MHD_VARIANT) when
+    variant is given, else as the flags choose."""
+    if variant is None:
+        return fn(*args, **kw)
+    os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
+    try:
+        return fn(*args, **kw)
+    finally:
+        del os.environ["MHD_VARIANT"]
+
+
+def fixed_run(wl, precision, steps, variant):
+    """The workload's state after its fixed step count (graph replay, the
+    timed run's variant) and the event counters of box 0."""
+    from paper_2606_12753_amd import mhd
+
+    def go():
+        with mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH) as sim:
+            for b, st in enumerate(wl.states):
+                sim.set_state(b, st.cons, st.bface, 0.0)
+            sim.step(steps)
+            cons, bface, _ = sim.get_state(0)
+            return (cons, bface), sim.counters(0)
+    return with_variant(variant, go)
+
+
+def drift(cons0, cons1):
+    """|sum q(t) - sum q(0)| / sum |q(0)| of the mass, momentum and energy
+    totals (exact sums): conservation of a periodic box."""
+    import math
+    import numpy as np
+    out = {}
+    for name, a, b in zip(("mass", "mx", "my", "mz", "energy"), cons0, cons1):
+        den = float(np.sum(np.abs(a))) or 1.0
+        out[name] = float(abs(math.fsum(b.ravel()) - math.fsum(a.ravel())) / den)
+    return out
 
 
 if __name__ == "__main__":

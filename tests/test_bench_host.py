@@ -72,10 +72,10 @@ def test_ingest_counters_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     _counter_csv(f, "FETCH_SIZE", fetch)
     _counter_csv(w, "WRITE_SIZE", write)
     out = tmp_path / "traffic.json"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    monkeypatch.setattr(bench, "profile_file", lambda kind, a, ext: str(out))
     args = bench.argparse.Namespace(ingest_counters=(str(f), str(w)), n=8, fetch_command="f",
                                     write_command="w", variant64="1,2,64,0,64",
-                                    variant_mixed="1,8,64,0,128")
+                                    variant_mixed="1,8,64,0,128", workload="blast")
     bench.ingest_counters(args)
     rec = json.loads(out.read_text())
     assert rec["scale"] == {"fetch": 2.0, "write": 1.0}
@@ -101,4 +101,36 @@ def test_counter_records_take_the_variants_of_their_commands(monkeypatch):
     assert bench.parse().variant64 == "3,9,16,1,32"
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
+    fixed = bench.BENCH_VARIANTS[("turbulence", 512)]
+    assert (a.workload, a.n, a.fixed_steps) == ("turbulence", 512, 200)
+    assert (a.variant64, a.variant_mixed) == (fixed["fp64"], fixed["mixed"])
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "blast", "--n", "96"])
+    a = bench.parse()
+    assert (a.n, a.fixed_steps, a.cpu_n) == (96, 100, 256)
     assert (a.variant64, a.variant_mixed) == ("1,1,64,0,64", "1,1,64,0,128")
+
+
+def test_recorded_kernel_needs_matching_source_and_variant(tmp_path):
+    """A counter record is used only for the kernel source and the launch
+    variant it was taken on."""
+    v = [1, 2, 64, 0, 64]
+    rec = {"source_sha": bench.source_sha(),
+           "fp64": {"kernels": {"sweep_x": {"launch": bench.launch_key("sweep_x", "double", v),
+                                            "bytes": 123, "valu_issue": 0.5}}}}
+    path = tmp_path / "r.json"
+    path.write_text(json.dumps(rec))
+    assert bench.recorded_kernel(str(path), 0, "sweep_x", v)["bytes"] == 123
+    assert bench.recorded_kernel(str(path), 0, "sweep_x", [3, 2, 64, 0, 64]) is None
+    assert bench.recorded_kernel(str(path), 1, "sweep_x", v) is None
+    rec["source_sha"] = "0" * 16
+    path.write_text(json.dumps(rec))
+    assert bench.recorded_kernel(str(path), 0, "sweep_x", v) is None
+
+
+def test_drift_of_totals():
+    import numpy as np
+    a = [np.array([1.0, 2.0, -3.0])] * 5
+    b = [np.array([1.0, 2.0, -3.0 + 6e-12])] * 5
+    d = bench.drift(a, b)
+    assert set(d) == {"mass", "mx", "my", "mz", "energy"}
+    assert abs(d["mass"] - 1e-12) < 1e-15
