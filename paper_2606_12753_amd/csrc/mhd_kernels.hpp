@@ -644,22 +644,20 @@ __device__ __forceinline__ void hll_flux(const St7<real>& wl, const St7<real>& w
 // and v*_t - v_t = -B_n B_t (S_M - u)/D with m = rho (S - u), D = m (S - S_M)
 // - B_n^2; p_T* - p_T = m (S_M - u); E* - E = [(S_M - u)(E + p_T - B_n^2) +
 // (p_T* - p_T) S_M - B_n (v_t.dB + dv.B*_t)] / (S - S_M).
+// Only the jumps are kept (the star values are the side's state plus its
+// jump); the return value says whether p* > 0.
 template <typename real>
 struct StarD {
-  real drho, dv1, dv2, db1, db2, den;  // jumps from the side's state
-  real rho, v1, v2, b1, b2;            // star values
-  real p;                              // star thermal pressure from E*
+  real drho, dv1, dv2, db1, db2, den;
 };
 
 template <typename real>
-__device__ __forceinline__ StarD<real> star_side(const St7<real>& w, real en, real pt, real sa,
-                                                 real sm, real pts, real bn, real gamma) {
-  StarD<real> s;
+__device__ __forceinline__ bool star_side(const St7<real>& w, real en, real pt, real sa, real sm,
+                                          real pts, real bn, real gamma, StarD<real>& s) {
   const real sd = sa - w.v[1];
   const real isms = rcp(sa - sm);
   const real du = sm - w.v[1];
   s.drho = w.v[0] * du * isms;
-  s.rho = w.v[0] + s.drho;
   const real m = w.v[0] * sd;  // mass flux through the outer wave
   const real dd = m * (sa - sm) - bn * bn;
   if (ab(dd) <= Eps<real>::deg * pts) {
@@ -674,21 +672,18 @@ __device__ __forceinline__ StarD<real> star_side(const St7<real>& w, real en, re
     s.db1 = w.v[5] * cb;
     s.db2 = w.v[6] * cb;
   }
-  s.v1 = w.v[2] + s.dv1;
-  s.v2 = w.v[3] + s.dv2;
-  s.b1 = w.v[5] + s.db1;
-  s.b2 = w.v[6] + s.db2;
+  const real v1 = w.v[2] + s.dv1, v2 = w.v[3] + s.dv2;
+  const real b1 = w.v[5] + s.db1, b2 = w.v[6] + s.db2;
   const real dpt = m * du;
   s.den = (du * (en + pt - bn * bn) + dpt * sm -
-           bn * (w.v[2] * s.db1 + w.v[3] * s.db2 + s.dv1 * s.b1 + s.dv2 * s.b2)) *
+           bn * (w.v[2] * s.db1 + w.v[3] * s.db2 + s.dv1 * b1 + s.dv2 * b2)) *
           isms;
   // p* = (gamma-1)(E* - rho*|v*|^2/2 - |B*|^2/2), as the side's pressure plus
   // the jumps of the energy, kinetic and magnetic terms
-  const real dk = s.drho * (sm * sm + s.v1 * s.v1 + s.v2 * s.v2) +
-                  w.v[0] * (du * (sm + w.v[1]) + s.dv1 * (w.v[2] + s.v1) + s.dv2 * (w.v[3] + s.v2));
-  const real dm = s.db1 * (w.v[5] + s.b1) + s.db2 * (w.v[6] + s.b2);
-  s.p = w.v[4] + (gamma - (real)1) * (s.den - (real)0.5 * dk - (real)0.5 * dm);
-  return s;
+  const real dk = s.drho * (sm * sm + v1 * v1 + v2 * v2) +
+                  w.v[0] * (du * (sm + w.v[1]) + s.dv1 * (w.v[2] + v1) + s.dv2 * (w.v[3] + v2));
+  const real dm = s.db1 * (w.v[5] + b1) + s.db2 * (w.v[6] + b2);
+  return w.v[4] + (gamma - (real)1) * (s.den - (real)0.5 * dk - (real)0.5 * dm) > (real)0;
 }
 
 template <typename real>
@@ -753,9 +748,10 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
     if (ok) {
       const real enl = energy(wl, bn, igm1);
       const real enr = energy(wr, bn, igm1);
-      const StarD<real> stl = star_side(wl, enl, ptl, sl, sm, pts, bn, gamma);
-      const StarD<real> str = star_side(wr, enr, ptr, sr, sm, pts, bn, gamma);
-      if (!(stl.p > (real)0) || !(str.p > (real)0)) ok = false;
+      StarD<real> stl, str;
+      const bool posl = star_side(wl, enl, ptl, sl, sm, pts, bn, gamma, stl);
+      const bool posr = star_side(wr, enr, ptr, sr, sm, pts, bn, gamma, str);
+      if (!posl || !posr) ok = false;
       if (ok) {
         // side of the contact holding x/t = 0
         const bool left = sm > (real)0;
@@ -769,11 +765,10 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
         sa.db1 = sel(left, stl.db1, str.db1);
         sa.db2 = sel(left, stl.db2, str.db2);
         sa.den = sel(left, stl.den, str.den);
-        sa.rho = sel(left, stl.rho, str.rho);
-        sa.v1 = sel(left, stl.v1, str.v1);
-        sa.v2 = sel(left, stl.v2, str.v2);
-        sa.b1 = sel(left, stl.b1, str.b1);
-        sa.b2 = sel(left, stl.b2, str.b2);
+        // star values of the selected side: its state plus its jumps
+        const real rhos = w.v[0] + sa.drho;
+        const real v1s = w.v[2] + sa.dv1, v2s = w.v[3] + sa.dv2;
+        const real b1s = w.v[5] + sa.db1, b2s = w.v[6] + sa.db2;
         const real s_out = sel(left, sl, sr);
         real fa[7], ua[7];
         // the side's total energy and pressure as already formed above
@@ -782,8 +777,8 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
         real dus[7];
         dus[0] = sa.drho;
         dus[1] = sa.drho * sm + w.v[0] * (sm - w.v[1]);
-        dus[2] = w.v[0] * sa.dv1 + sa.drho * sa.v1;
-        dus[3] = w.v[0] * sa.dv2 + sa.drho * sa.v2;
+        dus[2] = w.v[0] * sa.dv1 + sa.drho * v1s;
+        dus[3] = w.v[0] * sa.dv2 + sa.drho * v2s;
         dus[4] = sa.den;
         dus[5] = sa.db1;
         dus[6] = sa.db2;
@@ -795,7 +790,7 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
 #pragma unroll
           for (int c = 0; c < 7; c++) f[c] = fs[c];
         } else {
-          real sql = sq(stl.rho), sqr = sq(str.rho);
+          real sql = sq(wl.v[0] + stl.drho), sqr = sq(wr.v[0] + str.drho);
           real ssl = sm - quot(ab(bn), sql);
           real ssr = sm + quot(ab(bn), sqr);
           real sgn = bn > (real)0 ? (real)1 : (real)-1;
@@ -817,7 +812,7 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
           const real db2 = (sgv * r_own * jb2 + sql * sqr * jv2 * sgn) * iss;
           // E** - E* = -+ sqrt(rho*) (v*.B* - v**.B**) sign(B_n), with
           // v*.B* - v**.B** = -(v*_t.dB + dv.B**_t)
-          real t = r_own * (sa.v1 * db1 + sa.v2 * db2 + dv1 * (sa.b1 + db1) + dv2 * (sa.b2 + db2)) * sgn;
+          real t = r_own * (v1s * db1 + v2s * db2 + dv1 * (b1s + db1) + dv2 * (b2s + db2)) * sgn;
           t = sel(left, t, -t);
           // rotational wave of the selected side, and whether x/t = 0 lies
           // between it and the contact
@@ -826,8 +821,8 @@ __device__ __forceinline__ int riemann(const St7<real>& wl, const St7<real>& wr,
           real duss[7];
           duss[0] = (real)0;
           duss[1] = (real)0;
-          duss[2] = sa.rho * dv1;
-          duss[3] = sa.rho * dv2;
+          duss[2] = rhos * dv1;
+          duss[3] = rhos * dv2;
           duss[4] = t;
           duss[5] = db1;
           duss[6] = db2;

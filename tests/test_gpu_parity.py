@@ -1041,8 +1041,8 @@ UCT_OPTIONS = dict(rk=3, solver="hlld", recon="prim", limiter="vanleer", emf="uc
 def test_upwind_ct_ensemble_and_blast():
     """Upwind CT in an ensemble of 3D, 2D and 1D boxes with outflow walls
     (SSP-RK3, van Leer slopes, graph replay, persistent grid) and through
-    the strong shocks of a small blast: within the FP64 bar of the oracle; the
-    mixed path within its bar, div B at rounding."""
+    the strong shocks of a small blast: within the FP64 bar of the oracle
+    (its mixed path is checked in test_mixed_low_beta_blast_every_corner_emf)."""
     boxes, states = [], []
     for n, seed, bc in [((22, 17, 13), 51, (1, 0, 0)), ((31, 19, 1), 52, (0, 1, 0)),
                         ((1, 36, 1), 53, (0, 1, 0))]:
@@ -1054,20 +1054,50 @@ def test_upwind_ct_ensemble_and_blast():
     for i, g in enumerate(res):
         o = oracle_run(boxes[i], states[i], 3, **UCT_OPTIONS)
         assert_fp64_parity(g, o, f"uct box {i}")
-    # the low-beta blast (p = 0.1 against |B|^2/2 = 50) keeps the mixed
-    # path's pressure within its bar from about 48^3 on (at 24^3 the
-    # contact-upwinded average misses it too)
     wl2 = W.blast_3d(n=48)
     spec2, st2 = wl2.boxes[0], wl2.states[0]
     o = oracle_run(spec2, st2, 20, emf="uct_hll")
     g = gpu_run(wl2, 20, flags=mhd.MHD_F_GRAPH, emf="uct_hll")[0]
     assert_fp64_parity(g, o, "blast uct")
-    m = gpu_run(wl2, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, emf="uct_hll")[0]
-    mp, mb = pressure_bmag(spec2, m[0], m[1])
-    op, ob = pressure_bmag(spec2, o[0], o[1])
-    for name, a, b in (("rho", m[0][0], o[0][0]), ("p", mp, op), ("|B|", mb, ob)):
-        assert rel_l1(a, b) <= TOLMIX, name
-    assert divb_norm(spec2, m[1])[0] <= 1e-12
+
+
+# Measured on one MI355X: 2.27e-4 (jump-form Riemann solver; 1.83e-4 with the
+# earlier form, whose 48^3 error was twice as large).  See
+# test_mixed_low_beta_blast_every_corner_emf.
+CONTACT_EMF_24_BOUND = 3e-4
+
+
+@pytest.mark.parametrize("n", [24, 48])
+@pytest.mark.parametrize("emf", ["contact", "e0", "arith", "uct_hll"])
+def test_mixed_low_beta_blast_every_corner_emf(n, emf):
+    """The mixed path on the low-beta blast (p = 0.1 against |B|^2/2 = 50,
+    beta = 0.002) at 24^3 and 48^3 after 20 steps, against the oracle, for
+    every corner EMF.  The Riemann solver forms its star states as jumps from
+    each side's state, so two states at rest give an exactly zero flux
+    difference in FP32 as in FP64 (before that form, the rounding of the
+    magnetically dominated total energy moved the ambient pressure).
+    Every case meets the mixed bar except one: the contact-upwinded EMF at
+    24^3.  Its corner average switches with the sign of the FP32 mass flux,
+    and there the blast fills much of the box, 2% of the cell updates hit the
+    pressure floor and the FP64 solution itself has negative recovered
+    pressures.  A change of B by one FP32 rounding moves the pressure by
+    (gamma - 1)|B| dB, 500 times its own relative size at this beta.  That
+    case is held to the measured level (CONTACT_EMF_24_BOUND); the E0,
+    arithmetic and upwind-CT averages, which are continuous in the mass flux,
+    and every average at 48^3 meet 1e-4."""
+    wl = W.blast_3d(n=n)
+    spec, st = wl.boxes[0], wl.states[0]
+    o = oracle_run(spec, st, 20, emf=emf)
+    m = gpu_run(wl, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH, emf=emf)[0]
+    mp, mb = pressure_bmag(spec, m[0], m[1])
+    op, ob = pressure_bmag(spec, o[0], o[1])
+    errs = {"rho": rel_l1(m[0][0], o[0][0]), "p": rel_l1(mp, op), "|B|": rel_l1(mb, ob)}
+    print(f"[mixed] blast {n}^3 x 20 emf={emf}: " +
+          ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    bar = CONTACT_EMF_24_BOUND if (n == 24 and emf == "contact") else TOLMIX
+    for k, e in errs.items():
+        assert e <= bar, (n, emf, k, e)
+    assert divb_norm(spec, m[1])[0] <= 1e-12
 
 
 @pytest.mark.parametrize("precision,kw", [
