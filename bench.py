@@ -60,16 +60,30 @@ WORKLOADS = {
                            "(beta ~ 1), PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3"},
     "blast": {"n": 256, "fixed_steps": 100, "cpu_n": 256, "cpu_steps": 12,
               "what": "blast_3d {n}^3 periodic, PLM-minmod+HLLD+CT+SSP-RK2, CFL 0.3"},
+    # the paper's profiled case (its Tables 2 and 5): counter records and the
+    # per-kernel table; the timed line stays on the workloads above
+    "orszag_tang": {"n": 352, "fixed_steps": 10, "cpu_n": 128, "cpu_steps": 4,
+                    "what": "orszag_tang_3d {n}^3 periodic, PLM-minmod+HLLD+CT+SSP-RK3, CFL 0.3"},
 }
 BENCH_VARIANTS = {
-    ("turbulence", 512): {"fp64": "1,2,64,0,64", "mixed": "1,9,64,0,128"},
+    ("turbulence", 512): {"fp64": "1,1,64,0,64", "mixed": "1,9,64,0,128"},
     ("blast", 256): {"fp64": "1,2,64,0,64", "mixed": "1,9,64,0,128"},
+    ("orszag_tang", 352): {"fp64": "1,2,64,0,64", "mixed": "1,9,64,0,128"},
 }
 
 
 def make_workload(name, n):
     from paper_2606_12753_amd import workloads
-    return workloads.turbulence_3d(n=n) if name == "turbulence" else workloads.blast_3d(n=n)
+    if name == "turbulence":
+        return workloads.turbulence_3d(n=n)
+    if name == "orszag_tang":
+        return workloads.orszag_tang_3d(n=n)
+    return workloads.blast_3d(n=n)
+
+
+def wl_rk(wl):
+    """Runge-Kutta stages of a workload (the paper's case runs three)."""
+    return int(wl.meta.get("rk", 2)) if getattr(wl, "meta", None) else 2
 
 
 def profile_file(kind, a, ext):
@@ -303,7 +317,7 @@ def pcie_inclusive(wl, precision, steps, variant):
     from paper_2606_12753_amd import mhd
     os.environ["MHD_VARIANT"] = ",".join(str(v) for v in variant)
     try:
-        sim = mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH)
+        sim = mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH, rk=wl_rk(wl))
         st = wl.states[0]
         sim.set_state(0, st.cons, st.bface, 0.0)
         sim.step(1)
@@ -360,7 +374,7 @@ def kernel_times(wl, precision, steps, variant):
     try:
         stream = torch.cuda.Stream()
         sim = mhd.Sim(wl.boxes, precision=precision, stream=stream.cuda_stream,
-                      flags=mhd.MHD_F_TIMING)
+                      flags=mhd.MHD_F_TIMING, rk=wl_rk(wl))
         for b, st in enumerate(wl.states):
             sim.set_state(b, st.cons, st.bface, 0.0)
         sim.step(2)
@@ -391,10 +405,11 @@ def recorded_kernel(path, precision, dom, variant):
     return None
 
 
-def roofline(kt, cells, table, variant, precision, a):
+def roofline(kt, cells, table, variant, precision, a, rk=2):
     per_step = {k: kt[k][0] * kt[k][1] for k in table}
     dom = max(per_step, key=per_step.get)
-    bytes_per_launch = 0.5 * (table[dom][0] + table[dom][1]) * cells
+    # mean over the stages of a step: the first stage, then rk - 1 later ones
+    bytes_per_launch = (table[dom][0] + (rk - 1) * table[dom][1]) / rk * cells
     avg_ms = kt[dom][0]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     k = recorded_kernel(profile_file("hbm_traffic", a, "json"), precision, dom, variant)
@@ -503,7 +518,7 @@ def counter_pass(a):
     for prec, text in ((mhd.MHD_FP64, a.variant64), (mhd.MHD_MIXED, a.variant_mixed)):
         os.environ["MHD_VARIANT"] = ",".join(str(v) for v in parse_variant(text))
         try:
-            sim = mhd.Sim(wl.boxes, precision=prec)
+            sim = mhd.Sim(wl.boxes, precision=prec, rk=wl_rk(wl))
             for b, st in enumerate(wl.states):
                 sim.set_state(b, st.cons, st.bface, 0.0)
             sim.step(a.steps)
@@ -568,7 +583,8 @@ def ingest_counters(a):
             f = sum(rec["fetch"]) / len(rec["fetch"])
             w = sum(rec["write"]) / len(rec["write"])
             byts = (f * scale["fetch"] + w * scale["write"]) * 1024
-            alg = 0.5 * (algo[kind][0] + algo[kind][1]) * cells
+            rk = 3 if a.workload == "orszag_tang" else 2
+            alg = (algo[kind][0] + (rk - 1) * algo[kind][1]) / rk * cells
             real = "double" if key == "fp64" else "float"
             kernels[kind] = {"launch": launch_key(kind, real, parse_variant(text)),
                              "kernel": sorted(rec["names"]), "dispatches": len(rec["fetch"]),
@@ -624,9 +640,11 @@ def ingest_sq(a):
              "SGPR_Count, LDS and scratch are rocprofv3's per-dispatch fields (VGPR_Count is half "
              "the compiler's register count on this target: 72 for the FP64 x sweep's 142).", "",
              "| precision | kernel | waves | VALU / wave | SALU / wave | VMEM rd / wave | "
-             "LDS / wave | LDS conflict cycles / LDS instr | avg us | VALU issue | VGPR_Count | "
-             "SGPR_Count | LDS bytes | scratch bytes |",
-             "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+             "LDS / wave | LDS conflict cycles / LDS instr | avg us | algorithmic GB/s | "
+             "VALU issue | VGPR_Count | SGPR_Count | LDS bytes | scratch bytes |",
+             "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    rk = 3 if a.workload == "orszag_tang" else 2
+    cells = a.n ** 3
     record = {"workload": f"{a.workload} {a.n}^3", "source_sha": source_sha(),
               "commands": {"sq": a.sq_command, "trace": a.trace_command}}
     for key, text in (("fp64", a.variant64), ("mixed", a.variant_mixed)):
@@ -643,10 +661,12 @@ def ingest_sq(a):
         issue = valu / (avg * VALU_ISSUE_PER_S) if d else float("nan")
         vg, sg, lb, sc = res.get(name, ("-", "-", "-", "-"))
         conf = mean("SQ_LDS_BANK_CONFLICT") / lds if lds > 0 else 0.0
+        algo = (BYTES_FP64 if key == "fp64" else BYTES_MIXED)[kind]
+        gbs = (algo[0] + (rk - 1) * algo[1]) / rk * cells / avg / 1e9 if d else float("nan")
         lines.append(f"| {key} | `{name.replace('void ', '').replace('(mhd::Launch)', '')}` | "
                      f"{waves:.0f} | {valu / waves:.0f} | {mean('SQ_INSTS_SALU') / waves:.0f} | "
                      f"{mean('SQ_INSTS_VMEM_RD') / waves:.1f} | {lds / waves:.1f} | {conf:.3f} | "
-                     f"{avg * 1e6:.1f} | {issue:.2f} | {vg} | {sg} | {lb} | {sc} |")
+                     f"{avg * 1e6:.1f} | {gbs:.0f} | {issue:.2f} | {vg} | {sg} | {lb} | {sc} |")
         real = "double" if key == "fp64" else "float"
         variant = record[key]["variant"]
         if kernel_name(kind, real, variant) in name:
@@ -655,6 +675,18 @@ def ingest_sq(a):
                 "valu_per_wave": round(valu / waves, 1), "valu_issue": round(issue, 3),
                 "lds_conflict_per_instr": round(conf, 4), "avg_us_unfused": round(avg * 1e6, 1),
                 "vgpr_count": vg, "scratch_bytes": sc}
+    if a.workload == "orszag_tang":
+        lines += ["", "Context, not a target: the paper's own kernel table for this case on one "
+                  "MI250X GCD (its Table 5, section 3.2; OpenMP, FP64, one direction of one "
+                  "stage per invocation, unified memory), time / memory bandwidth / VGPRs per "
+                  "wavefront / scratch / VALU utilisation: HLLD_i 29.7 ms / 566 GB/s / 120 / 32 B "
+                  "/ 15%; HLLD_j,k 110.6 ms / 248 GB/s / 108 / 32 B / 4%; Reconstruct 25.7 ms / "
+                  "417 GB/s / 92 / 32 B / 58%; RightHandSide 35.0 ms / 447 GB/s / 88 / 32 B / 3%; "
+                  "CT_EMF 32.4 ms / 717 GB/s / 88 / 32 B / 0.3%; US 119.8 ms / 290 GB/s / 56 / "
+                  "32 B / 4%.  Here reconstruction, Riemann solve and flux divergence of a "
+                  "direction are one kernel (the x sweep, the y and z marches), CT_EMF is the "
+                  "corner-EMF kernel and the face update with the stage combine is the "
+                  "face kernel; the algorithmic GB/s count each kernel's compulsory bytes once."]
     with open(profile_file("sq_counters", a, "md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     with open(profile_file("sq_counters", a, "json"), "w") as fh:
@@ -948,14 +980,15 @@ def main():
         fixed = {mhd.MHD_FP64: parse_variant(a.variant64), mhd.MHD_MIXED: parse_variant(a.variant_mixed)}
         flags = mhd.MHD_F_GRAPH
     print("# FP64 timed run", file=sys.stderr, flush=True)
+    rk = wl_rk(wl)
     r64 = with_variant(fixed.get(mhd.MHD_FP64), run_gpu, wl, mhd.MHD_FP64, a.steps, a.warmup,
-                       flags, a.repeats)
+                       flags, a.repeats, rk=rk)
     r64["sim"].close()
     ms = r64["ms"]
     value = cells * a.steps / (ms * 1e-3) / 1e6
     print("# FP64 kernel timing pass", file=sys.stderr, flush=True)
     kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10), r64["variant"])
-    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64, a)
+    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64, a, rk)
     print("# FP64 PCIe-inclusive run", file=sys.stderr, flush=True)
     pcie = pcie_inclusive(wl, mhd.MHD_FP64, a.steps, r64["variant"])
     mixed = None
@@ -965,7 +998,7 @@ def main():
     if not a.no_mixed:
         print("# mixed timed run", file=sys.stderr, flush=True)
         rmx = with_variant(fixed.get(mhd.MHD_MIXED), run_gpu, wl, mhd.MHD_MIXED, a.steps,
-                           a.warmup, flags, a.repeats)
+                           a.warmup, flags, a.repeats, rk=rk)
         rmx["sim"].close()
         ktm = kernel_times(wl, mhd.MHD_MIXED, min(a.steps, 10), rmx["variant"])
         print(f"# mixed run over the fixed step count ({a.fixed_steps})", file=sys.stderr,
@@ -984,7 +1017,7 @@ def main():
             "conservation_drift": drift(wl.states[0].cons, smx[0]),
             "counters": cntmx,
             "variant": rmx["variant"],
-            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED, a),
+            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED, a, rk),
             "kernels_ms": {k: round(v[0], 4) for k, v in ktm.items() if v[1]},
         }
         del smx
@@ -1048,7 +1081,7 @@ def fixed_run(wl, precision, steps, variant):
     from paper_2606_12753_amd import mhd
 
     def go():
-        with mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH) as sim:
+        with mhd.Sim(wl.boxes, precision=precision, flags=mhd.MHD_F_GRAPH, rk=wl_rk(wl)) as sim:
             for b, st in enumerate(wl.states):
                 sim.set_state(b, st.cons, st.bface, 0.0)
             sim.step(steps)
