@@ -254,8 +254,36 @@ int mhd_tuning(mhd_ctx *ctx, int32_t variant[5]);
  * workspace is left alone).  NULL is a no-op. */
 void mhd_destroy(mhd_ctx *ctx);
 
+/* Allocation-free CFL time step of one box whose state the caller holds in
+ * device memory: a variant of mhd_dt for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  It needs no context and calls no hipMalloc,
+ * hipFree or other allocating routine: its per-tile partial maxima go to a
+ * static device array of the library (8 MiB, one copy per GPU, held until
+ * the process ends).
+ * Arguments: box as for mhd_create (validated the same way); cons[5] and
+ * bface[3] are DEVICE pointers to the state in the boundary layout of this
+ * file (read only, not retained); p_floor the pressure floor of the
+ * primitive recovery (<= 0: 1e-10); dt_out a DEVICE pointer that receives
+ * one double, dt = cfl / max over cells and active axes d of
+ * (|v_d| + c_f,d) / dx_d, the value mhd_dt returns for the same state (0 if
+ * a cell is non-physical: rho <= 0 or a non-finite state); stream a
+ * hipStream_t (NULL: the null stream).  The two kernels are enqueued on the
+ * stream and the call returns without waiting.
+ * Limit: at most 2^28 cells (2^20 tiles of 256 cells); larger boxes are
+ * rejected with MHD_E_INVAL before any device work.  All calls on one GPU
+ * share its scratch array, which keeps the last call's partials: calls that
+ * overlap in time on one GPU (different streams or host threads) race.
+ * Errors: MHD_E_INVAL (bad box, NULL pointer, non-finite p_floor, box too
+ * large), MHD_E_DEVICE (no device, symbol lookup or launch failure); the
+ * message is read with mhd_last_error(NULL). */
+int mhd_dt_noalloc(const mhd_box *box, const double *const cons[5],
+                   const double *const bface[3], double p_floor, double *dt_out,
+                   void *stream);
+
 /* Message of the last failed call on ctx ("" if none); for ctx == NULL, the
- * last failure of mhd_create / mhd_workspace_bytes in this thread. */
+ * last failure of mhd_create / mhd_workspace_bytes / mhd_dt_noalloc in this
+ * thread. */
 const char *mhd_last_error(const mhd_ctx *ctx);
 
 #ifdef __cplusplus

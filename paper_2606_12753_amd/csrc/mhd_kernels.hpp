@@ -864,7 +864,9 @@ __device__ __forceinline__ void count(unsigned long long* c, int fl) {
 }
 
 // CFL rate of a cell: max over active axes of (|v_d| + c_f,d) / dx_d
-__device__ __forceinline__ double cfl_rate(CBox& b, const PrimD& w) {
+// (the box type B is a device box descriptor or a FlatBox kernel argument)
+template <typename B>
+__device__ __forceinline__ double cfl_rate(B& b, const PrimD& w) {
   const double v[3] = {w.vx, w.vy, w.vz};
   const double bc[3] = {w.bx, w.by, w.bz};
   double l = 0.0;
@@ -1870,6 +1872,57 @@ static __global__ __launch_bounds__(kTPB) void k_dt(const Box* boxes, int mode, 
       b.scal[1] = t + dt;
     }
   }
+}
+
+// CFL time step of one box whose state the caller holds in the boundary
+// layout (five cell arrays, three face arrays with both bounding faces),
+// described by value in the kernel arguments, for the allocation-free entry
+// point: k_lambda_flat writes one max rate per tile of kTPB cells into the
+// caller-provided partials, k_dt_flat reduces them into dt = cfl / max.  A
+// non-physical cell makes its rate infinite, so the step is zero.
+struct FlatBox {
+  const double* U[kNQ];
+  const double* B[3];
+  int n[3];
+  int act[3];
+  double idx[3];
+  double gamma, pfloor, cfl;
+  int ntiles;
+};
+
+static __global__ __launch_bounds__(kTPB) void k_lambda_flat(FlatBox f, double* part) {
+  const int tile = blockIdx.x;
+  const int p = tile * kTPB + (int)threadIdx.x;
+  const int nx = f.n[0], ny = f.n[1];
+  double lmax = 0.0;
+  if (p < nx * ny * f.n[2]) {
+    int pos[3];
+    unflatten(p, nx, ny, pos);
+    const int i = pos[0], j = pos[1], k = pos[2];
+    const int fx = (k * ny + j) * (nx + 1) + i;
+    const int fy = (k * (ny + 1) + j) * nx + i;
+    const double bx = 0.5 * (ld<double>(f.B[0], fx) + ld<double>(f.B[0], fx + 1));
+    const double by = 0.5 * (ld<double>(f.B[1], fy) + ld<double>(f.B[1], fy + nx));
+    const double bz = 0.5 * (ld<double>(f.B[2], p) + ld<double>(f.B[2], p + nx * ny));
+    PrimD w;
+    const int fl = cons_to_prim(ld<double>(f.U[0], p), ld<double>(f.U[1], p), ld<double>(f.U[2], p),
+                                ld<double>(f.U[3], p), ld<double>(f.U[4], p), bx, by, bz, f.gamma,
+                                f.pfloor, w);
+    lmax = (fl & 2) ? __builtin_inf() : cfl_rate(f, w);
+  }
+  const double m = block_max(lmax);
+  if (threadIdx.x == 0) part[tile] = m;
+}
+
+static __global__ __launch_bounds__(kTPB) void k_dt_flat(const double* part, int ntiles, double cfl,
+                                                         double* dt_out) {
+  double m = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += kTPB) {
+    const double v = part[t];
+    if (v > m) m = v;
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) dt_out[0] = cfl / m;
 }
 
 // Periodic-face check of a caller array in the boundary layout: sets *bad

@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1085,3 +1086,117 @@ const char* mhd_last_error(const mhd_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- no-alloc dt
+//
+// Device memory of the allocation-free time-step query: one partial maximum
+// per tile of kTPB cells.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as a device
+// address: the address is looked up per device (hipGetSymbolAddress) on the
+// entry point's first call on that device and cached below.
+namespace {
+
+constexpr int kScratchTiles = 1 << 20;  // 8 MiB: boxes of up to 2^28 cells
+static __device__ __align__(256) double scratch[kScratchTiles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(double** out, std::string& err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return MHD_E_DEVICE;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device index beyond the library's per-device table";
+    return MHD_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return MHD_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MHD_OK;
+}
+
+}  // namespace
+
+extern "C" int mhd_dt_noalloc(const mhd_box* box, const double* const cons[5],
+                              const double* const bface[3], double p_floor, double* dt_out,
+                              void* stream) {
+  std::string err;
+  if (!box) {
+    g_create_error = "mhd_dt_noalloc: box is NULL";
+    return MHD_E_INVAL;
+  }
+  int rc = validate_box(*box, err);
+  if (rc) {
+    g_create_error = "mhd_dt_noalloc: " + err;
+    return rc;
+  }
+  const size_t N = (size_t)box->n[0] * box->n[1] * box->n[2];
+  const size_t ntiles = (N + kTPB - 1) / kTPB;
+  if (ntiles > (size_t)kScratchTiles) {
+    g_create_error = "mhd_dt_noalloc: box of " + std::to_string(N) +
+                     " cells exceeds the scratch capacity of " +
+                     std::to_string((size_t)kScratchTiles * kTPB) + " cells";
+    return MHD_E_INVAL;
+  }
+  if (!cons || !bface || !dt_out) {
+    g_create_error = "mhd_dt_noalloc: cons, bface or dt_out is NULL";
+    return MHD_E_INVAL;
+  }
+  for (int q = 0; q < 5; q++)
+    if (!cons[q]) {
+      g_create_error = "mhd_dt_noalloc: cons array is NULL";
+      return MHD_E_INVAL;
+    }
+  for (int d = 0; d < 3; d++)
+    if (!bface[d]) {
+      g_create_error = "mhd_dt_noalloc: bface array is NULL";
+      return MHD_E_INVAL;
+    }
+  if (!std::isfinite(p_floor)) {
+    g_create_error = "mhd_dt_noalloc: p_floor must be finite";
+    return MHD_E_INVAL;
+  }
+  double* part = nullptr;
+  rc = scratch_on_current_device(&part, err);
+  if (rc) {
+    g_create_error = "mhd_dt_noalloc: " + err;
+    return rc;
+  }
+  mhd::FlatBox f;
+  for (int q = 0; q < 5; q++) f.U[q] = cons[q];
+  for (int d = 0; d < 3; d++) {
+    f.B[d] = bface[d];
+    f.n[d] = box->n[d];
+    f.act[d] = box->n[d] > 1;
+    // the same cell size and reciprocal as a context's box descriptor
+    const double dx = (box->hi[d] - box->lo[d]) / (double)box->n[d];
+    f.idx[d] = 1.0 / dx;
+  }
+  f.gamma = box->gamma;
+  f.pfloor = p_floor > 0.0 ? p_floor : 1e-10;
+  f.cfl = box->cfl;
+  f.ntiles = (int)ntiles;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(mhd::k_lambda_flat, dim3((unsigned)ntiles), dim3(kTPB), 0, st, f, part);
+  hipLaunchKernelGGL(mhd::k_dt_flat, dim3(1), dim3(kTPB), 0, st, (const double*)part, (int)ntiles,
+                     box->cfl, dt_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_error = std::string("mhd_dt_noalloc: launch: ") + hipGetErrorString(e);
+    return MHD_E_DEVICE;
+  }
+  return MHD_OK;
+}

@@ -57,7 +57,7 @@ KERNELS = ["lambda", "dt", "sweep_x", "sweep_y", "sweep_z", "ct_edge", "ct_face"
 EXPORTED = [
     "mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_dt",
     "mhd_get_state", "mhd_counters", "mhd_kernel_times", "mhd_tuning",
-    "mhd_destroy", "mhd_last_error",
+    "mhd_destroy", "mhd_last_error", "mhd_dt_noalloc",
 ]
 
 
@@ -128,6 +128,8 @@ def load():
     lib.mhd_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     lib.mhd_destroy.argtypes = [C.c_void_p]
     lib.mhd_destroy.restype = None
+    lib.mhd_dt_noalloc.argtypes = [C.POINTER(mhd_box), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), C.c_double, C.c_void_p, C.c_void_p]
     lib.mhd_last_error.argtypes = [C.c_void_p]
     lib.mhd_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -322,3 +324,30 @@ class Sim:
         c = (C.c_int64 * 3)()
         self._check(self._lib.mhd_counters(self._h, int(box), c))
         return {"floor": int(c[0]), "hll": int(c[1]), "bad": int(c[2])}
+
+
+def dt_noalloc(spec, cons, bface, dt_out, p_floor: float = 0.0, stream=None):
+    """Allocation-free CFL time step (mhd_dt_noalloc) of one box whose state
+    is held in torch CUDA float64 tensors in the boundary layout; the step is
+    written into ``dt_out`` (a CUDA float64 tensor of at least one element)
+    on ``stream`` (a torch stream or None for the null stream), without
+    waiting."""
+    lib = load()
+    nx, ny, nz = (int(v) for v in spec.n)
+    shapes = [(nz, ny, nx)] * 5 + [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+    arrays = list(cons) + list(bface) + [dt_out]
+    import torch
+    for a, s in zip(arrays, shapes + [None]):
+        if not (_is_torch(a) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()):
+            raise ValueError("dt_noalloc needs contiguous CUDA float64 tensors")
+        if s is not None and tuple(a.shape) != s:
+            raise ValueError(f"need shape {s}, got {tuple(a.shape)}")
+    if dt_out.numel() < 1:
+        raise ValueError("dt_out needs one element")
+    box = _box_struct(spec)
+    ca = (C.c_void_p * 5)(*[a.data_ptr() for a in cons])
+    ba = (C.c_void_p * 3)(*[a.data_ptr() for a in bface])
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = lib.mhd_dt_noalloc(C.byref(box), ca, ba, float(p_floor), C.c_void_p(dt_out.data_ptr()), st)
+    if rc != MHD_OK:
+        raise MhdError(rc, lib.mhd_last_error(None).decode())

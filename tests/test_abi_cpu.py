@@ -132,3 +132,21 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hb, "LIB", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         mhd.load()
+
+
+def test_dt_noalloc_rejects_before_device_work(lib):
+    """The allocation-free time-step query validates on the host: a box
+    beyond its scratch capacity (2^28 cells), a bad box and NULL arrays are
+    rejected with MHD_E_INVAL without touching a device."""
+    import ctypes as C
+    null5 = (C.c_void_p * 5)()
+    null3 = (C.c_void_p * 3)()
+    big = mhd._box_struct(W.BoxSpec((1024, 1024, 257)))
+    assert lib.mhd_dt_noalloc(C.byref(big), null5, null3, 0.0, None, None) == mhd.MHD_E_INVAL
+    assert b"scratch capacity" in lib.mhd_last_error(None)
+    bad = mhd._box_struct(W.BoxSpec((8, 8, 8), gamma=0.5))
+    assert lib.mhd_dt_noalloc(C.byref(bad), null5, null3, 0.0, None, None) == mhd.MHD_E_INVAL
+    ok = mhd._box_struct(W.BoxSpec((8, 8, 8)))
+    assert lib.mhd_dt_noalloc(C.byref(ok), null5, null3, 0.0, None, None) == mhd.MHD_E_INVAL
+    assert b"NULL" in lib.mhd_last_error(None)
+    assert lib.mhd_dt_noalloc(None, null5, null3, 0.0, None, None) == mhd.MHD_E_INVAL
