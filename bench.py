@@ -126,6 +126,21 @@ BYTES_MIXED = {
     "ct_edge": (60, 60),
     "ct_face": (60, 84),
 }
+# x variant 0: no x sweep; the y march reads the state once (64 B) and
+# writes the cell EMF, the x- and y-face EMFs and mass fluxes and the x+y
+# residual (FP64 112 B, mixed 56 B)
+BYTES_FP64_FUSED = {k: v for k, v in BYTES_FP64.items() if k != "sweep_x"}
+BYTES_FP64_FUSED["sweep_y"] = (176, 176)
+BYTES_MIXED_FUSED = {k: v for k, v in BYTES_MIXED.items() if k != "sweep_x"}
+BYTES_MIXED_FUSED["sweep_y"] = (120, 120)
+
+
+def bytes_table(precision, variant):
+    """Algorithmic bytes per cell of each kernel kind for a launch variant."""
+    fused = variant is not None and int(variant[0]) == 0
+    if precision == 0:
+        return BYTES_FP64_FUSED if fused else BYTES_FP64
+    return BYTES_MIXED_FUSED if fused else BYTES_MIXED
 
 
 def parse():
@@ -244,6 +259,9 @@ def kernel_name(kind, real, variant):
     x, m = variant[0], variant[1]
     if kind == "sweep_x":
         return f"mhd::k_sweep_x<{real}, {x}, 0, 0>"
+    if kind == "sweep_y" and x == 0:
+        lw = 1 if real == "float" and m in (5, 6, 7, 9, 10) else 0
+        return f"mhd::k_sweep_march_xy<{real}, {lw}, 0>"
     if kind in ("sweep_y", "sweep_z"):
         d = 1 if kind == "sweep_y" else 2
         if d == 1 and m >= 8:
@@ -271,7 +289,7 @@ def kind_of(name):
     for real, key in (("double", "fp64"), ("float", "mixed")):
         if f"k_sweep_x<{real}," in name:
             return key, "sweep_x"
-        if f"k_sweep_march<{real}, 1," in name:
+        if f"k_sweep_march<{real}, 1," in name or f"k_sweep_march_xy<{real}," in name:
             return key, "sweep_y"
         if f"k_sweep_march<{real}, 2," in name:
             return key, "sweep_z"
@@ -591,7 +609,7 @@ def ingest_counters(a):
             rec[name].append(v)
     out["scale"] = scale
     for key, text in (("fp64", a.variant64), ("mixed", a.variant_mixed)):
-        algo = BYTES_FP64 if key == "fp64" else BYTES_MIXED
+        algo = bytes_table(0 if key == "fp64" else 1, parse_variant(text))
         cells = a.n ** 3
         kernels = {}
         for kind in KINDS:
@@ -679,7 +697,7 @@ def ingest_sq(a):
         issue = valu / (avg * VALU_ISSUE_PER_S) if d else float("nan")
         vg, sg, lb, sc = res.get(name, ("-", "-", "-", "-"))
         conf = mean("SQ_LDS_BANK_CONFLICT") / lds if lds > 0 else 0.0
-        algo = (BYTES_FP64 if key == "fp64" else BYTES_MIXED)[kind]
+        algo = bytes_table(0 if key == "fp64" else 1, record[key]["variant"])[kind]
         gbs = (algo[0] + (rk - 1) * algo[1]) / rk * cells / avg / 1e9 if d else float("nan")
         lines.append(f"| {key} | `{name.replace('void ', '').replace('(mhd::Launch)', '')}` | "
                      f"{waves:.0f} | {valu / waves:.0f} | {mean('SQ_INSTS_SALU') / waves:.0f} | "
@@ -909,13 +927,14 @@ def options_bench(a, flags):
             r["sim"].close()
             kt = kernel_times_of(wl, prec, min(a.steps, 10), r["variant"], kw["rk"], kw["solver"],
                                  kw["recon"], kw["emf"], kw.get("limiter", "minmod"))
-            table = BYTES_FP64 if prec == mhd.MHD_FP64 else BYTES_MIXED
-            xbytes = 0.5 * (table["sweep_x"][0] + table["sweep_x"][1]) * cells
+            table = bytes_table(prec, r["variant"])
+            xk = "sweep_x" if "sweep_x" in table and kt.get("sweep_x") else "sweep_y"
+            xbytes = 0.5 * (table[xk][0] + table[xk][1]) * cells
             row[key] = {"Mcell_updates_per_s": round(cells * a.steps / (r["ms"] * 1e-3) / 1e6, 1),
                         "ms_per_step": round(r["ms"] / a.steps, 4), "variant": r["variant"],
                         "kernels_ms_per_launch": kt,
-                        "sweep_x_hbm_frac": round(xbytes / (kt["sweep_x"] * 1e-3) / 1e9
-                                                  / HBM_PEAK_GBS, 4)}
+                        f"{xk}_hbm_frac": round(xbytes / (kt[xk] * 1e-3) / 1e9
+                                                / HBM_PEAK_GBS, 4)}
         row["speedup_mixed"] = round(row["mixed"]["Mcell_updates_per_s"]
                                      / row["fp64"]["Mcell_updates_per_s"], 3)
         out["options"][name] = row
@@ -1006,7 +1025,8 @@ def main():
     value = cells * a.steps / (ms * 1e-3) / 1e6
     print("# FP64 kernel timing pass", file=sys.stderr, flush=True)
     kt = kernel_times(wl, mhd.MHD_FP64, min(a.steps, 10), r64["variant"])
-    roof = roofline(kt, cells, BYTES_FP64, r64["variant"], mhd.MHD_FP64, a, rk)
+    t64 = bytes_table(mhd.MHD_FP64, r64["variant"])
+    roof = roofline(kt, cells, t64, r64["variant"], mhd.MHD_FP64, a, rk)
     print("# FP64 PCIe-inclusive run", file=sys.stderr, flush=True)
     pcie = pcie_inclusive(wl, mhd.MHD_FP64, a.steps, r64["variant"])
     mixed = None
@@ -1028,14 +1048,16 @@ def main():
             "ms_per_step": round(rmx["ms"] / a.steps, 4),
             "speedup_vs_fp64": round(ms / rmx["ms"], 3),
             "ms_per_step_repeats": [round(t / a.steps, 4) for t in rmx["times"]],
-            "fractions": fractions(rmx["ms"] / a.steps, cells, BYTES_MIXED, FP32_PEAK_FLOPS,
+            "fractions": fractions(rmx["ms"] / a.steps, cells,
+                                   bytes_table(mhd.MHD_MIXED, rmx["variant"]), FP32_PEAK_FLOPS,
                                    stream["triad_GBs"]),
             "accuracy_vs_fp64": acc,
             "after_steps": a.fixed_steps,
             "conservation_drift": drift(wl.states[0].cons, smx[0]),
             "counters": cntmx,
             "variant": rmx["variant"],
-            "roofline": roofline(ktm, cells, BYTES_MIXED, rmx["variant"], mhd.MHD_MIXED, a, rk),
+            "roofline": roofline(ktm, cells, bytes_table(mhd.MHD_MIXED, rmx["variant"]),
+                                 rmx["variant"], mhd.MHD_MIXED, a, rk),
             "kernels_ms": {k: round(v[0], 4) for k, v in ktm.items() if v[1]},
         }
         del smx
@@ -1066,7 +1088,7 @@ def main():
                    else "the workload's recorded autotuner choice",
                    "fixed_steps": a.fixed_steps},
         "roofline": roof,
-        "fractions": fractions(ms / a.steps, cells, BYTES_FP64, FP64_PEAK_FLOPS,
+        "fractions": fractions(ms / a.steps, cells, t64, FP64_PEAK_FLOPS,
                                stream["triad_GBs"]),
         "kernels_ms": {k: round(v[0], 4) for k, v in kt.items() if v[1]},
         "conservation_drift": drift64,

@@ -236,7 +236,10 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
                      int64_t launches[MHD_NKERNELS], int32_t reset);
 
 /* The launch variant in use: [0] min waves per SIMD of the x sweep's
- * register budget (1 = unconstrained, 3, 4), [1] y/z march variant (1:
+ * register budget (1 = unconstrained, 3, 4), or 0: no x sweep, the y march
+ * computes the x faces of its rows (offered for primitive minmod slopes
+ * without the upwind CT when every box has more than one cell along x and
+ * y), [1] y/z march variant (1:
  * unconstrained registers with the update inputs prefetched ahead of the
  * Riemann solve, 2: unconstrained without prefetch, 3 / 4: at least 3 / 4
  * waves per SIMD without prefetch, 5 / 6 / 7: the sliding window kept in

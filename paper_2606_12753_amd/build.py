@@ -2,11 +2,13 @@
 ``libmhd355.so`` inside the package (in-tree, so that it travels with the
 source tree).
 
-FP64 arithmetic is compiled without FMA contraction: every kernel then
-evaluates each formula in the written order, so results do not depend on the
-tiling or launch shape and equal the oracle's.  The mixed path's FP32
-kernels are compiled in their own unit with contraction.  Packed-FP32
-instructions are disabled.
+FP64 units are compiled with FMA contraction inside a statement
+(-ffp-contract=on): every kernel evaluates each formula the same way
+whatever the tiling or launch shape, so FP64 results are identical across
+launch variants, and they agree with the oracle (plain C, no contraction,
+IEEE division) to a few ulps per step.  The mixed path's FP32 kernels are
+compiled in their own units with contraction across statements.
+Packed-FP32 instructions are disabled.
 """
 import os
 import subprocess
@@ -14,9 +16,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhd355.so")
-# (source, extra flags): the FP64 kernels and the host runtime are built
-# without FMA contraction (bit-exact with the oracle); the mixed path's FP32
-# kernels with contraction.
+# (source, extra flags): the FP64 kernels and the host runtime contract
+# within a statement; the mixed path's FP32 kernels across statements.
 UNITS = [
     (os.path.join(CSRC, "mhd_lib.hip"), ["-ffp-contract=on"]),
     (os.path.join(CSRC, "mhd_fp32.hip"), ["-ffp-contract=fast"]),

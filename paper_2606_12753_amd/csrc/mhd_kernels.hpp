@@ -83,6 +83,9 @@ struct Box {
   int xft;            // x sweep: faces per tile
   int ctx;            // corner-EMF kernel: tile width along x (kTPB / ctx
                       // rows), 0 for flat order
+  int ckz;            // corner-EMF kernel: planes per block of the
+                      // column-major tile order, 0 for plane-major order
+  int cfo;            // face update in the corner-EMF kernel's tile order
   int emf;            // corner EMF: 0 contact-upwinded, 1 E0 (derivatives
                       // averaged), 2 mean of the four face EMFs, 3 upwind CT
   int lim;            // slope limiter (0 minmod, 1 MC, 2 van Leer), for the
@@ -1416,6 +1419,246 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
   }
 }
 
+// ---------------------------------------------------------------- fused x+y march
+//
+// The y march with the x faces of its own rows computed in the same kernel:
+// the lanes of a workgroup hold consecutive columns (i, k) of the box, so
+// at every step of the march the row of cells they load is also a row
+// segment along x.  Each lane writes the x-frame primitives of the cell it
+// loads into a three-row LDS ring; two steps later, when that row's cells
+// are completed, every lane computes the x face below its cell from the
+// four cells i-2..i+1 of the ring (cells beyond the workgroup's piece of
+// the row are loaded directly), the x-face fluxes are exchanged through LDS
+// (the face above a cell is its right neighbour's face below, or computed
+// by the last lane of a piece), and the x and y flux differences complete
+// the cell's residual together.  The x sweep, its second read of the state
+// and the x-face hydro flux array it hands to the y march are then not
+// needed; the march also writes what the x sweep wrote for the corner EMFs
+// (cell EMF, x-face EMFs and mass flux), counts floor hits and non-physical
+// cells and, in the first stage, reduces the CFL rate of its cells.  Every
+// x-face flux is the same function of the same values as in the x sweep.
+// Used for boxes whose three axes are active, with primitive slopes.
+template <typename real>
+struct XRing {
+  real q[3][7][kTPB];  // x-frame primitives of three rows, per lane
+  real f[kNQ][kTPB];   // x-face hydro fluxes of the row being completed
+};
+
+// x-frame primitives of cell (i, j, k) of state s
+template <typename real>
+__device__ __forceinline__ St7<real> xprim_of(CBox& b, int s, int i, int j, int k) {
+  PrimD w;
+  load_prim(b, s, map_cell(i, b.n[0], b.per[0]), j, k, w);
+  return rotate<real>(w, 0);
+}
+
+// the x-frame primitives of the cell at x offset d from lane t's column
+// (i, row j, k): from the ring when that cell's column belongs to a live
+// lane of this workgroup in the same row, else loaded
+template <typename real>
+__device__ __forceinline__ St7<real> xneighbour(CBox& b, int s, XRing<real>& xr, int slot, int t,
+                                                int col, int ncols, int i, int j, int k, int d) {
+  const int ii = map_cell(i + d, b.n[0], b.per[0]);
+  const int tt = t + (ii - i);
+  St7<real> q;
+  if (tt >= 0 && tt < kTPB && col + (ii - i) < ncols) {
+#pragma unroll
+    for (int v = 0; v < 7; v++) q.v[v] = xr.q[slot][v][tt];
+  } else {
+    q = xprim_of<real>(b, s, ii, j, k);
+  }
+  return q;
+}
+
+// x-face flux at the lower face of cell (i + d) of row (j, k) from its four
+// stencil cells; writes the face data the corner EMFs read when `store`
+template <typename real, int RS>
+__device__ __forceinline__ void xface(CBox& b, int s, XRing<real>& xr, int slot, int t, int col,
+                                      int ncols, int i, int j, int k, int d, bool store,
+                                      real* fl, int* used) {
+  St7<real> q[4], wl, wr;
+#pragma unroll
+  for (int m = 0; m < 4; m++) q[m] = xneighbour<real>(b, s, xr, slot, t, col, ncols, i, j, k, d + m - 2);
+  plm_face<0>(q[0], q[1], q[2], q[3], wl, wr);
+  // lower face of cell i + d: face index i + d (face n of an outflow axis)
+  const int f = i + d;
+  const int fi = fidx(b, 0, (b.per[0] && f == b.n[0]) ? 0 : f, j, k);
+  const real bn = (real)ld<double>(b.B[s][0], fi);
+  real F[7], fm, sp[2];
+  *used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
+#pragma unroll
+  for (int q2 = 0; q2 < kNQ; q2++) fl[q2] = F[q2];
+  if (store) {
+    st<real>(b.EF[0][0], fi, F[6]);
+    st<real>(b.EF[0][1], fi, -F[5]);
+    st<real>(b.MF[0], fi, fm);
+  }
+}
+
+template <typename real, int LW, int RS>
+__device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, int col, int ncols,
+                                                bool live, int j0, int j1, real (*lds)[kTPB],
+                                                XRing<real>& xr, int lam, double& lmax) {
+  const int t = threadIdx.x;
+  const int n = b.n[1];
+  const int per = b.per[1];
+  auto addr_at = [&](int a) { return addr_of(b, i, map_cell(a, n, per), tr); };
+  // an own cell of the march: its x-frame primitives into the ring; the
+  // x sweep's per-cell work (cell EMF, counters, CFL rate)
+  auto own_cell = [&](int j, const PrimD& w, int fl) {
+    const St7<real> qx = rotate<real>(w, 0);
+#pragma unroll
+    for (int v = 0; v < 7; v++) xr.q[j % 3][v][t] = qx.v[v];
+    if (live) {
+      const int c = cidx(b, i, j, tr);
+      st<real>(b.Ec[0], c, (real)(w.vz * w.by - w.vy * w.bz));
+      st<real>(b.Ec[1], c, (real)(w.vx * w.bz - w.vz * w.bx));
+      st<real>(b.Ec[2], c, (real)(w.vy * w.bx - w.vx * w.by));
+      if (fl) count(b.cnt, fl);
+      if (lam) {
+        const double l = cfl_rate(b, w);
+        if (l > lmax) lmax = l;
+      }
+    }
+  };
+  Window<real, LW, 0> win;
+  if constexpr (LW) {
+    win.lds = lds;
+    win.t = t;
+  }
+  {
+    PrimD w;
+    raw_to_prim(b, load_raw(b, s, addr_at(j0 - 2)), w);
+    const St7<real> q0 = rotate<real>(w, 1);
+    raw_to_prim(b, load_raw(b, s, addr_at(j0 - 1)), w);
+    const St7<real> q1 = rotate<real>(w, 1);
+    const int fl = raw_to_prim(b, load_raw(b, s, addr_at(j0)), w);
+    const St7<real> q2 = rotate<real>(w, 1);
+    own_cell(j0, w, fl);
+    St7<real> dm1;
+#pragma unroll
+    for (int v = 0; v < 7; v++) dm1.v[v] = limit<0>(q1.v[v] - q0.v[v], q2.v[v] - q1.v[v]);
+    win.init(q1, q2, dm1, (real)w.by);
+  }
+  Raw next = load_raw(b, s, addr_at(j0 + 1));
+  real fprev[kNQ];
+  const bool extra = (j1 == n) && (b.nf[1] == n + 1);
+  const int fstride = b.n[0];
+  const int fbase = (tr * b.nf[1]) * b.n[0] + i;
+  const int cbase = (tr * b.n[1]) * b.n[0] + i;
+  // the lane that holds the face above this lane's cell: its right
+  // neighbour in the same row piece, else this lane computes that face
+  const int iu = map_cell(i + 1, b.n[0], b.per[0]);
+  const bool up_in_ring = (i + 1 < b.n[0] || b.per[0]) && t + (iu - i) >= 0 &&
+                          t + (iu - i) < kTPB && col + (iu - i) < ncols;
+  for (int f = j0; f <= j1; ++f) {
+    PrimD w;
+    const int fl = raw_to_prim(b, next, w);
+    const St7<real> q3 = rotate<real>(w, 1);
+    // every lane has read the ring rows of the previous step
+    __syncthreads();
+    if (f + 1 < j1) own_cell(f + 1, w, fl);
+    if (f < j1) next = load_raw(b, s, addr_at(f + 2));
+    St7<real> wl, wr;
+    win.face_and_slide(q3, (real)w.by, (real)b.gamma, wl, wr);
+    const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
+    const real bn = (real)ld<double>(b.B[s][1], fi);
+    real F[7], fm, sp[2];
+    const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
+    real fy[kNQ];
+    fy[0] = F[0];
+    fy[4] = F[4];
+    fy[2] = F[1];
+    fy[3] = F[2];
+    fy[1] = F[3];
+    if (live && (f < j1 || (f == n && extra))) {
+      st<real>(b.EF[1][0], fi, F[6]);
+      st<real>(b.EF[1][1], fi, -F[5]);
+      st<real>(b.MF[1], fi, fm);
+      if (used) atomicAdd(&b.cnt[1], 1ull);
+    }
+    if (f > j0) {
+      // row f - 1 is complete along y: its x faces
+      const int c = f - 1;
+      const int slot = c % 3;
+      real flo[kNQ], fup[kNQ];
+      int ux = 0, uu = 0;
+      const bool up_boundary = !b.per[0] && i + 1 == b.n[0];  // face n of an outflow axis
+      // the face below the cell, then (lanes whose face above is not in the
+      // ring) the face above: one call site, so one copy of the solver
+#pragma unroll 1
+      for (int d = 0; d < 2; d++) {
+        if (d == 1 && up_in_ring) break;
+        real fx[kNQ];
+        int u = 0;
+        xface<real, RS>(b, s, xr, slot, t, col, ncols, i, c, tr, d,
+                        d == 0 ? live : (live && up_boundary), fx, &u);
+#pragma unroll
+        for (int q = 0; q < kNQ; q++) {
+          if (d == 0) flo[q] = fx[q]; else fup[q] = fx[q];
+        }
+        if (d == 0) ux = u; else uu = u;
+      }
+#pragma unroll
+      for (int q = 0; q < kNQ; q++) xr.f[q][t] = flo[q];
+      __syncthreads();
+      if (up_in_ring) {
+#pragma unroll
+        for (int q = 0; q < kNQ; q++) fup[q] = xr.f[q][t + (iu - i)];
+      }
+      if (live) {
+        if (ux) atomicAdd(&b.cnt[1], 1ull);
+        if (uu && up_boundary) atomicAdd(&b.cnt[1], 1ull);
+        const int cprev = cbase + c * fstride;
+        const double idx0 = b.idx[0], idx1 = b.idx[1];
+#pragma unroll
+        for (int q = 0; q < kNQ; q++) {
+          double r = 0.0;
+          r = r - ((double)fup[q] - (double)flo[q]) * idx0;
+          r = r - ((double)fy[q] - (double)fprev[q]) * idx1;
+          st<real>(b.R[q], cprev, (real)r);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kNQ; q++) fprev[q] = fy[q];
+  }
+}
+
+template <typename real, int LW, int RS>
+__global__ __launch_bounds__(kTPB) void k_sweep_march_xy(Launch L) {
+  __shared__ real lds[LW ? 21 : 1][kTPB];
+  __shared__ XRing<real> xr;
+  for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
+    const int tile = tile_of(L, v);
+    if (tile >= L.ntiles) continue;
+    const int bi = find_box(table(L.base) + kYS * (L.nboxes + 1), L.nboxes, tile);
+    CBox& b = box_at(L.boxes, bi);
+    const int lt = tile - table(L.base)[kYS * (L.nboxes + 1) + bi];
+    const int seg = lt % b.yseg;
+    const int ct = lt / b.yseg;
+    const int ncols = b.n[0] * b.n[2];
+    const int col0 = ct * kTPB + (int)threadIdx.x;
+    // lanes past the last column take part in the barriers on a copy of
+    // the last column and store nothing
+    const bool live = col0 < ncols;
+    const int col = live ? col0 : ncols - 1;
+    const int i = col % b.n[0];
+    const int tr = col / b.n[0];
+    const int j0 = seg * b.ysl;
+    const int j1 = min(j0 + b.ysl, b.n[1]);
+    double lmax = 0.0;
+    march_column_xy<real, LW, RS>(b, L.stage, i, tr, col0 < ncols ? col0 : col, ncols, live, j0,
+                                  j1, lds, xr, L.lam, lmax);
+    if (L.lam) {
+      const double m = block_max(lmax);
+      if (threadIdx.x == 0) b.lam[lt] = m;
+    } else {
+      __syncthreads();  // the next tile reuses the LDS
+    }
+  }
+}
+
 // inactive axis D: residual from the earlier axes only, face data from the
 // cell (EMF = cell EMF, mass flux = momentum)
 template <typename real, int D>
@@ -1508,10 +1751,14 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 }
 
 // Position of a lane in the corner-EMF kernel: tiles of ctx x (kTPB / ctx)
-// positions in one xy plane (x fastest, then y, then the plane), so that the
-// row below a lane's row, whose face values and cell EMFs the lane reads,
-// is mostly fetched by the same workgroup.  ctx = 0: flat order over all
-// positions.  Returns false for lanes past the edge.
+// positions in one xy plane, so that the row below a lane's row, whose face
+// values and cell EMFs the lane reads, is mostly fetched by the same
+// workgroup.  Tile order: with ckz = 0 plane by plane (x tiles fastest, then
+// y); with ckz > 0 in blocks of ckz planes, each block patch by patch with
+// the planes of a patch fastest, so the plane below a tile (its other half
+// of the stencil) was read by the tile just before it and is still in the
+// XCD's L2.  ctx = 0: flat order over all positions.  Returns false for
+// lanes past the edge.
 __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int cx = b.ctx;
   if (cx == 0) {
@@ -1523,12 +1770,25 @@ __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int cy = kTPB / cx;
   const int nbx = (b.nf[0] + cx - 1) / cx;
   const int nby = (b.nf[1] + cy - 1) / cy;
-  const int bx = lt % nbx;
-  const int r = lt / nbx;
-  const int by = r % nby;
+  int patch, k;
+  if (b.ckz == 0) {
+    const int np = nbx * nby;
+    k = lt / np;
+    patch = lt - k * np;
+  } else {
+    const int blk = nbx * nby * b.ckz;
+    const int kb = lt / blk;
+    const int k0 = kb * b.ckz;
+    const int keff = min(b.ckz, b.nf[2] - k0);
+    const int r = lt - kb * blk;
+    patch = r / keff;
+    k = k0 + (r - patch * keff);
+  }
+  const int by = patch / nbx;
+  const int bx = patch - by * nbx;
   pos[0] = bx * cx + (int)threadIdx.x % cx;
   pos[1] = by * cy + (int)threadIdx.x / cx;
-  pos[2] = r / nby;
+  pos[2] = k;
   return pos[0] < b.nf[0] && pos[1] < b.nf[1];
 }
 
@@ -1765,7 +2025,9 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
 
 // Face update: dB_d/dt = -[(E_f(e+1/2) - E_f(e-1/2))/dx_e
 //                          - (E_e(f+1/2) - E_e(f-1/2))/dx_f], (d, e, f)
-// cyclic, formed in FP64, then the Runge-Kutta stage combine.
+// cyclic, formed in FP64, then the Runge-Kutta stage combine.  Positions
+// in flat order, or with b.cfo in the corner-EMF kernel's tile order (the
+// plane above, whose edge EMFs a face reads, is then the next tile's).
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -1774,11 +2036,14 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
     const int bi = find_box(table(L.base) + kCTF * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kCTF * (L.nboxes + 1) + bi];
-    const int p = lt * kTPB + (int)threadIdx.x;
-    const int P = b.nf[0] * b.nf[1] * b.nf[2];
-    if (p >= P) continue;
     int pos[3];
-    unflatten(p, b.nf[0], b.nf[1], pos);
+    if (b.cfo) {
+      if (!ct_pos(b, lt, pos)) continue;
+    } else {
+      const int p = lt * kTPB + (int)threadIdx.x;
+      if (p >= b.nf[0] * b.nf[1] * b.nf[2]) continue;
+      unflatten(p, b.nf[0], b.nf[1], pos);
+    }
     const double dt = b.scal[0];
 #pragma unroll
     for (int d = 0; d < 3; d++) {

@@ -188,7 +188,7 @@ int validate_config(const mhd_config* cfg, std::string& err) {
 
 // tiling of one box (the y/z march segment lengths are tunable)
 struct Tiling {
-  int xft, ctx, ysl, yseg, zsl, zseg;
+  int xft, ctx, ckz, cfo, ysl, yseg, zsl, zseg;
   int ntile[6];
 };
 
@@ -237,6 +237,13 @@ Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64) {
       if (w == 0 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256) t.ctx = w;
     }
   }
+  // column-major order of the corner tiles: blocks of ckz planes (see
+  // ct_pos); the face update in the same order (cfo) or flat.
+  t.ckz = 0;
+  t.cfo = 0;
+  if (const char* v = std::getenv("MHD_CKZ")) t.ckz = std::max(0, std::atoi(v));
+  if (const char* v = std::getenv("MHD_CFO")) t.cfo = std::atoi(v) ? 1 : 0;
+  if (t.ctx == 0) t.ckz = t.cfo = 0;
   const long long P = (long long)g.nf[0] * g.nf[1] * g.nf[2];
   if (t.ctx == 0) {
     t.ntile[mhd::kCTE] = (int)((P + kTPB - 1) / kTPB);
@@ -245,7 +252,7 @@ Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64) {
     const long long nbx = (g.nf[0] + t.ctx - 1) / t.ctx, nby = (g.nf[1] + cy - 1) / cy;
     t.ntile[mhd::kCTE] = (int)(nbx * nby * g.nf[2]);
   }
-  t.ntile[mhd::kCTF] = (int)((P + kTPB - 1) / kTPB);
+  t.ntile[mhd::kCTF] = t.cfo ? t.ntile[mhd::kCTE] : (int)((P + kTPB - 1) / kTPB);
 
   t.ntile[mhd::kLAM] = (int)((g.N + kTPB - 1) / kTPB);
   return t;
@@ -283,7 +290,7 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies, bool uct
     for (int d = 0; d < 3; d++) s += 2 * slot(g.F[d] * rs);  // SP
     s += 3 * slot(g.N * rs);                                 // V
   }
-  s += slot((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8);  // lam
+  s += slot((size_t)std::max({t.ntile[mhd::kLAM], t.ntile[mhd::kXS], t.ntile[mhd::kYS]}) * 8);  // lam
   s += slot(4 * 8);                             // scal
   s += slot(3 * 8);                             // cnt
   return s;
@@ -327,6 +334,9 @@ struct mhd_ctx {
   int fz = 0;  // every box: one cell along z, more along y (no z march)
   int sl = 0;  // slope kind: recon + 2 * limiter (MHD_REC_*, MHD_LIM_*)
   int uct = 0;  // corner EMFs by the upwind CT (MHD_EMF_UCT_HLL)
+  int fusable = 0;  // the y march may compute the x faces (x variant 0):
+                    // primitive minmod slopes, no upwind CT, no fused 2D y
+                    // march, x and y active in every box
   double pfloor = 1e-10;
   uint32_t flags = 0;
   int device = 0;
@@ -567,6 +577,22 @@ int autotune(mhd_ctx* c) {
       if ((rc = try_var(&c->var_m, v, set_m))) return rc;
     for (int v : {3, 4})
       if ((rc = try_var(&c->var_x, v, set_x))) return rc;
+    if (c->fusable) {
+      // the x faces in the y march, with the window in registers and in LDS
+      const int mx = c->var_m, xx = c->var_x;
+      for (int v : {2, 6}) {
+        c->var_x = 0;
+        c->var_m = v;
+        float ms = 0.f;
+        if ((rc = trial(c, steps, &ms))) return rc;
+        if (ms < 0.99f * best) {
+          best = ms;
+        } else {
+          c->var_x = xx;
+          c->var_m = mx;
+        }
+      }
+    }
   }
   for (int v : {16, 32, 64, 128})
     if (v != c->var_seg && (rc = try_var(&c->var_seg, v, set_seg))) return rc;
@@ -652,11 +678,13 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
         b.V[d] = take(g.N * rs);
       }
     b.lam = reinterpret_cast<double*>(
-        take((size_t)std::max(t.ntile[mhd::kLAM], t.ntile[mhd::kXS]) * 8));
+        take((size_t)std::max({t.ntile[mhd::kLAM], t.ntile[mhd::kXS], t.ntile[mhd::kYS]}) * 8));
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xft = t.xft;
     b.ctx = t.ctx;
+    b.ckz = t.ckz;
+    b.cfo = t.cfo;
     b.emf = cfg->ct_emf;
     b.lim = cfg->limiter;
     b.ysl = t.ysl;
@@ -841,6 +869,9 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->fz = 1;
   for (int b = 0; b < cfg->nboxes; b++)
     if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;
+  c->fusable = c->sl == 0 && !c->uct && !c->fz;
+  for (int b = 0; b < cfg->nboxes; b++)
+    if (cfg->boxes[b].n[0] == 1 || cfg->boxes[b].n[1] == 1) c->fusable = 0;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";
@@ -866,7 +897,8 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     int x = 1, m = 1, sg = 32, pe = 0, sz = -1;
     const int got = std::sscanf(v, "%d,%d,%d,%d,%d", &x, &m, &sg, &pe, &sz);
     if (got == 4) sz = sg;
-    if ((got == 4 || got == 5) && (x == 1 || x == 3 || x == 4) && (m >= 1 && m <= 10) &&
+    if ((got == 4 || got == 5) && (x == 1 || x == 3 || x == 4 || (x == 0 && c->fusable)) &&
+        (m >= 1 && m <= 10) &&
         sg >= 1 && sg <= 4096 && sz >= 1 && sz <= 4096 && (pe == 0 || pe == 1)) {
       c->var_x = x;
       c->var_m = m;
