@@ -236,8 +236,11 @@ int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
                      int64_t launches[MHD_NKERNELS], int32_t reset);
 
 /* The launch variant in use: [0] min waves per SIMD of the x sweep's
- * register budget (1 = unconstrained, 3, 4), or 0: no x sweep, the y march
- * computes the x faces of its rows (offered for primitive minmod slopes
+ * register budget (1 = unconstrained, 3, 4), or 0 / 2: no x sweep, the y
+ * march computes the x faces of its rows with its sliding window in
+ * registers in workgroups of 512 lanes (0) or, in the mixed path only, in
+ * LDS with 256 lanes (2), and [1] then chooses the z march's variant alone
+ * (offered for primitive minmod slopes
  * without the upwind CT when every box has more than one cell along x and
  * y), [1] y/z march variant (1:
  * unconstrained registers with the update inputs prefetched ahead of the

@@ -901,16 +901,17 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// block-wide max: wavefront butterfly, then across the four wavefronts
+// block-wide max: wavefront butterfly, then across the TPB / 64 wavefronts
+template <int TPB = kTPB>
 __device__ __forceinline__ double block_max(double v) {
-  __shared__ double part[kTPB / 64];
+  __shared__ double part[TPB / 64];
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) part[wid] = v;
   __syncthreads();
   double m = part[0];
 #pragma unroll
-  for (int w = 1; w < kTPB / 64; w++) m = part[w] > m ? part[w] : m;
+  for (int w = 1; w < TPB / 64; w++) m = part[w] > m ? part[w] : m;
   __syncthreads();
   return m;
 }
@@ -1438,10 +1439,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
 // cells and, in the first stage, reduces the CFL rate of its cells.  Every
 // x-face flux is the same function of the same values as in the x sweep.
 // Used for boxes whose three axes are active, with primitive slopes.
-template <typename real>
+template <typename real, int TPB>
 struct XRing {
-  real q[3][7][kTPB];  // x-frame primitives of three rows, per lane
-  real f[kNQ][kTPB];   // x-face hydro fluxes of the row being completed
+  real q[3][7][TPB];  // x-frame primitives of three rows, per lane
+  real f[kNQ][TPB];   // x-face hydro fluxes of the row being completed
 };
 
 // x-frame primitives of cell (i, j, k) of state s
@@ -1455,13 +1456,14 @@ __device__ __forceinline__ St7<real> xprim_of(CBox& b, int s, int i, int j, int 
 // the x-frame primitives of the cell at x offset d from lane t's column
 // (i, row j, k): from the ring when that cell's column belongs to a live
 // lane of this workgroup in the same row, else loaded
-template <typename real>
-__device__ __forceinline__ St7<real> xneighbour(CBox& b, int s, XRing<real>& xr, int slot, int t,
-                                                int col, int ncols, int i, int j, int k, int d) {
+template <typename real, int TPB>
+__device__ __forceinline__ St7<real> xneighbour(CBox& b, int s, XRing<real, TPB>& xr, int slot,
+                                                int t, int col, int ncols, int i, int j, int k,
+                                                int d) {
   const int ii = map_cell(i + d, b.n[0], b.per[0]);
   const int tt = t + (ii - i);
   St7<real> q;
-  if (tt >= 0 && tt < kTPB && col + (ii - i) < ncols) {
+  if (tt >= 0 && tt < TPB && col + (ii - i) < ncols) {
 #pragma unroll
     for (int v = 0; v < 7; v++) q.v[v] = xr.q[slot][v][tt];
   } else {
@@ -1472,13 +1474,14 @@ __device__ __forceinline__ St7<real> xneighbour(CBox& b, int s, XRing<real>& xr,
 
 // x-face flux at the lower face of cell (i + d) of row (j, k) from its four
 // stencil cells; writes the face data the corner EMFs read when `store`
-template <typename real, int RS>
-__device__ __forceinline__ void xface(CBox& b, int s, XRing<real>& xr, int slot, int t, int col,
-                                      int ncols, int i, int j, int k, int d, bool store,
+template <typename real, int RS, int TPB>
+__device__ __forceinline__ void xface(CBox& b, int s, XRing<real, TPB>& xr, int slot, int t,
+                                      int col, int ncols, int i, int j, int k, int d, bool store,
                                       real* fl, int* used) {
   St7<real> q[4], wl, wr;
 #pragma unroll
-  for (int m = 0; m < 4; m++) q[m] = xneighbour<real>(b, s, xr, slot, t, col, ncols, i, j, k, d + m - 2);
+  for (int m = 0; m < 4; m++)
+    q[m] = xneighbour<real, TPB>(b, s, xr, slot, t, col, ncols, i, j, k, d + m - 2);
   plm_face<0>(q[0], q[1], q[2], q[3], wl, wr);
   // lower face of cell i + d: face index i + d (face n of an outflow axis)
   const int f = i + d;
@@ -1495,10 +1498,10 @@ __device__ __forceinline__ void xface(CBox& b, int s, XRing<real>& xr, int slot,
   }
 }
 
-template <typename real, int LW, int RS>
+template <typename real, int LW, int RS, int TPB>
 __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, int col, int ncols,
                                                 bool live, int j0, int j1, real (*lds)[kTPB],
-                                                XRing<real>& xr, int lam, double& lmax) {
+                                                XRing<real, TPB>& xr, int lam, double& lmax) {
   const int t = threadIdx.x;
   const int n = b.n[1];
   const int per = b.per[1];
@@ -1550,7 +1553,7 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
   // neighbour in the same row piece, else this lane computes that face
   const int iu = map_cell(i + 1, b.n[0], b.per[0]);
   const bool up_in_ring = (i + 1 < b.n[0] || b.per[0]) && t + (iu - i) >= 0 &&
-                          t + (iu - i) < kTPB && col + (iu - i) < ncols;
+                          t + (iu - i) < TPB && col + (iu - i) < ncols;
   for (int f = j0; f <= j1; ++f) {
     PrimD w;
     const int fl = raw_to_prim(b, next, w);
@@ -1591,7 +1594,7 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
         if (d == 1 && up_in_ring) break;
         real fx[kNQ];
         int u = 0;
-        xface<real, RS>(b, s, xr, slot, t, col, ncols, i, c, tr, d,
+        xface<real, RS, TPB>(b, s, xr, slot, t, col, ncols, i, c, tr, d,
                         d == 0 ? live : (live && up_boundary), fx, &u);
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
@@ -1625,10 +1628,20 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
   }
 }
 
-template <typename real, int LW, int RS>
-__global__ __launch_bounds__(kTPB) void k_sweep_march_xy(Launch L) {
+// lanes (columns) per workgroup of the y march with the x faces when its
+// window is in registers
+constexpr int kYXW = 2 * kTPB;
+
+// TPB lanes per workgroup: 256, or 512 with the window in registers, so
+// that a periodic row of up to 512 cells lies in one workgroup and every
+// x face above a lane's cell is a face another lane computes (with rows
+// split between workgroups, the last lane of a piece solves one more face
+// and its wavefront runs the solver twice).
+template <typename real, int LW, int RS, int TPB>
+__global__ __launch_bounds__(TPB) void k_sweep_march_xy(Launch L) {
+  static_assert(TPB == kTPB || (TPB == 2 * kTPB && LW == 0), "LDS window: 256 lanes only");
   __shared__ real lds[LW ? 21 : 1][kTPB];
-  __shared__ XRing<real> xr;
+  __shared__ XRing<real, TPB> xr;
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
     const int tile = tile_of(L, v);
     if (tile >= L.ntiles) continue;
@@ -1638,7 +1651,7 @@ __global__ __launch_bounds__(kTPB) void k_sweep_march_xy(Launch L) {
     const int seg = lt % b.yseg;
     const int ct = lt / b.yseg;
     const int ncols = b.n[0] * b.n[2];
-    const int col0 = ct * kTPB + (int)threadIdx.x;
+    const int col0 = ct * TPB + (int)threadIdx.x;
     // lanes past the last column take part in the barriers on a copy of
     // the last column and store nothing
     const bool live = col0 < ncols;
@@ -1648,10 +1661,10 @@ __global__ __launch_bounds__(kTPB) void k_sweep_march_xy(Launch L) {
     const int j0 = seg * b.ysl;
     const int j1 = min(j0 + b.ysl, b.n[1]);
     double lmax = 0.0;
-    march_column_xy<real, LW, RS>(b, L.stage, i, tr, col0 < ncols ? col0 : col, ncols, live, j0,
-                                  j1, lds, xr, L.lam, lmax);
+    march_column_xy<real, LW, RS, TPB>(b, L.stage, i, tr, col0 < ncols ? col0 : col, ncols, live,
+                                       j0, j1, lds, xr, L.lam, lmax);
     if (L.lam) {
-      const double m = block_max(lmax);
+      const double m = block_max<TPB>(lmax);
       if (threadIdx.x == 0) b.lam[lt] = m;
     } else {
       __syncthreads();  // the next tile reuses the LDS
@@ -1754,11 +1767,13 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 // positions in one xy plane, so that the row below a lane's row, whose face
 // values and cell EMFs the lane reads, is mostly fetched by the same
 // workgroup.  Tile order: with ckz = 0 plane by plane (x tiles fastest, then
-// y); with ckz > 0 in blocks of ckz planes, each block patch by patch with
-// the planes of a patch fastest, so the plane below a tile (its other half
-// of the stencil) was read by the tile just before it and is still in the
-// XCD's L2.  ctx = 0: flat order over all positions.  Returns false for
-// lanes past the edge.
+// y).  With ckz > 0 in blocks of ckz planes; within a block, groups of eight
+// neighbouring patches, each group plane by plane.  The hardware deals
+// workgroups to the eight XCDs in turn, so tile t + 8 (the same patch one
+// plane up) runs on the XCD that ran tile t and finds the plane below, the
+// other half of its stencil, in that XCD's L2, while the eight XCDs work on
+// neighbouring patches of one plane at a time.  ctx = 0: flat order over all
+// positions.  Returns false for lanes past the edge.
 __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int cx = b.ctx;
   if (cx == 0) {
@@ -1770,19 +1785,23 @@ __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int cy = kTPB / cx;
   const int nbx = (b.nf[0] + cx - 1) / cx;
   const int nby = (b.nf[1] + cy - 1) / cy;
+  const int np = nbx * nby;
   int patch, k;
   if (b.ckz == 0) {
-    const int np = nbx * nby;
     k = lt / np;
     patch = lt - k * np;
   } else {
-    const int blk = nbx * nby * b.ckz;
+    const int blk = np * b.ckz;
     const int kb = lt / blk;
     const int k0 = kb * b.ckz;
     const int keff = min(b.ckz, b.nf[2] - k0);
     const int r = lt - kb * blk;
-    patch = r / keff;
-    k = k0 + (r - patch * keff);
+    const int g = r / (8 * keff);            // group of eight patches
+    const int ng = min(8, np - 8 * g);       // patches in this group
+    const int rr = r - g * 8 * keff;
+    const int kk = rr / ng;
+    k = k0 + kk;
+    patch = 8 * g + (rr - kk * ng);
   }
   const int by = patch / nbx;
   const int bx = patch - by * nbx;

@@ -192,7 +192,9 @@ struct Tiling {
   int ntile[6];
 };
 
-Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64) {
+// ycols: columns per y-march tile (kTPB, or kYXW for the y march with the
+// x faces in registers, x variant 0)
+Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64, int ycols = kTPB) {
   Tiling t;
   // x sweep: kTPB consecutive faces of the rows per tile when the pieces of
   // rows they touch fit the LDS, else whole rows
@@ -210,7 +212,7 @@ Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64) {
   t.zseg = (g.n[2] + t.zsl - 1) / t.zsl;
   const long long nrows = (long long)g.n[1] * g.n[2];
   t.ntile[mhd::kXS] = (int)((nrows * nf + t.xft - 1) / t.xft);
-  t.ntile[mhd::kYS] = (int)(((long long)g.n[0] * g.n[2] + kTPB - 1) / kTPB * t.yseg);
+  t.ntile[mhd::kYS] = (int)(((long long)g.n[0] * g.n[2] + ycols - 1) / ycols * t.yseg);
   t.ntile[mhd::kZS] = (int)(((long long)g.n[0] * g.n[1] + kTPB - 1) / kTPB * t.zseg);
   // corner-EMF kernel: tiles of ctx x (kTPB / ctx) positions per xy plane,
   // rows of 32 in FP64 and of 128 in the mixed path (measured best on rows
@@ -277,6 +279,15 @@ size_t backup_bytes_of(const Geom& g) {
 // stage states (SSP-RK3)
 int state_copies(const mhd_config* cfg) { return cfg->rk_stages == 3 ? 3 : 2; }
 
+// per-tile CFL partials of a box: one per tile of the kernel that reduces
+// the rate (the x sweep, the y march with the x faces, the mhd_dt query),
+// sized for the y march's shortest segment (one cell) so that no segment
+// length a launch variant or the autotuner sets can overrun it
+size_t lam_slots(const Geom& g, const Tiling& t) {
+  const size_t ymax = ((size_t)g.n[0] * g.n[2] + kTPB - 1) / kTPB * (size_t)g.n[1];
+  return std::max({(size_t)t.ntile[mhd::kLAM], (size_t)t.ntile[mhd::kXS], ymax});
+}
+
 size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies, bool uct) {
   size_t s = 0;
   s += copies * mhd::kNQ * slot(g.N * 8);
@@ -290,7 +301,7 @@ size_t box_bytes(const Geom& g, const Tiling& t, size_t rs, int copies, bool uct
     for (int d = 0; d < 3; d++) s += 2 * slot(g.F[d] * rs);  // SP
     s += 3 * slot(g.N * rs);                                 // V
   }
-  s += slot((size_t)std::max({t.ntile[mhd::kLAM], t.ntile[mhd::kXS], t.ntile[mhd::kYS]}) * 8);  // lam
+  s += slot(lam_slots(g, t) * 8);               // lam
   s += slot(4 * 8);                             // scal
   s += slot(3 * 8);                             // cnt
   return s;
@@ -458,13 +469,16 @@ void set_persistent(mhd_ctx* c, int on) {
 // re-tile the y/z marches with segment length seg (device tables updated
 // on the context stream)
 // segment lengths of the y and z marches
+// columns per y-march tile for the context's x variant
+int ycols_of(const mhd_ctx* c) { return c->var_x == 0 ? mhd::kYXW : kTPB; }
+
 int apply_tiling(mhd_ctx* c, int segy, int segz) {
   const int nb = (int)c->boxes.size();
   c->var_seg = segy;
   c->var_segz = segz;
   for (int k = 0; k < 6; k++) c->total[k] = 0;
   for (int bi = 0; bi < nb; bi++) {
-    Tiling t = tiling_of(c->geom[bi], segy, segz, c->precision == MHD_FP64);
+    Tiling t = tiling_of(c->geom[bi], segy, segz, c->precision == MHD_FP64, ycols_of(c));
     Box& b = c->hbox[bi];
     b.ysl = t.ysl;
     b.yseg = t.yseg;
@@ -536,6 +550,9 @@ int trial(mhd_ctx* c, int steps, float* ms) {
   return backup_state(c, false);
 }
 
+// MHD_TUNE_LOG set: the autotuner prints each trial's time to stderr
+static bool tune_log() { return std::getenv("MHD_TUNE_LOG") != nullptr; }
+
 // Coordinate search over the launch variants on the context's own boxes and
 // state: register budget of the x sweep and of the marches, march segment
 // length, persistent grid.  The arithmetic of every variant is the same, so
@@ -557,6 +574,9 @@ int autotune(mhd_ctx* c) {
     float ms = 0.f;
     r = trial(c, steps, &ms);
     if (r) return r;
+    if (tune_log())
+      std::fprintf(stderr, "[mhd autotune] x %d m %d seg %d/%d pers %d: %.3f ms (best %.3f)\n",
+                   c->var_x, c->var_m, c->var_seg, c->var_segz, c->var_pers, ms, best);
     if (ms < 0.99f * best) {
       best = ms;
     } else {
@@ -565,7 +585,12 @@ int autotune(mhd_ctx* c) {
     }
     return MHD_OK;
   };
-  auto set_x = [&](int v) { c->var_x = v; return MHD_OK; };
+  auto set_x = [&](int v) {
+    // the y march's tiles are wider with the x faces in registers
+    const bool retile = (v == 0) != (c->var_x == 0);
+    c->var_x = v;
+    return retile ? apply_tiling(c, c->var_seg, c->var_segz) : MHD_OK;
+  };
   auto set_m = [&](int v) { c->var_m = v; return MHD_OK; };
   auto set_seg = [&](int v) { return apply_tiling(c, v, c->var_segz); };
   auto set_segz = [&](int v) { return apply_tiling(c, c->var_seg, v); };
@@ -578,20 +603,10 @@ int autotune(mhd_ctx* c) {
     for (int v : {3, 4})
       if ((rc = try_var(&c->var_x, v, set_x))) return rc;
     if (c->fusable) {
-      // the x faces in the y march, with the window in registers and in LDS
-      const int mx = c->var_m, xx = c->var_x;
-      for (int v : {2, 6}) {
-        c->var_x = 0;
-        c->var_m = v;
-        float ms = 0.f;
-        if ((rc = trial(c, steps, &ms))) return rc;
-        if (ms < 0.99f * best) {
-          best = ms;
-        } else {
-          c->var_x = xx;
-          c->var_m = mx;
-        }
-      }
+      // the x faces in the y march, its window in registers and (mixed
+      // path) in LDS; the z march keeps the variant chosen above
+      for (int v : {0, 2})
+        if ((v == 0 || c->precision != MHD_FP64) && (rc = try_var(&c->var_x, v, set_x))) return rc;
     }
   }
   for (int v : {16, 32, 64, 128})
@@ -633,7 +648,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
   for (int bi = 0; bi < nb; bi++) {
     const mhd_box& mb = cfg->boxes[bi];
     Geom g = geom_of(mb);
-    Tiling t = tiling_of(g, c->var_seg, c->var_segz, c->precision == MHD_FP64);
+    Tiling t = tiling_of(g, c->var_seg, c->var_segz, c->precision == MHD_FP64, ycols_of(c));
     c->geom[bi] = g;
     Box& b = c->hbox[bi];
     std::memset(&b, 0, sizeof(Box));
@@ -677,8 +692,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
         b.SP[d][1] = take(g.F[d] * rs);
         b.V[d] = take(g.N * rs);
       }
-    b.lam = reinterpret_cast<double*>(
-        take((size_t)std::max({t.ntile[mhd::kLAM], t.ntile[mhd::kXS], t.ntile[mhd::kYS]}) * 8));
+    b.lam = reinterpret_cast<double*>(take(lam_slots(g, t) * 8));
     b.scal = reinterpret_cast<double*>(take(4 * 8));
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xft = t.xft;
@@ -897,7 +911,8 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
     int x = 1, m = 1, sg = 32, pe = 0, sz = -1;
     const int got = std::sscanf(v, "%d,%d,%d,%d,%d", &x, &m, &sg, &pe, &sz);
     if (got == 4) sz = sg;
-    if ((got == 4 || got == 5) && (x == 1 || x == 3 || x == 4 || (x == 0 && c->fusable)) &&
+    const bool fx = c->fusable && (x == 0 || (x == 2 && cfg->precision != MHD_FP64));
+    if ((got == 4 || got == 5) && (x == 1 || x == 3 || x == 4 || fx) &&
         (m >= 1 && m <= 10) &&
         sg >= 1 && sg <= 4096 && sz >= 1 && sz <= 4096 && (pe == 0 || pe == 1)) {
       c->var_x = x;

@@ -24,8 +24,9 @@ struct StepCtx {
   const int* total;    // tiles per kernel kind over all boxes
   const int* grid;     // persistent grid size per kind (0: one group per tile)
   int var_x, var_m;    // launch variants of the x sweep and the marches; var_x
-                       // = 0: the x faces are computed by the y march
-                       // (k_sweep_march_xy) and no x sweep runs
+                       // = 0 or 2: the x faces are computed by the y march
+                       // (k_sweep_march_xy), no x sweep runs and var_m
+                       // chooses the z march's variant only
   int rk;              // Runge-Kutta stages: 2 or 3
   int rs;              // Riemann solver: 0 HLLD (HLL fallback), 1 HLL
   int sl;              // slope kind: reconstruction (0 primitive, 1
@@ -93,17 +94,20 @@ inline void launch_march(int var, dim3 g, hipStream_t st, const Launch& L) {
   }
 }
 
-// the y march with the x faces (x variant 0): the window in registers, or
-// in LDS for march variants 5, 6, 7, 9, 10 in the mixed path (the FP64 ring
-// leaves no LDS for the window)
+// the y march with the x faces: x variant 0 keeps its window in registers
+// and runs workgroups of 2 * kTPB lanes (kYXW columns per tile); x variant 2
+// (mixed path only: the FP64 kernel's three-row ring leaves no LDS for it)
+// keeps it in LDS with kTPB lanes.  The march variant then applies to the z
+// march alone.
 template <typename real, int RS>
-inline void launch_march_xy(int var, dim3 g, hipStream_t st, const Launch& L) {
-  const bool lw = sizeof(real) == 4 && (var == 5 || var == 6 || var == 7 || var == 9 || var == 10);
-  if (lw)
-    hipLaunchKernelGGL((k_sweep_march_xy<real, sizeof(real) == 4 ? 1 : 0, RS>), g, dim3(kTPB), 0,
-                       st, L);
-  else
-    hipLaunchKernelGGL((k_sweep_march_xy<real, 0, RS>), g, dim3(kTPB), 0, st, L);
+inline void launch_march_xy(int var_x, dim3 g, hipStream_t st, const Launch& L) {
+  if constexpr (sizeof(real) == 4) {
+    if (var_x == 2) {
+      hipLaunchKernelGGL((k_sweep_march_xy<real, 1, RS, kTPB>), g, dim3(kTPB), 0, st, L);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_sweep_march_xy<real, 0, RS, kYXW>), g, dim3(kYXW), 0, st, L);
 }
 
 // Enqueues one step on sc.stream with slope kind SL (reconstruction
@@ -139,7 +143,7 @@ inline int enqueue_step_sl(const StepCtx& sc) {
     L.stage = kSrc[r][s];
     L.dst = kDst[r][s];
     L.comb = kComb[r][s];
-    const bool fused = SL == 0 && sc.var_x == 0;
+    const bool fused = SL == 0 && (sc.var_x == 0 || sc.var_x == 2);
     if (fused) {
       // the y march computes the x faces and, in the first stage, the CFL
       // rate of its cells; the time step follows it
@@ -148,9 +152,9 @@ inline int enqueue_step_sl(const StepCtx& sc) {
       L.xcd = (sc.xcd >> kYS) & 1;
       mark(MHD_K_SWEEP_Y, true);
       if (sc.rs)
-        launch_march_xy<real, 1>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march_xy<real, 1>(sc.var_x, dim3(grid(kYS)), sc.stream, L);
       else
-        launch_march_xy<real, 0>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_march_xy<real, 0>(sc.var_x, dim3(grid(kYS)), sc.stream, L);
       mark(MHD_K_SWEEP_Y, false);
       L.lam = 0;
       if (s == 0) {
@@ -159,36 +163,36 @@ inline int enqueue_step_sl(const StepCtx& sc) {
         mark(MHD_K_DT, false);
       }
     } else {
-    L.lam = s == 0;
-    L.ntiles = sc.total[kXS];
-    L.xcd = (sc.xcd >> kXS) & 1;
-    mark(MHD_K_SWEEP_X, true);
-    if (sc.rs)
-      launch_x<real, 1, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
-    else
-      launch_x<real, 0, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
-    mark(MHD_K_SWEEP_X, false);
-    L.lam = 0;
-    if (s == 0) {
-      mark(MHD_K_DT, true);
-      hipLaunchKernelGGL(k_dt, dim3(L.nboxes), dim3(kTPB), 0, sc.stream, L.boxes, 0, (int)kXS);
-      mark(MHD_K_DT, false);
-    }
-    L.ntiles = sc.total[kYS];
-    L.xcd = (sc.xcd >> kYS) & 1;
-    mark(MHD_K_SWEEP_Y, true);
-    if (sc.fz) {
+      L.lam = s == 0;
+      L.ntiles = sc.total[kXS];
+      L.xcd = (sc.xcd >> kXS) & 1;
+      mark(MHD_K_SWEEP_X, true);
       if (sc.rs)
-        launch_march<real, 1, 1, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        launch_x<real, 1, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
       else
-        launch_march<real, 1, 0, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
-    } else {
-      if (sc.rs)
-        launch_march<real, 1, 1, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
-      else
-        launch_march<real, 1, 0, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
-    }
-    mark(MHD_K_SWEEP_Y, false);
+        launch_x<real, 0, SL>(sc.var_x, dim3(grid(kXS)), sc.stream, L);
+      mark(MHD_K_SWEEP_X, false);
+      L.lam = 0;
+      if (s == 0) {
+        mark(MHD_K_DT, true);
+        hipLaunchKernelGGL(k_dt, dim3(L.nboxes), dim3(kTPB), 0, sc.stream, L.boxes, 0, (int)kXS);
+        mark(MHD_K_DT, false);
+      }
+      L.ntiles = sc.total[kYS];
+      L.xcd = (sc.xcd >> kYS) & 1;
+      mark(MHD_K_SWEEP_Y, true);
+      if (sc.fz) {
+        if (sc.rs)
+          launch_march<real, 1, 1, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        else
+          launch_march<real, 1, 0, 1, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+      } else {
+        if (sc.rs)
+          launch_march<real, 1, 1, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+        else
+          launch_march<real, 1, 0, 0, SL>(sc.var_m, dim3(grid(kYS)), sc.stream, L);
+      }
+      mark(MHD_K_SWEEP_Y, false);
     }
     if (!sc.fz) {
       L.ntiles = sc.total[kZS];

@@ -40,6 +40,22 @@ def test_kernel_names_and_launch_keys():
         assert bench.kind_of(name) == want
 
 
+def test_fused_variants_name_the_xy_march_and_drop_the_x_sweep():
+    # x variant 0: window in registers; 2 (mixed path): window in LDS; the
+    # march variant then names the z march alone
+    for x, real, tail in ((0, "double", "0, 0, 512"), (0, "float", "0, 0, 512"),
+                          (2, "float", "1, 0, 256")):
+        v = [x, 9, 64, 0, 128]
+        name = bench.kernel_name("sweep_y", real, v)
+        assert name == f"mhd::k_sweep_march_xy<{real}, {tail}>"
+        assert bench.kind_of(f"void {name}(mhd::Launch)")[1] == "sweep_y"
+        assert bench.kernel_name("sweep_z", real, v) == \
+            f"mhd::k_sweep_march<{real}, 2, 1, 0, 1, 1, 0, 0, 0>"
+        prec = 0 if real == "double" else 1
+        t = bench.bytes_table(prec, v)
+        assert "sweep_x" not in t and t["sweep_y"][0] > bench.bytes_table(prec, [1] + v[1:])["sweep_y"][0]
+
+
 def test_fractions_arithmetic():
     cells = 1000
     table = {"a": (100, 100), "b": (50, 70)}

@@ -972,6 +972,74 @@ def test_kelvin_helmholtz_full_size_sampled():
     _check_sampled(spec, st, cons, bface, dt_gpu, centres, label="KH 768x384x384")
 
 
+@pytest.fixture(scope="module")
+def ensemble_oracle_100():
+    """The 96-box ensemble's smallest, median and largest box and box 1,
+    each advanced by the threaded oracle over the ensemble's fixed step
+    count (100 steps, every box with its own CFL time step)."""
+    wl = W.ensemble()
+    sizes = [s.n[0] * s.n[1] * s.n[2] for s in wl.boxes]
+    order = np.argsort(sizes, kind="stable")
+    picks = sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1]), 1})
+    _host_threads()
+    return wl, picks, {b: oracle_run(wl.boxes[b], wl.states[b], 100) for b in picks}
+
+
+def _ensemble_run(wl, nsteps, precision, picks):
+    """All boxes in one context in the benchmark's launch configuration
+    (graph replay, persistent tiles, autotuned); the states of `picks`."""
+    flags = mhd.MHD_F_GRAPH | mhd.MHD_F_PERSISTENT | mhd.MHD_F_AUTOTUNE
+    with mhd.Sim(wl.boxes, precision=precision, flags=flags) as sim:
+        for b, st in enumerate(wl.states):
+            sim.set_state(b, st.cons, st.bface, 0.0)
+        sim.step(nsteps)
+        return {b: sim.get_state(b) + (sim.counters(b),) for b in picks}
+
+
+def test_ensemble_96_boxes_fixed_steps_fp64(ensemble_oracle_100):
+    """The 96-box ensemble over its fixed step count (100): the full state,
+    time and event counters of four boxes (smallest, median, largest and
+    box 1) within the FP64 bar of the oracle."""
+    wl, picks, o = ensemble_oracle_100
+    g = _ensemble_run(wl, 100, mhd.MHD_FP64, picks)
+    for b in picks:
+        assert_fp64_parity(g[b], o[b], f"ensemble box {b} {wl.boxes[b].n} x 100")
+
+
+def test_ensemble_96_boxes_fixed_steps_mixed(ensemble_oracle_100):
+    """The mixed path on the 96-box ensemble over its 100 fixed steps: the
+    same four boxes within the mixed bar of the oracle."""
+    wl, picks, o = ensemble_oracle_100
+    m = _ensemble_run(wl, 100, mhd.MHD_MIXED, picks)
+    for b in picks:
+        assert_mixed_bar(wl.boxes[b], m[b], o[b], f"ensemble box {b} {wl.boxes[b].n} x 100")
+
+
+def test_kelvin_helmholtz_10_steps_sampled():
+    """768 x 384 x 384 with outflow walls in y, in the benchmark's launch
+    configuration (graph replay, autotuned): ten FP64 steps at full size,
+    then the oracle advances neighbourhoods of radius 72 of sampled cells
+    (at both outflow walls, on the shear layers and inside) with the GPU's
+    ten time steps; cells within 12 of each centre, and every cell next to
+    a real wall, are compared."""
+    wl = W.kelvin_helmholtz()
+    spec, st = wl.boxes[0], wl.states[0]
+    dts = []
+    with mhd.Sim([spec], flags=mhd.MHD_F_GRAPH | mhd.MHD_F_AUTOTUNE) as sim:
+        sim.set_state(0, st.cons, st.bface, 0.0)
+        for _ in range(10):
+            dts.append(sim.dt(0)[0])
+            sim.step(1)
+        cons, bface, t = sim.get_state(0)
+    tsum = 0.0
+    for dt in dts:
+        tsum += dt
+    assert t == tsum
+    _host_threads()
+    centres = [(0, 0, 0), (767, 383, 383), (400, 96, 200), (123, 287, 301), (384, 192, 192)]
+    _check_sampled(spec, st, cons, bface, dts, centres, r=72, label="KH 768x384x384 x 10")
+
+
 def test_ensemble_96_boxes_full_size():
     """The 96-box ensemble (sizes 32^3..128^3) in one context with graph
     replay and persistent tiles: per-box dt equals the oracle's; sampled
@@ -1039,7 +1107,8 @@ def test_corner_tile_order_bitwise(n, bc, order, emf, monkeypatch):
 
 
 FUSED_CASES = [((40, 33, 29), (0, 1, 0)), ((300, 7, 6), (1, 0, 0)), ((17, 9, 23), (1, 1, 1)),
-               ((2, 3, 5), (0, 0, 0)), ((260, 5, 4), (0, 0, 1))]
+               ((2, 3, 5), (0, 0, 0)), ((260, 5, 4), (0, 0, 1)), ((600, 5, 3), (0, 0, 0)),
+               ((530, 4, 3), (1, 0, 0))]
 
 
 @pytest.mark.parametrize("n,bc", FUSED_CASES)
@@ -1050,7 +1119,8 @@ def test_fused_xy_march_bitwise_fp64(n, bc, variant, monkeypatch):
     FP64 results, time and event counters equal the x sweep's bit for bit:
     rows shorter and longer than a workgroup, rows split across workgroups,
     outflow walls on each axis (the last lane of an outflow row computes the
-    boundary face), two-cell rows that wrap onto themselves."""
+    boundary face), two-cell rows that wrap onto themselves, rows longer
+    than the fused march's 512-lane workgroup."""
     wl = W.random_smooth(n=n, seed=sum(n) + 5, bc=bc)
     monkeypatch.delenv("MHD_VARIANT", raising=False)
     ref = gpu_run(wl, 3)[0]
@@ -1061,6 +1131,25 @@ def test_fused_xy_march_bitwise_fp64(n, bc, variant, monkeypatch):
     assert g[2] == ref[2] and g[3] == ref[3]
     for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
         assert np.array_equal(a, b), (n, bc, variant)
+
+
+@pytest.mark.parametrize("n,variant", [((3, 40, 2), "0,1,1,0"), ((5, 33, 3), "0,2,3,1"),
+                                       ((3, 40, 2), "1,1,1,0")])
+def test_short_y_segments_keep_cfl_partials_in_bounds(n, variant, monkeypatch):
+    """Thin boxes with y-march segments of one and three cells: the fused
+    march writes one CFL partial per y tile, more than the box's x-sweep and
+    cell tiles, and the partials buffer is sized for the shortest segment.
+    Results, time and counters equal the default variant's bit for bit."""
+    wl = W.random_smooth(n=n, seed=sum(n) + 9)
+    monkeypatch.delenv("MHD_VARIANT", raising=False)
+    ref = gpu_run(wl, 3)[0]
+    monkeypatch.setenv("MHD_VARIANT", variant)
+    with mhd.Sim(wl.boxes) as sim:
+        assert list(sim.tuning()[:3]) == [int(x) for x in variant.split(",")[:3]]
+    g = gpu_run(wl, 3)[0]
+    assert g[2] == ref[2] and g[3] == ref[3]
+    for a, b in zip(g[0] + g[1], ref[0] + ref[1]):
+        assert np.array_equal(a, b), (n, variant)
 
 
 @pytest.mark.parametrize("kw", [dict(rk=3), dict(solver="hll"), dict(limiter="mc")])
@@ -1090,7 +1179,21 @@ def test_fused_xy_march_options_and_ensemble(kw, monkeypatch):
             assert np.array_equal(a, b), kw
 
 
-def test_fused_xy_march_mixed_blast(monkeypatch):
+@pytest.mark.parametrize("x", [2, 5])
+def test_fused_xy_march_lds_window_mixed_only(x, monkeypatch):
+    """x variant 2 (the fused y march with its window in LDS) exists in the
+    mixed path only: a FP64 context ignores it and keeps the default, a
+    mixed one takes it; x variant 5 exists in neither."""
+    wl = W.random_smooth(n=(24, 20, 16), seed=7)
+    monkeypatch.setenv("MHD_VARIANT", f"{x},9,32,0,64")
+    with mhd.Sim(wl.boxes) as sim:
+        assert list(sim.tuning()[:2]) == [1, 1]
+    with mhd.Sim(wl.boxes, precision=mhd.MHD_MIXED) as sim:
+        assert list(sim.tuning()[:2]) == ([x, 9] if x == 2 else [1, 1])
+
+
+@pytest.mark.parametrize("variant", ["0,9,64,0,128", "2,9,64,0,128"])
+def test_fused_xy_march_mixed_blast(variant, monkeypatch):
     """The mixed path with the fused y march on the blast (low beta, floor
     hits, HLL fallbacks) within the mixed bar of the oracle.  It differs from
     the mixed path with the x sweep only in where the FP32 residual is
@@ -1100,9 +1203,9 @@ def test_fused_xy_march_mixed_blast(monkeypatch):
     wl = W.blast_3d(n=48)
     spec, st = wl.boxes[0], wl.states[0]
     o = oracle_run(spec, st, 20)
-    monkeypatch.setenv("MHD_VARIANT", "0,6,64,0,128")
+    monkeypatch.setenv("MHD_VARIANT", variant)
     m = gpu_run(wl, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH)[0]
-    assert_mixed_bar(spec, m, o, "blast 48 x 20, fused x+y march")
+    assert_mixed_bar(spec, m, o, f"blast 48 x 20, fused x+y march {variant}")
     monkeypatch.delenv("MHD_VARIANT")
     u = gpu_run(wl, 20, precision=mhd.MHD_MIXED, flags=mhd.MHD_F_GRAPH)[0]
     assert_mixed_bar(spec, u, o, "blast 48 x 20, x sweep")
