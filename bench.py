@@ -1149,13 +1149,18 @@ def fixed_run(wl, precision, steps, variant):
 
 def drift(cons0, cons1):
     """|sum q(t) - sum q(0)| / sum |q(0)| of the mass, momentum and energy
-    totals (exact sums): conservation of a periodic box."""
+    totals (exact sums): conservation of a periodic box.  A momentum
+    component is measured against the L1 norm of the momentum vector (the
+    sum over its three components), so that a component whose total starts
+    at or near zero is not divided by its own small norm."""
     import math
     import numpy as np
+    norms = [float(np.sum(np.abs(a))) for a in cons0]
+    msum = norms[1] + norms[2] + norms[3]
+    dens = [norms[0], msum, msum, msum, norms[4]]
     out = {}
-    for name, a, b in zip(("mass", "mx", "my", "mz", "energy"), cons0, cons1):
-        den = float(np.sum(np.abs(a))) or 1.0
-        out[name] = float(abs(math.fsum(b.ravel()) - math.fsum(a.ravel())) / den)
+    for name, a, b, den in zip(("mass", "mx", "my", "mz", "energy"), cons0, cons1, dens):
+        out[name] = float(abs(math.fsum(b.ravel()) - math.fsum(a.ravel())) / (den or 1.0))
     return out
 
 

@@ -150,3 +150,9 @@ def test_drift_of_totals():
     d = bench.drift(a, b)
     assert set(d) == {"mass", "mx", "my", "mz", "energy"}
     assert abs(d["mass"] - 1e-12) < 1e-15
+    # momentum components against the momentum vector's L1 norm (18 here)
+    assert abs(d["mz"] - 6e-12 / 18.0) < 1e-15
+    # a component that starts at zero is not divided by its own zero norm
+    z = [a[0], a[1], a[2], np.zeros(3), a[4]]
+    d = bench.drift(z, [a[0], a[1], a[2], np.array([0.0, 0.0, 1.2e-11]), a[4]])
+    assert abs(d["mz"] - 1.2e-11 / 12.0) < 1e-15
