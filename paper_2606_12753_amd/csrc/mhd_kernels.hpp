@@ -1441,8 +1441,9 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
 // Used for boxes whose three axes are active, with primitive slopes.
 template <typename real, int TPB>
 struct XRing {
-  real q[3][7][TPB];  // x-frame primitives of three rows, per lane
-  real f[kNQ][TPB];   // x-face hydro fluxes of the row being completed
+  real q[3][7][TPB];     // x-frame primitives of three rows, per lane
+  real f[2][kNQ][TPB];   // x-face hydro fluxes of the row being completed,
+                         // alternating between two buffers row by row
 };
 
 // x-frame primitives of cell (i, j, k) of state s
@@ -1558,8 +1559,11 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
     PrimD w;
     const int fl = raw_to_prim(b, next, w);
     const St7<real> q3 = rotate<real>(w, 1);
-    // every lane has read the ring rows of the previous step
-    __syncthreads();
+    // Ring slot (f + 1) % 3 was last read by the x faces of row f - 2 in
+    // the previous step, before that step's flux-exchange barrier, which
+    // also made the rows written since visible; the first two steps, with
+    // no exchange behind them, wait here instead.
+    if (f <= j0 + 1) __syncthreads();
     if (f + 1 < j1) own_cell(f + 1, w, fl);
     if (f < j1) next = load_raw(b, s, addr_at(f + 2));
     St7<real> wl, wr;
@@ -1602,12 +1606,15 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
         }
         if (d == 0) ux = u; else uu = u;
       }
+      // flux exchange: a buffer is written again two rows later, after
+      // the next row's barrier, which every reader of this row has passed
+      const int fb = c & 1;
 #pragma unroll
-      for (int q = 0; q < kNQ; q++) xr.f[q][t] = flo[q];
+      for (int q = 0; q < kNQ; q++) xr.f[fb][q][t] = flo[q];
       __syncthreads();
       if (up_in_ring) {
 #pragma unroll
-        for (int q = 0; q < kNQ; q++) fup[q] = xr.f[q][t + (iu - i)];
+        for (int q = 0; q < kNQ; q++) fup[q] = xr.f[fb][q][t + (iu - i)];
       }
       if (live) {
         if (ux) atomicAdd(&b.cnt[1], 1ull);
