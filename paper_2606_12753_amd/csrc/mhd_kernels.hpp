@@ -83,9 +83,8 @@ struct Box {
   int xft;            // x sweep: faces per tile
   int ctx;            // corner-EMF kernel: tile width along x (kTPB / ctx
                       // rows), 0 for flat order
-  int ckz;            // corner-EMF kernel: planes per block of the
-                      // column-major tile order, 0 for plane-major order
-  int cfo;            // face update in the corner-EMF kernel's tile order
+  int czk;            // corner-EMF kernel: planes per lane (each lane walks
+                      // czk consecutive planes of its column; 1 with ctx = 0)
   int emf;            // corner EMF: 0 contact-upwinded, 1 E0 (derivatives
                       // averaged), 2 mean of the four face EMFs, 3 upwind CT
   int lim;            // slope limiter (0 minmod, 1 MC, 2 van Leer), for the
@@ -1771,16 +1770,12 @@ __device__ __forceinline__ void unflatten(int p, int e0, int e1, int pos[3]) {
 }
 
 // Position of a lane in the corner-EMF kernel: tiles of ctx x (kTPB / ctx)
-// positions in one xy plane, so that the row below a lane's row, whose face
-// values and cell EMFs the lane reads, is mostly fetched by the same
-// workgroup.  Tile order: with ckz = 0 plane by plane (x tiles fastest, then
-// y).  With ckz > 0 in blocks of ckz planes; within a block, groups of eight
-// neighbouring patches, each group plane by plane.  The hardware deals
-// workgroups to the eight XCDs in turn, so tile t + 8 (the same patch one
-// plane up) runs on the XCD that ran tile t and finds the plane below, the
-// other half of its stencil, in that XCD's L2, while the eight XCDs work on
-// neighbouring patches of one plane at a time.  ctx = 0: flat order over all
-// positions.  Returns false for lanes past the edge.
+// positions of a patch of the xy plane, so that the row below a lane's row,
+// whose face values and cell EMFs the lane reads, is mostly fetched by the
+// same workgroup; each lane then walks czk planes of its column from plane
+// pos[2] (tiles: patches fastest, then blocks of czk planes).  ctx = 0:
+// flat order over all positions, one plane per lane.  Returns false for
+// lanes past the edge.
 __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int cx = b.ctx;
   if (cx == 0) {
@@ -1793,29 +1788,19 @@ __device__ __forceinline__ bool ct_pos(CBox& b, int lt, int pos[3]) {
   const int nbx = (b.nf[0] + cx - 1) / cx;
   const int nby = (b.nf[1] + cy - 1) / cy;
   const int np = nbx * nby;
-  int patch, k;
-  if (b.ckz == 0) {
-    k = lt / np;
-    patch = lt - k * np;
-  } else {
-    const int blk = np * b.ckz;
-    const int kb = lt / blk;
-    const int k0 = kb * b.ckz;
-    const int keff = min(b.ckz, b.nf[2] - k0);
-    const int r = lt - kb * blk;
-    const int g = r / (8 * keff);            // group of eight patches
-    const int ng = min(8, np - 8 * g);       // patches in this group
-    const int rr = r - g * 8 * keff;
-    const int kk = rr / ng;
-    k = k0 + kk;
-    patch = 8 * g + (rr - kk * ng);
-  }
+  const int kb = lt / np;
+  const int patch = lt - kb * np;
   const int by = patch / nbx;
   const int bx = patch - by * nbx;
   pos[0] = bx * cx + (int)threadIdx.x % cx;
   pos[1] = by * cy + (int)threadIdx.x / cx;
-  pos[2] = k;
+  pos[2] = kb * b.czk;
   return pos[0] < b.nf[0] && pos[1] < b.nf[1];
+}
+
+// planes a lane of the corner-EMF kernel walks from its first plane k0
+__device__ __forceinline__ int ct_planes(CBox& b, int k0) {
+  return b.ctx == 0 ? 1 : min(b.czk, b.nf[2] - k0);
 }
 
 // Slope limiter chosen at run time (the upwind-CT corner states).
@@ -1967,12 +1952,33 @@ __global__ __launch_bounds__(kTPB) void k_ct_uct(Launch L) {
     const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
     int pos[3];
     if (!ct_pos(b, lt, pos)) continue;
+    const int nk = ct_planes(b, pos[2]);
+    for (int kk = 0; kk < nk; ++kk, ++pos[2]) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      if (pos[c] >= b.n[c]) continue;
-      st<real>(b.ED[c], eidx(b, c, pos[0], pos[1], pos[2]), uct_corner<real>(b, L.stage, c, pos));
+      for (int c = 0; c < 3; c++) {
+        if (pos[c] >= b.n[c]) continue;
+        st<real>(b.ED[c], eidx(b, c, pos[0], pos[1], pos[2]), uct_corner<real>(b, L.stage, c, pos));
+      }
     }
   }
+}
+
+// The corner EMF from its four face EMFs (fa1, fa0 on the a-faces at b-cell
+// index ib and ib - 1, fb1, fb0 on the b-faces at a-cell index ia and
+// ia - 1), the cell EMFs of the four cells around the edge ((ia-1, ib-1),
+// (ia, ib-1), (ia-1, ib), (ia, ib)) and the mass fluxes of the four faces,
+// for the averages of k_ct_edge.
+template <typename real>
+__device__ __forceinline__ real corner_avg(int emf, real fa1, real fa0, real fb1, real fb0,
+                                           const real ec[4], real m_a1, real m_a0, real m_b1,
+                                           real m_b0) {
+  if (emf == 2) return (real)0.25 * (fa1 + fa0 + fb1 + fb0);
+  const real dbp = upwind(m_a1, ec[2] - fb0, ec[3] - fb1);
+  const real dbm = upwind(m_a0, fb0 - ec[0], fb1 - ec[1]);
+  const real dap = upwind(m_b1, ec[1] - fa0, ec[3] - fa1);
+  const real dam = upwind(m_b0, fa0 - ec[0], fa1 - ec[2]);
+  return (real)0.25 * (fa1 + fa0 + fb1 + fb0) + (real)0.25 * (dbm - dbp) +
+         (real)0.25 * (dam - dap);
 }
 
 // Corner EMFs: for every corner position one lane computes the EMF along
@@ -1980,7 +1986,11 @@ __global__ __launch_bounds__(kTPB) void k_ct_uct(Launch L) {
 // Gardiner & Stone (2005) (b.emf = 0), their E0 average with every
 // face-to-corner derivative taken as the mean of its two sides (1), or the
 // mean of the four face EMFs (2, Balsara & Spicer 1999; no cell EMF or mass
-// flux is read).
+// flux is read).  A lane walks ct_planes planes of its column: the EMFs
+// along x and y at plane k read the plane below (z-cell k - 1) for the
+// y-face and x-face EMFs, mass fluxes and cell EMFs that the lane loaded
+// itself at plane k - 1, so from the second plane on those come from
+// registers (the same values, so the same results).
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -1991,69 +2001,105 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
     const int lt = tile - table(L.base)[kCTE * (L.nboxes + 1) + bi];
     int pos[3];
     if (!ct_pos(b, lt, pos)) continue;
-    // mapped cell indices of the positions and of the positions - 1
-    int m1[3], m0[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      m1[d] = map_cell(pos[d], b.n[d], b.per[d]);
-      m0[d] = map_cell(pos[d] - 1, b.n[d], b.per[d]);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const int a = (c + 1) % 3, bb = (c + 2) % 3;
-      if (pos[c] >= b.n[c]) continue;
-      int q[3];
-      // a-faces (ia; ib) and (ia; ib-1)
-      q[c] = pos[c];
-      q[a] = pos[a];
-      q[bb] = m1[bb];
-      const int fa1i = fidx(b, a, q[0], q[1], q[2]);
-      q[bb] = m0[bb];
-      const int fa0i = fidx(b, a, q[0], q[1], q[2]);
-      // b-faces (ib; ia) and (ib; ia-1)
-      q[bb] = pos[bb];
-      q[a] = m1[a];
-      const int fb1i = fidx(b, bb, q[0], q[1], q[2]);
-      q[a] = m0[a];
-      const int fb0i = fidx(b, bb, q[0], q[1], q[2]);
-      const real fa1 = ld<real>(b.EF[a][1], fa1i);
-      const real fa0 = ld<real>(b.EF[a][1], fa0i);
-      const real fb1 = ld<real>(b.EF[bb][0], fb1i);
-      const real fb0 = ld<real>(b.EF[bb][0], fb0i);
-      real e;
-      if (b.emf == 2) {
-        e = (real)0.25 * (fa1 + fa0 + fb1 + fb0);
-      } else {
-        // cells (ia-1, ib-1), (ia, ib-1), (ia-1, ib), (ia, ib)
-        real ec[4];
-        q[a] = m0[a]; q[bb] = m0[bb]; ec[0] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-        q[a] = m1[a]; q[bb] = m0[bb]; ec[1] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-        q[a] = m0[a]; q[bb] = m1[bb]; ec[2] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-        q[a] = m1[a]; q[bb] = m1[bb]; ec[3] = ld<real>(b.Ec[c], cidx(b, q[0], q[1], q[2]));
-        real m_a1 = (real)0, m_a0 = (real)0, m_b1 = (real)0, m_b0 = (real)0;
-        if (b.emf == 0) {
-          m_a1 = ld<real>(b.MF[a], fa1i);
-          m_a0 = ld<real>(b.MF[a], fa0i);
-          m_b1 = ld<real>(b.MF[bb], fb1i);
-          m_b0 = ld<real>(b.MF[bb], fb0i);
+    const int nk = ct_planes(b, pos[2]);
+    const int i = pos[0], j = pos[1];
+    // mapped cell indices of the positions and of the positions - 1 in x, y
+    const int m1x = map_cell(i, b.n[0], b.per[0]), m0x = map_cell(i - 1, b.n[0], b.per[0]);
+    const int m1y = map_cell(j, b.n[1], b.per[1]), m0y = map_cell(j - 1, b.n[1], b.per[1]);
+    const bool cm = b.emf != 2;   // cell EMFs read
+    const bool mf = b.emf == 0;   // mass fluxes read
+    // plane-k values of the EMFs along x (y-face EMF and mass flux, cell
+    // EMFs (i, m0y) and (i, m1y)) and along y (x-face EMF and mass flux, cell
+    // EMFs (m0x, j) and (m1x, j)), which are the next plane's plane-below
+    real xa = 0, xma = 0, xe0 = 0, xe1 = 0, ya = 0, yma = 0, ye0 = 0, ye1 = 0;
+    for (int kk = 0; kk < nk; ++kk) {
+      const int k = pos[2] + kk;
+      const int m1z = map_cell(k, b.n[2], b.per[2]), m0z = map_cell(k - 1, b.n[2], b.per[2]);
+      const bool carry = kk > 0;
+      if (k < b.n[2]) {
+        // along z: a = x-faces (i; m1y), (i; m0y), b = y-faces (j; m1x), (j; m0x)
+        const int fa1i = fidx(b, 0, i, m1y, k), fa0i = fidx(b, 0, i, m0y, k);
+        const int fb1i = fidx(b, 1, m1x, j, k), fb0i = fidx(b, 1, m0x, j, k);
+        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
+        if (cm) {
+          ec[0] = ld<real>(b.Ec[2], cidx(b, m0x, m0y, k));
+          ec[1] = ld<real>(b.Ec[2], cidx(b, m1x, m0y, k));
+          ec[2] = ld<real>(b.Ec[2], cidx(b, m0x, m1y, k));
+          ec[3] = ld<real>(b.Ec[2], cidx(b, m1x, m1y, k));
         }
-        const real dbp = upwind(m_a1, ec[2] - fb0, ec[3] - fb1);
-        const real dbm = upwind(m_a0, fb0 - ec[0], fb1 - ec[1]);
-        const real dap = upwind(m_b1, ec[1] - fa0, ec[3] - fa1);
-        const real dam = upwind(m_b0, fa0 - ec[0], fa1 - ec[2]);
-        e = (real)0.25 * (fa1 + fa0 + fb1 + fb0) + (real)0.25 * (dbm - dbp) +
-            (real)0.25 * (dam - dap);
+        if (mf) {
+          ma1 = ld<real>(b.MF[0], fa1i);
+          ma0 = ld<real>(b.MF[0], fa0i);
+          mb1 = ld<real>(b.MF[1], fb1i);
+          mb0 = ld<real>(b.MF[1], fb0i);
+        }
+        const real e = corner_avg<real>(b.emf, ld<real>(b.EF[0][1], fa1i), ld<real>(b.EF[0][1], fa0i),
+                                        ld<real>(b.EF[1][0], fb1i), ld<real>(b.EF[1][0], fb0i), ec,
+                                        ma1, ma0, mb1, mb0);
+        st<real>(b.ED[2], eidx(b, 2, i, j, k), e);
       }
-      st<real>(b.ED[c], eidx(b, c, pos[0], pos[1], pos[2]), e);
+      if (i < b.n[0]) {
+        // along x: a = y-faces (j; m1z), (j; m0z), b = z-faces (k; m1y), (k; m0y)
+        const int fa1i = fidx(b, 1, i, j, m1z);
+        const int fb1i = fidx(b, 2, i, m1y, k), fb0i = fidx(b, 2, i, m0y, k);
+        const real fa1 = ld<real>(b.EF[1][1], fa1i);
+        const real fa0 = carry ? xa : ld<real>(b.EF[1][1], fidx(b, 1, i, j, m0z));
+        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
+        if (cm) {
+          ec[0] = carry ? xe0 : ld<real>(b.Ec[0], cidx(b, i, m0y, m0z));
+          ec[1] = carry ? xe1 : ld<real>(b.Ec[0], cidx(b, i, m1y, m0z));
+          ec[2] = ld<real>(b.Ec[0], cidx(b, i, m0y, m1z));
+          ec[3] = ld<real>(b.Ec[0], cidx(b, i, m1y, m1z));
+        }
+        if (mf) {
+          ma1 = ld<real>(b.MF[1], fa1i);
+          ma0 = carry ? xma : ld<real>(b.MF[1], fidx(b, 1, i, j, m0z));
+          mb1 = ld<real>(b.MF[2], fb1i);
+          mb0 = ld<real>(b.MF[2], fb0i);
+        }
+        const real e = corner_avg<real>(b.emf, fa1, fa0, ld<real>(b.EF[2][0], fb1i),
+                                        ld<real>(b.EF[2][0], fb0i), ec, ma1, ma0, mb1, mb0);
+        st<real>(b.ED[0], eidx(b, 0, i, j, k), e);
+        xa = fa1;
+        xma = ma1;
+        xe0 = ec[2];
+        xe1 = ec[3];
+      }
+      if (j < b.n[1]) {
+        // along y: a = z-faces (k; m1x), (k; m0x), b = x-faces (i; m1z), (i; m0z)
+        const int fa1i = fidx(b, 2, m1x, j, k), fa0i = fidx(b, 2, m0x, j, k);
+        const int fb1i = fidx(b, 0, i, j, m1z);
+        const real fb1 = ld<real>(b.EF[0][0], fb1i);
+        const real fb0 = carry ? ya : ld<real>(b.EF[0][0], fidx(b, 0, i, j, m0z));
+        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
+        if (cm) {
+          ec[0] = carry ? ye0 : ld<real>(b.Ec[1], cidx(b, m0x, j, m0z));
+          ec[1] = ld<real>(b.Ec[1], cidx(b, m0x, j, m1z));
+          ec[2] = carry ? ye1 : ld<real>(b.Ec[1], cidx(b, m1x, j, m0z));
+          ec[3] = ld<real>(b.Ec[1], cidx(b, m1x, j, m1z));
+        }
+        if (mf) {
+          ma1 = ld<real>(b.MF[2], fa1i);
+          ma0 = ld<real>(b.MF[2], fa0i);
+          mb1 = ld<real>(b.MF[0], fb1i);
+          mb0 = carry ? yma : ld<real>(b.MF[0], fidx(b, 0, i, j, m0z));
+        }
+        const real e = corner_avg<real>(b.emf, ld<real>(b.EF[2][1], fa1i),
+                                        ld<real>(b.EF[2][1], fa0i), fb1, fb0, ec, ma1, ma0, mb1,
+                                        mb0);
+        st<real>(b.ED[1], eidx(b, 1, i, j, k), e);
+        ya = fb1;
+        yma = mb1;
+        ye0 = ec[1];
+        ye1 = ec[3];
+      }
     }
   }
 }
 
 // Face update: dB_d/dt = -[(E_f(e+1/2) - E_f(e-1/2))/dx_e
 //                          - (E_e(f+1/2) - E_e(f-1/2))/dx_f], (d, e, f)
-// cyclic, formed in FP64, then the Runge-Kutta stage combine.  Positions
-// in flat order, or with b.cfo in the corner-EMF kernel's tile order (the
-// plane above, whose edge EMFs a face reads, is then the next tile's).
+// cyclic, formed in FP64, then the Runge-Kutta stage combine.
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -2062,14 +2108,10 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
     const int bi = find_box(table(L.base) + kCTF * (L.nboxes + 1), L.nboxes, tile);
     CBox& b = box_at(L.boxes, bi);
     const int lt = tile - table(L.base)[kCTF * (L.nboxes + 1) + bi];
+    const int p = lt * kTPB + (int)threadIdx.x;
+    if (p >= b.nf[0] * b.nf[1] * b.nf[2]) continue;
     int pos[3];
-    if (b.cfo) {
-      if (!ct_pos(b, lt, pos)) continue;
-    } else {
-      const int p = lt * kTPB + (int)threadIdx.x;
-      if (p >= b.nf[0] * b.nf[1] * b.nf[2]) continue;
-      unflatten(p, b.nf[0], b.nf[1], pos);
-    }
+    unflatten(p, b.nf[0], b.nf[1], pos);
     const double dt = b.scal[0];
 #pragma unroll
     for (int d = 0; d < 3; d++) {

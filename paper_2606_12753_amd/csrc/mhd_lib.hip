@@ -186,9 +186,14 @@ int validate_config(const mhd_config* cfg, std::string& err) {
   return MHD_OK;
 }
 
+// planes per lane of the corner-EMF kernel (turbulence 512^3, per launch
+// FP64 / mixed: 1 plane 3.88 / 1.68 ms, 2 3.59 / 1.59, 4 3.48 / 1.61,
+// 8 3.56 / 1.60, 16 3.56 / 1.63)
+constexpr int kDefaultCzk = 4;
+
 // tiling of one box (the y/z march segment lengths are tunable)
 struct Tiling {
-  int xft, ctx, ckz, cfo, ysl, yseg, zsl, zseg;
+  int xft, ctx, czk, ysl, yseg, zsl, zseg;
   int ntile[6];
 };
 
@@ -239,22 +244,20 @@ Tiling tiling_of(const Geom& g, int ysl, int zsl, bool fp64, int ycols = kTPB) {
       if (w == 0 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256) t.ctx = w;
     }
   }
-  // column-major order of the corner tiles: blocks of ckz planes (see
-  // ct_pos); the face update in the same order (cfo) or flat.
-  t.ckz = 0;
-  t.cfo = 0;
-  if (const char* v = std::getenv("MHD_CKZ")) t.ckz = std::max(0, std::atoi(v));
-  if (const char* v = std::getenv("MHD_CFO")) t.cfo = std::atoi(v) ? 1 : 0;
-  if (t.ctx == 0) t.ckz = t.cfo = 0;
+  // planes each lane of the corner-EMF kernel walks (its plane-below values
+  // then come from registers; see k_ct_edge); one in flat order
+  t.czk = kDefaultCzk;
+  if (const char* v = std::getenv("MHD_CZK")) t.czk = std::max(1, std::atoi(v));
+  if (t.ctx == 0) t.czk = 1;
   const long long P = (long long)g.nf[0] * g.nf[1] * g.nf[2];
   if (t.ctx == 0) {
     t.ntile[mhd::kCTE] = (int)((P + kTPB - 1) / kTPB);
   } else {
     const long long cy = kTPB / t.ctx;
     const long long nbx = (g.nf[0] + t.ctx - 1) / t.ctx, nby = (g.nf[1] + cy - 1) / cy;
-    t.ntile[mhd::kCTE] = (int)(nbx * nby * g.nf[2]);
+    t.ntile[mhd::kCTE] = (int)(nbx * nby * ((g.nf[2] + t.czk - 1) / t.czk));
   }
-  t.ntile[mhd::kCTF] = t.cfo ? t.ntile[mhd::kCTE] : (int)((P + kTPB - 1) / kTPB);
+  t.ntile[mhd::kCTF] = (int)((P + kTPB - 1) / kTPB);
 
   t.ntile[mhd::kLAM] = (int)((g.N + kTPB - 1) / kTPB);
   return t;
@@ -607,6 +610,11 @@ int autotune(mhd_ctx* c) {
       // path) in LDS; the z march keeps the variant chosen above
       for (int v : {0, 2})
         if ((v == 0 || c->precision != MHD_FP64) && (rc = try_var(&c->var_x, v, set_x))) return rc;
+      // with the y march fused, the march variant chooses the z march alone:
+      // its choice above was made beside the unfused y march, so try again
+      if (c->var_x == 0 || c->var_x == 2)
+        for (int v : {1, 2, 3, 5, 6, 7, 8, 9, 10})
+          if (v != c->var_m && (rc = try_var(&c->var_m, v, set_m))) return rc;
     }
   }
   for (int v : {16, 32, 64, 128})
@@ -697,8 +705,7 @@ int build_ctx(mhd_ctx* c, const mhd_config* cfg) {
     b.cnt = reinterpret_cast<unsigned long long*>(take(3 * 8));
     b.xft = t.xft;
     b.ctx = t.ctx;
-    b.ckz = t.ckz;
-    b.cfo = t.cfo;
+    b.czk = t.czk;
     b.emf = cfg->ct_emf;
     b.lim = cfg->limiter;
     b.ysl = t.ysl;
