@@ -187,7 +187,8 @@ int mhd_set_state(mhd_ctx *ctx, int32_t box, const double *const cons[5],
 /* Enqueues nsteps full Runge-Kutta steps (rk_stages stages each) of every box
  * on the context stream.
  * Defines: the main cycle of the paper's section 2.2.3.  Each stage
- * reconstructs primitive (or characteristic) variables per direction,
+ * reconstructs, per direction, the primitive variables (or their
+ * characteristic fields, MHD_REC_CHAR) with limited linear slopes,
  * solves a Riemann problem at every interface (HLLD, or HLL for the
  * paper's 2D Riemann runs) and applies the flux-conservative update, then
  * constrained transport updates the face field; the Runge-Kutta stage
