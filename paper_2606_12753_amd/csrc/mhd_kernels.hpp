@@ -1017,6 +1017,16 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const XTile x = x_tile(b, lt);
     double lmax = 0.0;
     if (b.act[0]) {
+      // the normal field of the lane's face (a tile has at most one face
+      // per lane), loaded before the staging so that it has arrived when
+      // the face is solved
+      real bn_lane = (real)0;
+      if ((int)threadIdx.x < x.nF) {
+        int p, f, o, j, k;
+        x_face(x, threadIdx.x, p, f, o);
+        x_row(x, p, j, k);
+        bn_lane = (real)ld<double>(b.B[s][0], fidx(b, 0, f, j, k));
+      }
       const int npieces = 1 + (x.nF - x.W0 + x.nf - 1) / x.nf;
       const int ncell = x.nF + 3 * npieces;
       for (int sidx = threadIdx.x; sidx < ncell; sidx += kTPB) {
@@ -1094,7 +1104,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(WPE))) voi
           plm_face<LIM>(q[0], q[1], q[2], q[3], wl, wr);
         }
         const int fi = fidx(b, 0, f, j, k);
-        const real bn = (real)ld<double>(b.B[s][0], fi);
+        const real bn = t == (int)threadIdx.x ? bn_lane : (real)ld<double>(b.B[s][0], fi);
         real F[7], fm, sp[2];
         const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
         if (b.emf == 3) {
@@ -1317,6 +1327,8 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
   // face offsets along D: face f of this column
   const int fstride = D == 1 ? b.n[0] : b.n[0] * b.n[1];
   const int fbase = D == 1 ? (tr * b.nf[1]) * b.n[0] + i : tr * b.n[0] + i;
+  // face f along D is in [0, n]; periodic face n is face 0
+  auto face_at = [&](int f) { return fbase + ((per && f == n) ? 0 : f) * fstride; };
   const int cstride = fstride;
   const int cbase = D == 1 ? (tr * b.n[1]) * b.n[0] + i : tr * b.n[0] + i;
   constexpr bool kFin = D == 2 || FZ;  // this march applies the RK combine
@@ -1366,8 +1378,7 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     if (PF && f > j0) load_update_inputs();
     St7<real> wl, wr;
     win.face_and_slide(q3, bnorm(w), gam, wl, wr);
-    // face index f along D is in [0, n]; periodic face n is face 0
-    const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
+    const int fi = face_at(f);
     const real bn = (real)ld<double>(b.B[s][D], fi);
     real F[7], fm, sp[2];
     const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
@@ -1472,21 +1483,26 @@ __device__ __forceinline__ St7<real> xneighbour(CBox& b, int s, XRing<real, TPB>
   return q;
 }
 
+// x-face index of the lower face of cell (i + d) of row (j, k): face i + d
+// (face n of an outflow axis; periodic face n is face 0)
+__device__ __forceinline__ int xface_idx(CBox& b, int i, int j, int k, int d) {
+  const int f = i + d;
+  return fidx(b, 0, (b.per[0] && f == b.n[0]) ? 0 : f, j, k);
+}
+
 // x-face flux at the lower face of cell (i + d) of row (j, k) from its four
-// stencil cells; writes the face data the corner EMFs read when `store`
+// stencil cells and the face's normal field bn; writes the face data the
+// corner EMFs read when `store`
 template <typename real, int RS, int TPB>
-__device__ __forceinline__ void xface(CBox& b, int s, XRing<real, TPB>& xr, int slot, int t,
-                                      int col, int ncols, int i, int j, int k, int d, bool store,
-                                      real* fl, int* used) {
+__device__ __forceinline__ void xface(CBox& b, XRing<real, TPB>& xr, int s, int slot, int t,
+                                      int col, int ncols, int i, int j, int k, int d, real bn,
+                                      bool store, real* fl, int* used) {
   St7<real> q[4], wl, wr;
 #pragma unroll
   for (int m = 0; m < 4; m++)
     q[m] = xneighbour<real, TPB>(b, s, xr, slot, t, col, ncols, i, j, k, d + m - 2);
   plm_face<0>(q[0], q[1], q[2], q[3], wl, wr);
-  // lower face of cell i + d: face index i + d (face n of an outflow axis)
-  const int f = i + d;
-  const int fi = fidx(b, 0, (b.per[0] && f == b.n[0]) ? 0 : f, j, k);
-  const real bn = (real)ld<double>(b.B[s][0], fi);
+  const int fi = xface_idx(b, i, j, k, d);
   real F[7], fm, sp[2];
   *used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
 #pragma unroll
@@ -1549,12 +1565,24 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
   const int fstride = b.n[0];
   const int fbase = (tr * b.nf[1]) * b.n[0] + i;
   const int cbase = (tr * b.n[1]) * b.n[0] + i;
+  // y face f in [0, n]; periodic face n is face 0
+  auto face_at = [&](int f) { return fbase + ((per && f == n) ? 0 : f) * fstride; };
+  // FP64: normal fields loaded ahead of their solves (a load completes only
+  // after every load issued before it, so a field loaded just before its
+  // solve waits for the next cell's prefetch): the y face one step ahead,
+  // the x face of the row being completed first thing in its step.  In the
+  // mixed path, whose waves wait less, the extra registers cost more than
+  // the waits (measured), and the fields are loaded at their solves.
+  constexpr bool kAhead = sizeof(real) == 8;
+  real bny_cur = kAhead ? (real)ld<double>(b.B[s][1], face_at(j0)) : (real)0;
   // the lane that holds the face above this lane's cell: its right
   // neighbour in the same row piece, else this lane computes that face
   const int iu = map_cell(i + 1, b.n[0], b.per[0]);
   const bool up_in_ring = (i + 1 < b.n[0] || b.per[0]) && t + (iu - i) >= 0 &&
                           t + (iu - i) < TPB && col + (iu - i) < ncols;
   for (int f = j0; f <= j1; ++f) {
+    const real bnx =
+        kAhead && f > j0 ? (real)ld<double>(b.B[s][0], xface_idx(b, i, f - 1, tr, 0)) : (real)0;
     PrimD w;
     const int fl = raw_to_prim(b, next, w);
     const St7<real> q3 = rotate<real>(w, 1);
@@ -1565,10 +1593,13 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
     if (f <= j0 + 1) __syncthreads();
     if (f + 1 < j1) own_cell(f + 1, w, fl);
     if (f < j1) next = load_raw(b, s, addr_at(f + 2));
+    real bny_nxt = bny_cur;
+    if (kAhead && f < j1) bny_nxt = (real)ld<double>(b.B[s][1], face_at(f + 1));
     St7<real> wl, wr;
     win.face_and_slide(q3, (real)w.by, (real)b.gamma, wl, wr);
-    const int fi = fbase + ((per && f == n) ? 0 : f) * fstride;
-    const real bn = (real)ld<double>(b.B[s][1], fi);
+    const int fi = face_at(f);
+    const real bn = kAhead ? bny_cur : (real)ld<double>(b.B[s][1], fi);
+    bny_cur = bny_nxt;
     real F[7], fm, sp[2];
     const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
     real fy[kNQ];
@@ -1597,8 +1628,9 @@ __device__ __forceinline__ void march_column_xy(CBox& b, int s, int i, int tr, i
         if (d == 1 && up_in_ring) break;
         real fx[kNQ];
         int u = 0;
-        xface<real, RS, TPB>(b, s, xr, slot, t, col, ncols, i, c, tr, d,
-                        d == 0 ? live : (live && up_boundary), fx, &u);
+        const real bnd = kAhead && d == 0 ? bnx : (real)ld<double>(b.B[s][0], xface_idx(b, i, c, tr, d));
+        xface<real, RS, TPB>(b, xr, s, slot, t, col, ncols, i, c, tr, d, bnd,
+                             d == 0 ? live : (live && up_boundary), fx, &u);
 #pragma unroll
         for (int q = 0; q < kNQ; q++) {
           if (d == 0) flo[q] = fx[q]; else fup[q] = fx[q];
@@ -1983,16 +2015,21 @@ __device__ __forceinline__ real corner_avg(int emf, real fa1, real fa0, real fb1
 
 // Corner EMFs: for every corner position one lane computes the EMF along
 // each axis c whose range contains it: the contact-upwinded average of
-// Gardiner & Stone (2005) (b.emf = 0), their E0 average with every
+// Gardiner & Stone (2005) (EMF = 0), their E0 average with every
 // face-to-corner derivative taken as the mean of its two sides (1), or the
 // mean of the four face EMFs (2, Balsara & Spicer 1999; no cell EMF or mass
 // flux is read).  A lane walks ct_planes planes of its column: the EMFs
 // along x and y at plane k read the plane below (z-cell k - 1) for the
 // y-face and x-face EMFs, mass fluxes and cell EMFs that the lane loaded
-// itself at plane k - 1, so from the second plane on those come from
-// registers (the same values, so the same results).
-template <typename real>
+// itself at plane k - 1, so those come from registers (loaded once before
+// the walk for its first plane; the same values, so the same results).
+// Every load of a plane is issued before any of its EMFs is formed; a
+// position outside an axis's range loads a clamped, valid index and
+// stores nothing for that axis.
+template <typename real, int EMF>
 __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
+  constexpr bool cm = EMF != 2;   // cell EMFs read
+  constexpr bool mf = EMF == 0;   // mass fluxes read
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
     const int tile = tile_of(L, v);
     if (tile >= L.ntiles) continue;
@@ -2006,100 +2043,117 @@ __global__ __launch_bounds__(kTPB) void k_ct_edge(Launch L) {
     // mapped cell indices of the positions and of the positions - 1 in x, y
     const int m1x = map_cell(i, b.n[0], b.per[0]), m0x = map_cell(i - 1, b.n[0], b.per[0]);
     const int m1y = map_cell(j, b.n[1], b.per[1]), m0y = map_cell(j - 1, b.n[1], b.per[1]);
-    const bool cm = b.emf != 2;   // cell EMFs read
-    const bool mf = b.emf == 0;   // mass fluxes read
-    // plane-k values of the EMFs along x (y-face EMF and mass flux, cell
-    // EMFs (i, m0y) and (i, m1y)) and along y (x-face EMF and mass flux, cell
-    // EMFs (m0x, j) and (m1x, j)), which are the next plane's plane-below
-    real xa = 0, xma = 0, xe0 = 0, xe1 = 0, ya = 0, yma = 0, ye0 = 0, ye1 = 0;
+    const bool ex_on = i < b.n[0], ey_on = j < b.n[1];
+    const int ic = ex_on ? i : b.n[0] - 1;   // x-cell index of the EMF along x
+    const int jc = ey_on ? j : b.n[1] - 1;   // y-cell index of the EMF along y
+    // plane-below values of the EMFs along x (y-face EMF and mass flux at
+    // (ic, j), cell EMFs (ic, m0y) and (ic, m1y)) and along y (x-face EMF
+    // and mass flux at (i, jc), cell EMFs (m0x, jc) and (m1x, jc))
+    real xa, xma = 0, xe0 = 0, xe1 = 0, ya, yma = 0, ye0 = 0, ye1 = 0;
+    {
+      const int m0z = map_cell(pos[2] - 1, b.n[2], b.per[2]);
+      xa = ld<real>(b.EF[1][1], fidx(b, 1, ic, j, m0z));
+      ya = ld<real>(b.EF[0][0], fidx(b, 0, i, jc, m0z));
+      if (mf) {
+        xma = ld<real>(b.MF[1], fidx(b, 1, ic, j, m0z));
+        yma = ld<real>(b.MF[0], fidx(b, 0, i, jc, m0z));
+      }
+      if (cm) {
+        xe0 = ld<real>(b.Ec[0], cidx(b, ic, m0y, m0z));
+        xe1 = ld<real>(b.Ec[0], cidx(b, ic, m1y, m0z));
+        ye0 = ld<real>(b.Ec[1], cidx(b, m0x, jc, m0z));
+        ye1 = ld<real>(b.Ec[1], cidx(b, m1x, jc, m0z));
+      }
+    }
     for (int kk = 0; kk < nk; ++kk) {
       const int k = pos[2] + kk;
-      const int m1z = map_cell(k, b.n[2], b.per[2]), m0z = map_cell(k - 1, b.n[2], b.per[2]);
-      const bool carry = kk > 0;
-      if (k < b.n[2]) {
-        // along z: a = x-faces (i; m1y), (i; m0y), b = y-faces (j; m1x), (j; m0x)
-        const int fa1i = fidx(b, 0, i, m1y, k), fa0i = fidx(b, 0, i, m0y, k);
-        const int fb1i = fidx(b, 1, m1x, j, k), fb0i = fidx(b, 1, m0x, j, k);
-        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
-        if (cm) {
-          ec[0] = ld<real>(b.Ec[2], cidx(b, m0x, m0y, k));
-          ec[1] = ld<real>(b.Ec[2], cidx(b, m1x, m0y, k));
-          ec[2] = ld<real>(b.Ec[2], cidx(b, m0x, m1y, k));
-          ec[3] = ld<real>(b.Ec[2], cidx(b, m1x, m1y, k));
-        }
-        if (mf) {
-          ma1 = ld<real>(b.MF[0], fa1i);
-          ma0 = ld<real>(b.MF[0], fa0i);
-          mb1 = ld<real>(b.MF[1], fb1i);
-          mb0 = ld<real>(b.MF[1], fb0i);
-        }
-        const real e = corner_avg<real>(b.emf, ld<real>(b.EF[0][1], fa1i), ld<real>(b.EF[0][1], fa0i),
-                                        ld<real>(b.EF[1][0], fb1i), ld<real>(b.EF[1][0], fb0i), ec,
-                                        ma1, ma0, mb1, mb0);
-        st<real>(b.ED[2], eidx(b, 2, i, j, k), e);
+      const int m1z = map_cell(k, b.n[2], b.per[2]);
+      const bool ez_on = k < b.n[2];
+      const int kc = ez_on ? k : b.n[2] - 1;   // z-cell index of the EMF along z
+      // loads of the plane
+      // along z: a = x-faces (i; m1y), (i; m0y), b = y-faces (j; m1x), (j; m0x)
+      const int za1 = fidx(b, 0, i, m1y, kc), za0 = fidx(b, 0, i, m0y, kc);
+      const int zb1 = fidx(b, 1, m1x, j, kc), zb0 = fidx(b, 1, m0x, j, kc);
+      const real zfa1 = ld<real>(b.EF[0][1], za1), zfa0 = ld<real>(b.EF[0][1], za0);
+      const real zfb1 = ld<real>(b.EF[1][0], zb1), zfb0 = ld<real>(b.EF[1][0], zb0);
+      real zec[4] = {0, 0, 0, 0}, zm[4] = {0, 0, 0, 0};
+      if (cm) {
+        zec[0] = ld<real>(b.Ec[2], cidx(b, m0x, m0y, kc));
+        zec[1] = ld<real>(b.Ec[2], cidx(b, m1x, m0y, kc));
+        zec[2] = ld<real>(b.Ec[2], cidx(b, m0x, m1y, kc));
+        zec[3] = ld<real>(b.Ec[2], cidx(b, m1x, m1y, kc));
       }
-      if (i < b.n[0]) {
-        // along x: a = y-faces (j; m1z), (j; m0z), b = z-faces (k; m1y), (k; m0y)
-        const int fa1i = fidx(b, 1, i, j, m1z);
-        const int fb1i = fidx(b, 2, i, m1y, k), fb0i = fidx(b, 2, i, m0y, k);
-        const real fa1 = ld<real>(b.EF[1][1], fa1i);
-        const real fa0 = carry ? xa : ld<real>(b.EF[1][1], fidx(b, 1, i, j, m0z));
-        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
-        if (cm) {
-          ec[0] = carry ? xe0 : ld<real>(b.Ec[0], cidx(b, i, m0y, m0z));
-          ec[1] = carry ? xe1 : ld<real>(b.Ec[0], cidx(b, i, m1y, m0z));
-          ec[2] = ld<real>(b.Ec[0], cidx(b, i, m0y, m1z));
-          ec[3] = ld<real>(b.Ec[0], cidx(b, i, m1y, m1z));
-        }
-        if (mf) {
-          ma1 = ld<real>(b.MF[1], fa1i);
-          ma0 = carry ? xma : ld<real>(b.MF[1], fidx(b, 1, i, j, m0z));
-          mb1 = ld<real>(b.MF[2], fb1i);
-          mb0 = ld<real>(b.MF[2], fb0i);
-        }
-        const real e = corner_avg<real>(b.emf, fa1, fa0, ld<real>(b.EF[2][0], fb1i),
-                                        ld<real>(b.EF[2][0], fb0i), ec, ma1, ma0, mb1, mb0);
-        st<real>(b.ED[0], eidx(b, 0, i, j, k), e);
-        xa = fa1;
-        xma = ma1;
-        xe0 = ec[2];
-        xe1 = ec[3];
+      if (mf) {
+        zm[0] = ld<real>(b.MF[0], za1);
+        zm[1] = ld<real>(b.MF[0], za0);
+        zm[2] = ld<real>(b.MF[1], zb1);
+        zm[3] = ld<real>(b.MF[1], zb0);
       }
-      if (j < b.n[1]) {
-        // along y: a = z-faces (k; m1x), (k; m0x), b = x-faces (i; m1z), (i; m0z)
-        const int fa1i = fidx(b, 2, m1x, j, k), fa0i = fidx(b, 2, m0x, j, k);
-        const int fb1i = fidx(b, 0, i, j, m1z);
-        const real fb1 = ld<real>(b.EF[0][0], fb1i);
-        const real fb0 = carry ? ya : ld<real>(b.EF[0][0], fidx(b, 0, i, j, m0z));
-        real ec[4] = {0, 0, 0, 0}, ma1 = 0, ma0 = 0, mb1 = 0, mb0 = 0;
-        if (cm) {
-          ec[0] = carry ? ye0 : ld<real>(b.Ec[1], cidx(b, m0x, j, m0z));
-          ec[1] = ld<real>(b.Ec[1], cidx(b, m0x, j, m1z));
-          ec[2] = carry ? ye1 : ld<real>(b.Ec[1], cidx(b, m1x, j, m0z));
-          ec[3] = ld<real>(b.Ec[1], cidx(b, m1x, j, m1z));
-        }
-        if (mf) {
-          ma1 = ld<real>(b.MF[2], fa1i);
-          ma0 = ld<real>(b.MF[2], fa0i);
-          mb1 = ld<real>(b.MF[0], fb1i);
-          mb0 = carry ? yma : ld<real>(b.MF[0], fidx(b, 0, i, j, m0z));
-        }
-        const real e = corner_avg<real>(b.emf, ld<real>(b.EF[2][1], fa1i),
-                                        ld<real>(b.EF[2][1], fa0i), fb1, fb0, ec, ma1, ma0, mb1,
-                                        mb0);
-        st<real>(b.ED[1], eidx(b, 1, i, j, k), e);
-        ya = fb1;
-        yma = mb1;
-        ye0 = ec[1];
-        ye1 = ec[3];
+      // along x: a = y-faces (j; m1z), (j; m0z), b = z-faces (k; m1y), (k; m0y)
+      const int xa1 = fidx(b, 1, ic, j, m1z);
+      const int xb1 = fidx(b, 2, ic, m1y, k), xb0 = fidx(b, 2, ic, m0y, k);
+      const real xfa1 = ld<real>(b.EF[1][1], xa1);
+      const real xfb1 = ld<real>(b.EF[2][0], xb1), xfb0 = ld<real>(b.EF[2][0], xb0);
+      real xec2 = 0, xec3 = 0, xm1 = 0, xmb1 = 0, xmb0 = 0;
+      if (cm) {
+        xec2 = ld<real>(b.Ec[0], cidx(b, ic, m0y, m1z));
+        xec3 = ld<real>(b.Ec[0], cidx(b, ic, m1y, m1z));
       }
+      if (mf) {
+        xm1 = ld<real>(b.MF[1], xa1);
+        xmb1 = ld<real>(b.MF[2], xb1);
+        xmb0 = ld<real>(b.MF[2], xb0);
+      }
+      // along y: a = z-faces (k; m1x), (k; m0x), b = x-faces (i; m1z), (i; m0z)
+      const int ya1 = fidx(b, 2, m1x, jc, k), ya0 = fidx(b, 2, m0x, jc, k);
+      const int yb1 = fidx(b, 0, i, jc, m1z);
+      const real yfa1 = ld<real>(b.EF[2][1], ya1), yfa0 = ld<real>(b.EF[2][1], ya0);
+      const real yfb1 = ld<real>(b.EF[0][0], yb1);
+      real yec1 = 0, yec3 = 0, yma1 = 0, yma0 = 0, ymb1 = 0;
+      if (cm) {
+        yec1 = ld<real>(b.Ec[1], cidx(b, m0x, jc, m1z));
+        yec3 = ld<real>(b.Ec[1], cidx(b, m1x, jc, m1z));
+      }
+      if (mf) {
+        yma1 = ld<real>(b.MF[2], ya1);
+        yma0 = ld<real>(b.MF[2], ya0);
+        ymb1 = ld<real>(b.MF[0], yb1);
+      }
+      // the EMFs of the plane
+      if (ez_on)
+        st<real>(b.ED[2], eidx(b, 2, i, j, k),
+                 corner_avg<real>(EMF, zfa1, zfa0, zfb1, zfb0, zec, zm[0], zm[1], zm[2], zm[3]));
+      if (ex_on) {
+        const real ec[4] = {xe0, xe1, xec2, xec3};
+        st<real>(b.ED[0], eidx(b, 0, i, j, k),
+                 corner_avg<real>(EMF, xfa1, xa, xfb1, xfb0, ec, xm1, xma, xmb1, xmb0));
+      }
+      if (ey_on) {
+        const real ec[4] = {ye0, yec1, ye1, yec3};
+        st<real>(b.ED[1], eidx(b, 1, i, j, k),
+                 corner_avg<real>(EMF, yfa1, yfa0, yfb1, ya, ec, yma1, yma0, ymb1, yma));
+      }
+      // this plane's values are the next plane's plane-below values
+      xa = xfa1;
+      xma = xm1;
+      xe0 = xec2;
+      xe1 = xec3;
+      ya = yfb1;
+      yma = ymb1;
+      ye0 = yec1;
+      ye1 = yec3;
     }
   }
 }
 
 // Face update: dB_d/dt = -[(E_f(e+1/2) - E_f(e-1/2))/dx_e
 //                          - (E_e(f+1/2) - E_e(f-1/2))/dx_f], (d, e, f)
-// cyclic, formed in FP64, then the Runge-Kutta stage combine.
+// cyclic, formed in FP64, then the Runge-Kutta stage combine.  Every input
+// of the lane's three faces is loaded before any is used (an index that a
+// face does not need points at a valid element, mostly one the lane reads
+// anyway, and its value is not used), so that the loads overlap instead of
+// waiting one after another behind the conditions on the axes and the
+// combine.
 template <typename real>
 __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
   for (int v = blockIdx.x; v < tile_slots(L); v += gridDim.x) {
@@ -2113,30 +2167,51 @@ __global__ __launch_bounds__(kTPB) void k_ct_face(Launch L) {
     int pos[3];
     unflatten(p, b.nf[0], b.nf[1], pos);
     const double dt = b.scal[0];
+    bool ok[3];
+    int fi[3], i1h[3], i1l[3], i2h[3], i2l[3];
+    real e1h[3], e1l[3], e2h[3], e2l[3];
+    double bs[3], bo[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
       const int e = (d + 1) % 3, f = (d + 2) % 3;
-      if (pos[e] >= b.n[e] || pos[f] >= b.n[f]) continue;
+      ok[d] = pos[e] < b.n[e] && pos[f] < b.n[f];
+      // a face that does not exist reads its lane's first face instead
+      int q0[3] = {pos[0], pos[1], pos[2]};
+      if (!ok[d]) q0[e] = q0[f] = 0;
+      const int lo_f = eidx(b, f, q0[0], q0[1], q0[2]);
+      const int lo_e = eidx(b, e, q0[0], q0[1], q0[2]);
+      int q[3] = {q0[0], q0[1], q0[2]};
+      if (b.act[e]) q[e] = face_up(q0[e], b.n[e], b.per[e]);
+      i1h[d] = b.act[e] ? eidx(b, f, q[0], q[1], q[2]) : lo_f;
+      i1l[d] = lo_f;
+      q[e] = q0[e];
+      if (b.act[f]) q[f] = face_up(q0[f], b.n[f], b.per[f]);
+      i2h[d] = b.act[f] ? eidx(b, e, q[0], q[1], q[2]) : lo_e;
+      i2l[d] = lo_e;
+      fi[d] = fidx(b, d, q0[0], q0[1], q0[2]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int e = (d + 1) % 3, f = (d + 2) % 3;
+      e1h[d] = ld<real>(b.ED[f], i1h[d]);
+      e1l[d] = ld<real>(b.ED[f], i1l[d]);
+      e2h[d] = ld<real>(b.ED[e], i2h[d]);
+      e2l[d] = ld<real>(b.ED[e], i2l[d]);
+      bs[d] = ld<double>(b.B[L.stage][d], fi[d]);
+      // the start-of-step field for the combine; without a combine the same
+      // element as bs again (no extra traffic), its value unused
+      bo[d] = ld<double>(b.B[L.comb ? 0 : L.stage][d], fi[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int e = (d + 1) % 3, f = (d + 2) % 3;
+      if (!ok[d]) continue;
       double t1 = 0.0, t2 = 0.0;
-      if (b.act[e]) {
-        int q[3] = {pos[0], pos[1], pos[2]};
-        q[e] = face_up(pos[e], b.n[e], b.per[e]);
-        const double hi = (double)ld<real>(b.ED[f], eidx(b, f, q[0], q[1], q[2]));
-        const double lo = (double)ld<real>(b.ED[f], eidx(b, f, pos[0], pos[1], pos[2]));
-        t1 = (hi - lo) * b.idx[e];
-      }
-      if (b.act[f]) {
-        int q[3] = {pos[0], pos[1], pos[2]};
-        q[f] = face_up(pos[f], b.n[f], b.per[f]);
-        const double hi = (double)ld<real>(b.ED[e], eidx(b, e, q[0], q[1], q[2]));
-        const double lo = (double)ld<real>(b.ED[e], eidx(b, e, pos[0], pos[1], pos[2]));
-        t2 = (hi - lo) * b.idx[f];
-      }
+      if (b.act[e]) t1 = ((double)e1h[d] - (double)e1l[d]) * b.idx[e];
+      if (b.act[f]) t2 = ((double)e2h[d] - (double)e2l[d]) * b.idx[f];
       const double rate = -(t1 - t2);
-      const int fi = fidx(b, d, pos[0], pos[1], pos[2]);
-      const double bold = L.comb ? ld<double>(b.B[0][d], fi) : 0.0;
-      st<double>(b.B[L.dst][d], fi,
-                 rk_combine(L.comb, bold, ld<double>(b.B[L.stage][d], fi), dt * rate));
+      const double bold = L.comb ? bo[d] : 0.0;
+      st<double>(b.B[L.dst][d], fi[d], rk_combine(L.comb, bold, bs[d], dt * rate));
     }
   }
 }

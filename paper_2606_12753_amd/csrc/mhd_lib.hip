@@ -348,6 +348,7 @@ struct mhd_ctx {
   int fz = 0;  // every box: one cell along z, more along y (no z march)
   int sl = 0;  // slope kind: recon + 2 * limiter (MHD_REC_*, MHD_LIM_*)
   int uct = 0;  // corner EMFs by the upwind CT (MHD_EMF_UCT_HLL)
+  int emf = 0;  // corner average (config ct_emf)
   int fusable = 0;  // the y march may compute the x faces (x variant 0):
                     // primitive minmod slopes, no upwind CT, no fused 2D y
                     // march, x and y active in every box
@@ -421,6 +422,7 @@ int enqueue_step_t(mhd_ctx* c) {
   sc.sl = c->sl;
   sc.xcd = c->var_xcd;
   sc.uct = c->uct;
+  sc.emf = c->emf;
   sc.stream = c->stream;
   const bool timing = (c->flags & MHD_F_TIMING) != 0;
   sc.ev = timing ? c->ev.data() : nullptr;
@@ -887,6 +889,7 @@ int mhd_create(const mhd_config* cfg, mhd_ctx** out) {
   c->rs = cfg->riemann;
   c->sl = cfg->recon + 2 * cfg->limiter;
   c->uct = cfg->ct_emf == MHD_EMF_UCT_HLL;
+  c->emf = cfg->ct_emf;
   c->fz = 1;
   for (int b = 0; b < cfg->nboxes; b++)
     if (cfg->boxes[b].n[2] != 1 || cfg->boxes[b].n[1] == 1) c->fz = 0;

@@ -37,6 +37,8 @@ struct StepCtx {
   int xcd;             // XCD-grouped tile order, bit k for kernel kind k
                        // (kXS .. kCTF)
   int uct;             // corner EMFs by the upwind CT (k_ct_uct)
+  int emf;             // corner average of k_ct_edge (0 contact-upwinded,
+                       // 1 E0, 2 arithmetic)
   hipStream_t stream;
   hipEvent_t* ev;      // timing: an event pair per launch, or null
   int* ev_kind;        // timing: kernel kind of each pair
@@ -209,8 +211,12 @@ inline int enqueue_step_sl(const StepCtx& sc) {
     mark(MHD_K_CT_EDGE, true);
     if (sc.uct)
       hipLaunchKernelGGL(k_ct_uct<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+    else if (sc.emf == 1)
+      hipLaunchKernelGGL((k_ct_edge<real, 1>), dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+    else if (sc.emf == 2)
+      hipLaunchKernelGGL((k_ct_edge<real, 2>), dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
     else
-      hipLaunchKernelGGL(k_ct_edge<real>, dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
+      hipLaunchKernelGGL((k_ct_edge<real, 0>), dim3(grid(kCTE)), dim3(kTPB), 0, sc.stream, L);
     mark(MHD_K_CT_EDGE, false);
     L.ntiles = sc.total[kCTF];
     L.xcd = (sc.xcd >> kCTF) & 1;
