@@ -1335,6 +1335,10 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
   const double dt = kFin ? b.scal[0] : 0.0;
   int cw = (j0 + 1) % 3;  // ring slot of cell f+1 at face f
   for (int f = j0; f <= j1; ++f) {
+    // the face's normal field first: a load completes only after every
+    // earlier one, so loaded after the next cell's prefetch its solve would
+    // wait for that prefetch too
+    const real bn = (real)ld<double>(b.B[s][D], face_at(f));
     PrimD w;
     raw_to_prim(b, next, w);
     const St7<real> q3 = rotate<real>(w, D);
@@ -1379,7 +1383,6 @@ __device__ __forceinline__ void march_column(CBox& b, int s, int dst, int comb, 
     St7<real> wl, wr;
     win.face_and_slide(q3, bnorm(w), gam, wl, wr);
     const int fi = face_at(f);
-    const real bn = (real)ld<double>(b.B[s][D], fi);
     real F[7], fm, sp[2];
     const int used = riemann<real, RS>(wl, wr, bn, (real)b.gamma, (real)b.igm1, F, &fm, sp);
     // lab-frame hydro flux: (rho, mx, my, mz, E)
