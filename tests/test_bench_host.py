@@ -28,7 +28,8 @@ def test_kernel_names_and_launch_keys():
         "mhd::k_sweep_march<float, 1, 1, 0, 1, 0, 0, 0, 0>"
     assert bench.kernel_name("sweep_z", "float", v) == \
         "mhd::k_sweep_march<float, 2, 1, 0, 1, 1, 0, 0, 0>"
-    assert bench.kernel_name("ct_edge", "double", v) == "mhd::k_ct_edge<double>"
+    assert bench.kernel_name("ct_edge", "double", v) == "mhd::k_ct_edge<double, 0>"
+    assert bench.kind_of("void mhd::k_ct_edge<float, 0>(mhd::Launch)") == ("mixed", "ct_edge")
     assert bench.launch_key("sweep_y", "float", v).endswith("|seg=64|persistent=0")
     assert bench.launch_key("sweep_z", "float", v).endswith("|seg=128|persistent=0")
     assert bench.launch_key("sweep_x", "double", v) == "mhd::k_sweep_x<double, 1, 0, 0>|persistent=0"
