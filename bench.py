@@ -195,6 +195,10 @@ def parse():
                     help="write the SQ-counter record from a --pmc run of the counter pass and "
                          "a kernel trace of the same variants")
     ap.add_argument("--sq-command", default="", help="command of the SQ-counter run")
+    ap.add_argument("--ingest-waves", metavar="SQ_CSV",
+                    help="write the wave-cycle record (where the waves of each kernel spend "
+                         "their cycles) from a --pmc run of the counter pass with WAVE_COUNTERS")
+    ap.add_argument("--waves-command", default="", help="command of the wave-cycle run")
     ap.add_argument("--trace-out", default="kernel_trace_paper_cases.md",
                     help="file under profiles/ for the summary of a run without a bench line")
     a = ap.parse_args()
@@ -207,7 +211,7 @@ def parse():
         a.cpu_n = w["cpu_n"]
     if a.cpu_steps is None:
         a.cpu_steps = w["cpu_steps"]
-    recorded = " ".join((a.fetch_command, a.write_command, a.sq_command))
+    recorded = " ".join((a.fetch_command, a.write_command, a.sq_command, a.waves_command))
     fixed = BENCH_VARIANTS.get((a.workload, a.n), {})
     for attr, flag, key, default in (("variant64", "--variant64", "fp64", "1,1,64,0,64"),
                                      ("variant_mixed", "--variant-mixed", "mixed", "1,1,64,0,128")):
@@ -738,6 +742,57 @@ def ingest_sq(a):
     print("\n".join(lines))
 
 
+# one --pmc pass: cycles of the resident waves and what they were doing
+WAVE_COUNTERS = ("SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                 "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS")
+
+
+def ingest_waves(a):
+    """Writes where the waves of each of the benchmark's kernels spend their
+    cycles, from one rocprofv3 --pmc run of the counter pass with
+    WAVE_COUNTERS: each counter summed over the kernel's dispatches, as a
+    fraction of the summed wave-cycles.  A wave can be issuing one
+    instruction while waiting on another, so the fractions need not add
+    up to one."""
+    import csv
+    per = {}
+    with open(a.ingest_waves, newline="") as fh:
+        for r in csv.DictReader(fh):
+            k = kind_of(r["Kernel_Name"])
+            if k is None or r["Counter_Name"] not in WAVE_COUNTERS:
+                continue
+            rec = per.setdefault((k, r["Kernel_Name"]), {})
+            rec[r["Counter_Name"]] = rec.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# Wave cycles: {a.workload} {a.n}^3, the benchmark's kernels", "",
+             "Command (from the repository root):", "", "```", a.waves_command, "```", "",
+             f"Kernel source hash {source_sha()}; variants FP64 {a.variant64}, mixed "
+             f"{a.variant_mixed}.  Each column is a counter summed over the kernel's dispatches "
+             "divided by SQ_WAVE_CYCLES summed the same way: SQ_ACTIVE_INST_VALU (a VALU "
+             "instruction in flight), SQ_WAIT_ANY (waiting on a memory counter or a barrier), "
+             "SQ_WAIT_INST_ANY (waiting to issue: dependencies and arbitration), "
+             "SQ_ACTIVE_INST_LDS and SQ_WAIT_INST_LDS.  A wave can issue while it waits on "
+             "an earlier load, so the columns need not add up to one.", "",
+             "| precision | kernel | VALU active | waiting (memory, barrier) | waiting to issue | "
+             "LDS active | LDS issue wait |",
+             "|---|---|---:|---:|---:|---:|---:|"]
+    record = {"workload": f"{a.workload} {a.n}^3", "source_sha": source_sha(),
+              "command": a.waves_command, "fp64": {}, "mixed": {}}
+    for ((key, kind), name), rec in sorted(per.items(), key=lambda x: (x[0][0][0], KINDS.index(x[0][0][1]))):
+        cyc = rec.get("SQ_WAVE_CYCLES", 0.0)
+        if cyc <= 0:
+            continue
+        f = {c: rec.get(c, 0.0) / cyc for c in WAVE_COUNTERS[1:]}
+        lines.append(f"| {key} | `{name.replace('void ', '').replace('(mhd::Launch)', '')}` | "
+                     + " | ".join(f"{f[c]:.2f}" for c in WAVE_COUNTERS[1:]) + " |")
+        record[key][name] = {c: round(v, 4) for c, v in f.items()}
+    with open(profile_file("sq_wave_cycles", a, "md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(profile_file("sq_wave_cycles", a, "json"), "w") as fh:
+        json.dump(record, fh, indent=1)
+        fh.write("\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(a):
     """Writes the kernel-trace summary: rocprofv3's per-kernel statistics and,
     for the dominant kernel of each precision, the average duration of the
@@ -1004,6 +1059,9 @@ def main():
         return
     if a.ingest_sq:
         ingest_sq(a)
+        return
+    if a.ingest_waves:
+        ingest_waves(a)
         return
     if a.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "

@@ -102,6 +102,41 @@ def test_ingest_counters_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     assert k["launch"] == bench.launch_key("sweep_x", "double", [1, 2, 64, 0, 64])
 
 
+def test_ingest_waves_divides_each_counter_by_the_wave_cycles(tmp_path, monkeypatch):
+    """Each counter is summed over the kernel's dispatches and divided by the
+    summed wave-cycles; kernels outside the benchmark's kinds and counters
+    outside the pass are ignored."""
+    xy = "void mhd::k_sweep_march_xy<double, 0, 0, 512>(mhd::Launch)"
+    rows = []
+    for i, (cyc, valu, wait) in enumerate(((1000.0, 300.0, 400.0), (3000.0, 900.0, 1200.0))):
+        for c, v in (("SQ_WAVE_CYCLES", cyc), ("SQ_ACTIVE_INST_VALU", valu), ("SQ_WAIT_ANY", wait),
+                     ("SQ_WAIT_INST_ANY", cyc / 5), ("SQ_ACTIVE_INST_LDS", cyc / 100),
+                     ("SQ_WAIT_INST_LDS", 0.0), ("SQ_BUSY_CYCLES", 7.0)):
+            rows.append({"Dispatch_Id": i, "Kernel_Name": xy, "Counter_Name": c,
+                         "Counter_Value": v})
+    rows.append({"Dispatch_Id": 9, "Kernel_Name": "__amd_rocclr_copyBuffer",
+                 "Counter_Name": "SQ_WAVE_CYCLES", "Counter_Value": 5.0})
+    path = tmp_path / "w.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    monkeypatch.setattr(bench, "profile_file",
+                        lambda kind, a, ext: str(tmp_path / f"{kind}.{ext}"))
+    args = bench.argparse.Namespace(ingest_waves=str(path), n=512, workload="turbulence",
+                                    waves_command="cmd", variant64="0,1,64,0,64",
+                                    variant_mixed="0,9,128,0,128")
+    bench.ingest_waves(args)
+    rec = json.loads((tmp_path / "sq_wave_cycles.json").read_text())
+    assert list(rec["fp64"]) == [xy] and rec["mixed"] == {}
+    f = rec["fp64"][xy]
+    assert f == {"SQ_ACTIVE_INST_VALU": 0.3, "SQ_WAIT_ANY": 0.4, "SQ_WAIT_INST_ANY": 0.2,
+                 "SQ_ACTIVE_INST_LDS": 0.01, "SQ_WAIT_INST_LDS": 0.0}
+    md = (tmp_path / "sq_wave_cycles.md").read_text()
+    assert "| fp64 | `mhd::k_sweep_march_xy<double, 0, 0, 512>` | 0.30 | 0.40 | 0.20 | 0.01 | 0.00 |" in md
+    assert "cmd" in md
+
+
 def test_counter_records_take_the_variants_of_their_commands(monkeypatch):
     """Ingestion keys a counter record by the launch variants the recorded
     counter runs used, unless they are given explicitly."""
