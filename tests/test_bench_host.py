@@ -192,3 +192,19 @@ def test_drift_of_totals():
     z = [a[0], a[1], a[2], np.zeros(3), a[4]]
     d = bench.drift(z, [a[0], a[1], a[2], np.array([0.0, 0.0, 1.2e-11]), a[4]])
     assert abs(d["mz"] - 1.2e-11 / 12.0) < 1e-15
+
+
+def test_committed_records_describe_the_benchmark_kernels():
+    """The HBM-traffic and SQ-counter records of the benchmark workload were
+    taken on the current kernel sources with the launch variants the bench
+    runs, so the bench line's roofline carries their traffic and VALU issue
+    for the dominant kernel of both precisions.  A kernel change makes them
+    stale until the counter runs are repeated (their commands are in the
+    records)."""
+    a = bench.argparse.Namespace(workload="turbulence", n=512)
+    variants = bench.BENCH_VARIANTS[("turbulence", 512)]
+    for precision, key in ((0, "fp64"), (1, "mixed")):
+        v = bench.parse_variant(variants[key])
+        for kind in ("hbm_traffic", "sq_counters"):
+            path = bench.profile_file(kind, a, "json")
+            assert bench.recorded_kernel(path, precision, "sweep_y", v) is not None, (kind, key)
