@@ -193,7 +193,7 @@ def turbulence_3d(n: int = 512, seed: int = 2607, steps: int = 200,
     del div
     for c in vh:
         c[0, 0, 0] = 0.0
-    v = [np.fft.irfftn(c, s=(n, n, n)) for c in vh]
+    v = [np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2)) for c in vh]
     del vh
     rms = math.sqrt(float(np.mean(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)))
     v = [c * (v_rms / rms) for c in v]
