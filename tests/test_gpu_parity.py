@@ -8,7 +8,8 @@ its rounding scales with the vector's magnitude and a component that is
 near zero by symmetry (the normal momentum of a transverse wave, B_z without
 a guide field) would otherwise compare rounding noise with rounding noise.
 The element-wise maximum relative error (each difference over |oracle
-value| + the variable's mean magnitude) is printed beside it.  The two codes round independently (the oracle writes its
+value| + the variable's mean magnitude) is printed beside it and held to
+TOL64_EL, a bar for gross errors in single cells.  The two codes round independently (the oracle writes its
 quotients as divisions, the library as reciprocals and products, with its
 own contraction), so they agree to rounding, not bit for bit.  The time
 agrees within 1e-12 relative, a single time step computed from one state
@@ -31,6 +32,13 @@ from paper_2606_12753_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
+# Element-wise bar of the FP64 comparison, a detector of gross errors in
+# single cells (a wrong index or branch gives an error of order one).  The
+# two codes' rounding differences are amplified by limiter switches, HLL
+# fallbacks and pressure-floor hits, so single cells of a long shocked run
+# differ by far more than the L1 norms do (1e-16 to 6.6e-9 measured,
+# the largest on the blast after 100 steps with two million floor hits).
+TOL64_EL = 1e-6
 TOLMIX = 1e-4
 # One CFL time step from a state both codes hold bit for bit: the rate of a
 # cell takes about 30 FP64 operations (three of them square roots and
@@ -115,6 +123,7 @@ def assert_fp64_parity(g, o, label=""):
         assert e <= TOL64, (label, name, e)
     print(f"[fp64 parity] {label}: max rel L1 {worst:.2e}, max element rel {worst_el:.2e}, "
           f"t rel {abs(gt - ot) / abs(ot) if ot else 0.0:.1e}, counters {gcnt}", flush=True)
+    assert worst_el <= TOL64_EL, (label, worst_el)
     assert gcnt == ocnt, (label, gcnt, ocnt)
     return worst
 
@@ -745,6 +754,7 @@ def _check_sampled(spec, st, cons, bface, dts, centres, r=8, rk=2, solver="hlld"
     print(f"[fp64 parity] {label}: {len(centres)} neighbourhoods, {ncell} cells, "
           f"{len(dts)} step(s): max rel L1 {worst:.2e}, max element rel {worst_el:.2e}",
           flush=True)
+    assert worst_el <= TOL64_EL, (label, worst_el)
 
 
 def test_blast_256_full_size_sampled():
