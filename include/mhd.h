@@ -111,7 +111,8 @@ extern "C" {
 #define MHD_K_LAMBDA 0   /* CFL rate max-reduction, per tile */
 #define MHD_K_DT 1       /* per-box time step from the tile maxima */
 #define MHD_K_SWEEP_X 2  /* x faces: PLM + Riemann solver */
-#define MHD_K_SWEEP_Y 3  /* y faces + x/y flux divergence */
+#define MHD_K_SWEEP_Y 3  /* y faces + x/y flux divergence (fused march:
+                            the x faces too) */
 #define MHD_K_SWEEP_Z 4  /* z faces + divergence + RK stage combine */
 #define MHD_K_CT_EDGE 5  /* constrained-transport corner EMFs */
 #define MHD_K_CT_FACE 6  /* face-field update + RK stage combine */
@@ -236,22 +237,25 @@ int mhd_counters(mhd_ctx *ctx, int32_t box, int64_t counters[3]);
 int mhd_kernel_times(mhd_ctx *ctx, double ms[MHD_NKERNELS],
                      int64_t launches[MHD_NKERNELS], int32_t reset);
 
-/* The launch variant in use: [0] min waves per SIMD of the x sweep's
- * register budget (1 = unconstrained, 3, 4), or 0 / 2: no x sweep, the y
- * march computes the x faces of its rows with its sliding window in
- * registers in workgroups of 512 lanes (0) or, in the mixed path only, in
- * LDS with 256 lanes (2), and [1] then chooses the z march's variant alone
- * (offered for primitive minmod slopes
- * without the upwind CT when every box has more than one cell along x and
- * y), [1] y/z march variant (1:
- * unconstrained registers with the update inputs prefetched ahead of the
- * Riemann solve, 2: unconstrained without prefetch, 3 / 4: at least 3 / 4
- * waves per SIMD without prefetch, 5 / 6 / 7: the sliding window kept in
- * LDS, with prefetch / without / at least 3 waves per SIMD, 8 / 9 / 10:
- * variants 2 / 6 / 7 whose z march keeps the swept state of its last three
- * cells in LDS for the RK combine instead of reading it again), [2] y march
- * segment length (cells), [3] persistent grid (0/1), [4] z march segment
- * length (cells).
+/* The launch variant in use, five entries:
+ * [0] the x direction.  1, 3 or 4: the x sweep, with at least that many
+ *     waves per SIMD in its register budget (1 = unconstrained).  0 or 2:
+ *     no x sweep; the y march also solves the x faces of its rows (fused
+ *     march), with its sliding window in registers and workgroups of 512
+ *     lanes (0) or, in the mixed path only, in LDS with 256 lanes (2).  The
+ *     fused march is offered for primitive minmod slopes without the upwind
+ *     CT when every box has more than one cell along x and y.
+ * [1] the march variant, of the y and z marches (with the fused march, of
+ *     the z march alone).  1: unconstrained registers with the update
+ *     inputs prefetched ahead of the Riemann solve; 2: unconstrained
+ *     without prefetch; 3 / 4: at least 3 / 4 waves per SIMD without
+ *     prefetch; 5 / 6 / 7: the sliding window kept in LDS, with prefetch /
+ *     without / at least 3 waves per SIMD; 8 / 9 / 10: variants 2 / 6 / 7
+ *     whose z march keeps the swept state of its last three cells in LDS
+ *     for the RK combine instead of reading it again.
+ * [2] y march segment length (cells).
+ * [3] persistent grid (0/1).
+ * [4] z march segment length (cells).
  * The variants differ only in scheduling: FP64 results are identical.  With
  * MHD_REC_CHAR or a limiter other than minmod the sweeps run one variant
  * ([0] and [1] are then ignored). */
