@@ -314,8 +314,10 @@ class Sim:
         return {k: (ms[i], int(n[i])) for i, k in enumerate(KERNELS)}
 
     def tuning(self):
-        """Launch variant in use: (x-sweep waves/SIMD, march variant, y march
-        segment length, persistent grid, z march segment length)."""
+        """Launch variant in use: (x direction: the x sweep's minimum waves
+        per SIMD, or 0 / 2 for the fused x + y march; march variant; y march
+        segment length; persistent grid; z march segment length), as
+        mhd_tuning describes."""
         v = (C.c_int32 * 5)()
         self._check(self._lib.mhd_tuning(self._h, v))
         return tuple(int(x) for x in v)
