@@ -137,6 +137,52 @@ def test_ingest_waves_divides_each_counter_by_the_wave_cycles(tmp_path, monkeypa
     assert "cmd" in md
 
 
+def test_ingest_sq_issue_rate_and_record(tmp_path, monkeypatch):
+    """VALU issue is the mean VALU instructions per dispatch over the mean
+    traced duration times the chip's issue ceiling (1024 SIMDs at 2.4 GHz,
+    4 cycles per wave64 instruction); per-wave figures divide by the mean
+    wave count; the record is keyed by the launch the variant names."""
+    xy = "void mhd::k_sweep_march_xy<double, 0, 0, 512>(mhd::Launch)"
+    valu = 0.5 * 2e-3 * bench.VALU_ISSUE_PER_S  # half the slots over 2 ms
+    rows = []
+    for i in range(2):
+        for c, v in (("SQ_WAVES", 32768.0), ("SQ_INSTS_VALU", valu), ("SQ_INSTS_SALU", 3276.8),
+                     ("SQ_INSTS_VMEM_RD", 65536.0), ("SQ_INSTS_LDS", 1000.0),
+                     ("SQ_LDS_BANK_CONFLICT", 250.0)):
+            rows.append({"Dispatch_Id": i, "Kernel_Name": xy, "Counter_Name": c,
+                         "Counter_Value": v})
+    sq = tmp_path / "sq.csv"
+    with open(sq, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    tdir = tmp_path / "trace"
+    tdir.mkdir()
+    with open(tdir / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp",
+                                           "VGPR_Count", "SGPR_Count", "LDS_Block_Size",
+                                           "Scratch_Size"])
+        w.writeheader()
+        for start, end in ((0, 1_000_000), (5_000_000, 8_000_000)):  # 1 ms and 3 ms
+            w.writerow({"Kernel_Name": xy, "Start_Timestamp": start, "End_Timestamp": end,
+                        "VGPR_Count": 128, "SGPR_Count": 112, "LDS_Block_Size": 127488,
+                        "Scratch_Size": 16})
+    monkeypatch.setattr(bench, "profile_file",
+                        lambda kind, a, ext: str(tmp_path / f"{kind}.{ext}"))
+    args = bench.argparse.Namespace(ingest_sq=(str(sq), str(tdir)), n=512, workload="turbulence",
+                                    sq_command="sq", trace_command="kt",
+                                    variant64="0,1,64,0,64", variant_mixed="0,9,128,0,128")
+    bench.ingest_sq(args)
+    rec = json.loads((tmp_path / "sq_counters.json").read_text())
+    k = rec["fp64"]["kernels"]["sweep_y"]
+    assert k["launch"] == bench.launch_key("sweep_y", "double", [0, 1, 64, 0, 64])
+    assert k["valu_issue"] == 0.5 and k["avg_us_unfused"] == 2000.0
+    assert k["valu_per_wave"] == round(valu / 32768, 1)
+    assert k["lds_conflict_per_instr"] == 0.25 and k["scratch_bytes"] == "16"
+    md = (tmp_path / "sq_counters.md").read_text()
+    assert "| fp64 | `mhd::k_sweep_march_xy<double, 0, 0, 512>` | 32768 |" in md
+
+
 def test_counter_records_take_the_variants_of_their_commands(monkeypatch):
     """Ingestion keys a counter record by the launch variants the recorded
     counter runs used, unless they are given explicitly."""
