@@ -183,6 +183,48 @@ def test_ingest_sq_issue_rate_and_record(tmp_path, monkeypatch):
     assert "| fp64 | `mhd::k_sweep_march_xy<double, 0, 0, 512>` | 32768 |" in md
 
 
+def test_summarize_trace_matches_the_bench_launch_shape(tmp_path, monkeypatch):
+    """The agreement row of each precision averages the dominant kernel's
+    dispatches of the launch shape with the most dispatches (the timed run,
+    not the autotuner's trial shapes) and divides by the bench's HIP-event
+    average."""
+    xy64 = "void mhd::k_sweep_march_xy<double, 0, 0, 512>(mhd::Launch)"
+    xy32 = "void mhd::k_sweep_march_xy<float, 0, 0, 512>(mhd::Launch)"
+    tdir = tmp_path / "kt"
+    tdir.mkdir()
+    with open(tdir / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": xy64, "Calls": 8, "AverageNs": 8.0e6, "Percentage": 60.0})
+        w.writerow({"Name": xy32, "Calls": 4, "AverageNs": 6.0e6, "Percentage": 40.0})
+    with open(tdir / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size_X", "Start_Timestamp",
+                                           "End_Timestamp"])
+        w.writeheader()
+        t = 0
+        for name, grid, us in ([(xy64, 2097152, 8600)] * 6 + [(xy64, 1048576, 3000)] * 2
+                               + [(xy32, 1048576, 6000)] * 4):
+            w.writerow({"Kernel_Name": name, "Grid_Size_X": grid, "Start_Timestamp": t,
+                        "End_Timestamp": t + us * 1000})
+            t += us * 1000 + 10
+    line = {"metric": "m", "value": 3400.0, "source_sha": "abc",
+            "config": {"variant": [0, 1, 64, 0, 64]},
+            "roofline": {"kernel": "sweep_y", "avg_launch_ms": 8.6},
+            "mixed": {"value": 4900.0, "variant": [0, 9, 128, 0, 128],
+                      "roofline": {"kernel": "sweep_y", "avg_launch_ms": 5.0}}}
+    log = tmp_path / "bench.log"
+    log.write_text("noise\n" + json.dumps(line) + "\n")
+    monkeypatch.setattr(bench, "profile_file",
+                        lambda kind, a, ext: str(tmp_path / f"{kind}.{ext}"))
+    args = bench.argparse.Namespace(summarize_trace=(str(tdir), str(log)), n=512,
+                                    workload="turbulence", trace_command="kt")
+    bench.summarize_trace(args)
+    md = (tmp_path / "kernel_trace.md").read_text()
+    assert "| fp64 | `mhd::k_sweep_march_xy<double, 0, 0, 512>` | 2097152 | 6 | 8600.0 | 8600.0 | 1.000 |" in md
+    assert "| mixed | `mhd::k_sweep_march_xy<float, 0, 0, 512>` | 1048576 | 4 | 6000.0 | 5000.0 | 1.200 |" in md
+    assert "Kernel source hash abc" in md
+
+
 def test_counter_records_take_the_variants_of_their_commands(monkeypatch):
     """Ingestion keys a counter record by the launch variants the recorded
     counter runs used, unless they are given explicitly."""
