@@ -77,6 +77,32 @@ def _counter_csv(path, counter, rows):
                         "Counter_Value": v})
 
 
+def test_roofline_of_the_dominant_kernel(monkeypatch):
+    """The dominant kernel is the one with the largest time per step
+    (average launch time x launches); its bytes per launch are the mean of
+    the stages' algorithmic bytes (first stage once, later stages rk - 1
+    times); achieved = bytes / average launch time; traffic and VALU issue
+    come from the committed records when they match, else null."""
+    cells = 1_000_000
+    table = {"sweep_y": (176, 176), "sweep_z": (168, 208), "ct_edge": (120, 120)}
+    kt = {"sweep_y": (8.0, 20), "sweep_z": (5.0, 20), "ct_edge": (9.0, 10)}
+    monkeypatch.setattr(bench, "recorded_kernel", lambda path, p, dom, v: None)
+    a = bench.argparse.Namespace(workload="turbulence", n=100)
+    r = bench.roofline(kt, cells, table, [0, 1, 64, 0, 64], 0, a)
+    assert r["kernel"] == "sweep_y" and r["bytes_per_launch"] == 176 * cells
+    assert r["achieved"] == round(176 * cells / 8e-3 / 1e9, 1)
+    assert r["frac"] == round(r["achieved"] / 8000.0, 4) and r["traffic"] is None
+    kt = {"sweep_y": (4.0, 20), "sweep_z": (5.0, 20), "ct_edge": (1.0, 20)}
+    r = bench.roofline(kt, cells, table, [0, 1, 64, 0, 64], 0, a, rk=3)
+    assert r["kernel"] == "sweep_z"
+    assert r["bytes_per_launch"] == int((168 + 2 * 208) / 3 * cells)
+    rec = {"bytes": 9_000_000_000, "valu_issue": 0.5, "valu_per_wave": 100.0}
+    monkeypatch.setattr(bench, "recorded_kernel", lambda path, p, dom, v: rec)
+    r = bench.roofline(kt, cells, table, [0, 1, 64, 0, 64], 0, a, rk=3)
+    assert r["traffic"] == 9_000_000_000 and r["valu_issue"] == 0.5
+    assert r["traffic_over_algorithmic"] == round(9e9 / ((168 + 2 * 208) / 3 * cells), 3)
+
+
 def test_ingest_counters_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     """FETCH_SIZE reads half the copy's bytes and WRITE_SIZE all of them in
     this synthetic record: the scales are 2 and 1, and each kernel's traffic
