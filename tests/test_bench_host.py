@@ -77,6 +77,21 @@ def _counter_csv(path, counter, rows):
                         "Counter_Value": v})
 
 
+def test_byte_tables_sum_to_the_step_totals():
+    """Per cell-update (one SSP-RK2 step, both stages) the algorithmic bytes
+    of the kernels add up to the design's totals: 1424 B FP64 and 1024 B
+    mixed with the x sweep, 1136 B and 816 B with the fused march (which
+    replaces the x sweep and the y march)."""
+    def total(t):
+        return sum(a + b for a, b in t.values())
+    assert total(bench.bytes_table(0, [1, 1, 64, 0, 64])) == 1424
+    assert total(bench.bytes_table(1, [1, 1, 64, 0, 128])) == 1024
+    assert total(bench.bytes_table(0, [0, 1, 64, 0, 64])) == 1136
+    assert total(bench.bytes_table(1, [2, 9, 64, 0, 128])) == 816
+    for p in (0, 1):
+        assert "sweep_x" not in bench.bytes_table(p, [0, 1, 64, 0, 64])
+
+
 def test_roofline_of_the_dominant_kernel(monkeypatch):
     """The dominant kernel is the one with the largest time per step
     (average launch time x launches); its bytes per launch are the mean of
