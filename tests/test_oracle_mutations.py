@@ -36,6 +36,9 @@ MUTATIONS = [
      "!(star_pressure(&str, sm, bn, gamma) > 0.0))\n      ok = 0;",
      "!(star_pressure(&str, sm, bn, gamma) > 0.0))\n      ok = ok;",
      "test_oracle_point.py::test_hll_fallback_on_negative_star_thermal_pressure"),
+    ("hlld_star_velocity_sign", "vt1s = w[2] - bn * w[5] * (sm - w[1]) / dd;",
+     "vt1s = w[2] + bn * w[5] * (sm - w[1]) / dd;",
+     "test_oracle_scheme.py::test_linear_magnetosonic_waves_second_order"),
     ("hlld_double_star_sign", "(str.bt1 - stl.bt1) * sgn) / (sql + sqr);",
      "(stl.bt1 - str.bt1) * sgn) / (sql + sqr);",
      "test_oracle_point.py::test_hlld_isolated_rotational_discontinuity"),
