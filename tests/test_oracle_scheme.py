@@ -357,6 +357,67 @@ def test_linear_magnetosonic_waves_second_order(family, axis):
     assert orders[1] > 1.7, orders
 
 
+def _entropy_wave(n, axis=0, amp=0.2, u0=1.0):
+    """A density profile 1 + amp sin(2 pi x) carried at u0 along one axis
+    through uniform pressure 0.6 and field (1 along the axis, 1.5 along the
+    next): an exact nonlinear solution (a moving contact), equal to its
+    initial state after t = 1 / u0."""
+    nn = [1, 1, 1]
+    nn[axis] = n
+    spec = W.BoxSpec(tuple(nn), cfl=0.4)
+    cell = (nn[2], nn[1], nn[0])
+    view = [1, 1, 1]
+    view[2 - axis] = n
+    prof = 1.0 + amp * np.sin(2 * np.pi * W.centres(spec, axis))
+    rho = np.broadcast_to(prof.reshape(view), cell).copy()
+    vel = [np.zeros(cell) for _ in range(3)]
+    vel[axis][...] = u0
+    bface = [np.zeros(f) for f in W.face_shapes(spec)]
+    bface[axis][...] = 1.0
+    bface[(axis + 1) % 3][...] = 1.5
+    bface = W.periodic_faces(spec, bface)
+    st = W.conserved(spec, rho, vel[0], vel[1], vel[2], np.full(cell, 0.6), bface)
+    return W.Workload("entropy_wave", [spec], [st], 0, {"t_end": 1.0 / u0})
+
+
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_entropy_wave_keeps_velocity_pressure_field_uniform(solver, axis):
+    """With primitive reconstruction every face state has the same velocity,
+    pressure and field, so both solvers return the contact's upwind flux
+    and the velocity, pressure and field stay uniform to rounding while the
+    density is carried along."""
+    wl = _entropy_wave(48, axis)
+    spec = wl.boxes[0]
+    b = make(wl, solver=solver)
+    _run_to(b, wl.meta["t_end"])
+    (rho, mx, my, mz, en), bf, _ = b.get_state()
+    v = [mx / rho, my / rho, mz / rho]
+    bc = [0.5 * (bf[0][:, :, :-1] + bf[0][:, :, 1:]), 0.5 * (bf[1][:, :-1, :] + bf[1][:, 1:, :]),
+          0.5 * (bf[2][:-1] + bf[2][1:])]
+    p = (spec.gamma - 1.0) * (en - 0.5 * rho * sum(x * x for x in v) - 0.5 * sum(x * x for x in bc))
+    for d in range(3):
+        assert np.max(np.abs(v[d] - (1.0 if d == axis else 0.0))) < 1e-13
+        want = 1.0 if d == axis else (1.5 if d == (axis + 1) % 3 else 0.0)
+        assert np.max(np.abs(bf[d] - want)) < 1e-13
+    assert np.max(np.abs(p - 0.6)) < 1e-13
+
+
+def test_entropy_wave_second_order_and_hlld_sharper_than_hll():
+    """The carried density converges at second order with either solver,
+    and HLLD, which resolves a contact, leaves less error than HLL."""
+    def err(n, solver):
+        wl = _entropy_wave(n)
+        b = make(wl, solver=solver)
+        _run_to(b, wl.meta["t_end"])
+        return float(np.mean(np.abs(b.get_state()[0][0] - wl.states[0].cons[0])))
+    ns = (32, 64, 128)
+    for solver in ("hlld", "hll"):
+        e = [err(n, solver) for n in ns]
+        assert math.log2(e[1] / e[2]) > 1.7, (solver, e)
+    assert err(128, "hlld") < 0.75 * err(128, "hll")
+
+
 @pytest.mark.slow
 def test_cp_alfven_oblique():
     ns = [8, 16, 32, 64]
